@@ -1,0 +1,314 @@
+"""Seeded synthetic inputs for the forward semi-Lagrangian step.
+
+This module only *describes* problems: grids, initial fields, velocity-family
+parameters, time steps and request streams.  It holds none of the method's
+arithmetic (no trajectories, no interpolation), so both the GPU library and the
+CPU oracle can be fed from it.  Every random draw comes from
+``numpy.random.Generator(PCG64(seed))``.
+
+Shapes follow the pure-advection tests of Sec. 3.1: a cosine hill (eq. "alpha"),
+a Gaussian, and a slotted (Zalesak) disc, plus their 3-D analogues.  Arrays are
+C-ordered with x fastest; ``shape`` lists the slowest axis first.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import Sequence
+
+import numpy as np
+
+# Velocity kinds, numbered as in the C interface.
+VEL_UNIFORM, VEL_SOLID_BODY, VEL_SWIRL2D, VEL_DEFORM3D, VEL_FOURIER = range(5)
+
+
+def rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def coords(shape: Sequence[int], length: Sequence[float] | None = None):
+    """Node-centred coordinates x_i = i*h per array axis, broadcastable."""
+    d = len(shape)
+    length = list(length) if length is not None else [1.0] * d
+    out = []
+    for a, (n, L) in enumerate(zip(shape, length)):
+        x = np.arange(n, dtype=np.float64) * (L / n)
+        sh = [1] * d
+        sh[a] = n
+        out.append(x.reshape(sh))
+    return out  # array order: [z,] y, x
+
+
+def _xyz(shape, length=None):
+    """Coordinates as (x, y[, z]) in physical-axis order."""
+    c = coords(shape, length)
+    return c[::-1]
+
+
+def gaussian(shape, center, sigma, length=None):
+    X = _xyz(shape, length)
+    r2 = sum((X[a] - center[a]) ** 2 for a in range(len(shape)))
+    return np.broadcast_to(np.exp(-r2 / (2.0 * sigma * sigma)), tuple(shape)).copy()
+
+
+def cosine_bell(shape, center, radius, length=None):
+    """0.5 (1 + cos(pi r / R)) inside r <= R, zero outside (eq. "alpha" has
+    R = 0.1 and centre (0.25, 0.5))."""
+    X = _xyz(shape, length)
+    r = np.sqrt(sum((X[a] - center[a]) ** 2 for a in range(len(shape))))
+    v = np.where(r <= radius, 0.5 * (1.0 + np.cos(np.pi * r / radius)), 0.0)
+    return np.broadcast_to(v, tuple(shape)).copy()
+
+
+def slotted_disk(shape, center, radius, slot_width, slot_length, length=None):
+    """Zalesak's notched disc (or sphere in 3-D): 1 inside, 0 outside, with a
+    slot of the given width along x, cut upward (+y) from the bottom of the
+    disc to a depth of slot_length."""
+    X = _xyz(shape, length)
+    r = np.sqrt(sum((X[a] - center[a]) ** 2 for a in range(len(shape))))
+    inside = r <= radius
+    slot = (np.abs(X[0] - center[0]) <= 0.5 * slot_width) & (
+        X[1] <= center[1] - radius + slot_length)
+    v = np.where(inside & ~slot, 1.0, 0.0)
+    return np.broadcast_to(v, tuple(shape)).copy()
+
+
+def disk(shape, center, radius, length=None):
+    X = _xyz(shape, length)
+    r = np.sqrt(sum((X[a] - center[a]) ** 2 for a in range(len(shape))))
+    return np.broadcast_to(np.where(r <= radius, 1.0, 0.0), tuple(shape)).copy()
+
+
+def fourier_modes(seed: int, dim: int, nmodes: int = 16, kmax: float = 4.0,
+                  gen: np.random.Generator | None = None) -> np.ndarray:
+    """Random divergence-free flow modes: rows (k[3], a[3], phase).
+
+    k is an integer wave vector with 1 <= |k| <= kmax, a ~ N(0, I) (one
+    component in 2-D, three in 3-D) and the phase ~ U[0, 2 pi).  The velocity
+    built from them is described with the C velocity descriptor."""
+    g = gen if gen is not None else rng(seed)
+    kk = int(math.floor(kmax))
+    cand = []
+    rng_k = range(-kk, kk + 1)
+    if dim == 2:
+        for ky in rng_k:
+            for kx in rng_k:
+                n2 = kx * kx + ky * ky
+                if 1 <= n2 <= kmax * kmax:
+                    cand.append((kx, ky, 0))
+    else:
+        for kz in rng_k:
+            for ky in rng_k:
+                for kx in rng_k:
+                    n2 = kx * kx + ky * ky + kz * kz
+                    if 1 <= n2 <= kmax * kmax:
+                        cand.append((kx, ky, kz))
+    cand = np.array(cand, dtype=np.float64)
+    pick = g.integers(0, len(cand), size=nmodes)
+    modes = np.zeros((nmodes, 7))
+    modes[:, 0:3] = cand[pick]
+    if dim == 2:
+        modes[:, 3] = g.standard_normal(nmodes)
+    else:
+        modes[:, 3:6] = g.standard_normal((nmodes, 3))
+    modes[:, 6] = g.uniform(0.0, 2.0 * np.pi, nmodes)
+    return modes
+
+
+def fourier_speed_max(modes: np.ndarray, dim: int, samples: int = 64) -> float:
+    """Max-norm speed of the unscaled Fourier flow on a samples^dim lattice of
+    the unit box at t = 0.  Used only to choose dt for a target CFL number
+    (part of the workload definition, not of the method)."""
+    x = np.arange(samples) / samples
+    grids = np.meshgrid(*([x] * dim), indexing="ij")  # grids[a] is axis a (x-first)
+    u = [np.zeros_like(grids[0]) for _ in range(dim)]
+    for md in modes:
+        k = md[0:dim]
+        k2 = float(np.dot(k, k))
+        th = md[6] + 2.0 * np.pi * sum(k[a] * grids[a] for a in range(dim))
+        c = np.cos(th) * 2.0 * np.pi / k2
+        if dim == 2:
+            u[0] += md[3] * c * k[1]
+            u[1] -= md[3] * c * k[0]
+        else:
+            a = md[3:6]
+            u[0] += c * (k[1] * a[2] - k[2] * a[1])
+            u[1] += c * (k[2] * a[0] - k[0] * a[2])
+            u[2] += c * (k[0] * a[1] - k[1] * a[0])
+    return float(max(np.abs(ui).max() for ui in u))
+
+
+@dataclass
+class Velocity:
+    kind: int
+    params: list = field(default_factory=lambda: [0.0] * 8)
+    modes: np.ndarray | None = None
+
+    def padded_params(self):
+        return list(self.params) + [0.0] * (8 - len(self.params))
+
+
+@dataclass
+class Workload:
+    """One advection run: grid, initial fields, velocity, time stepping."""
+    name: str
+    shape: tuple
+    length: tuple
+    fields: list          # FP64 numpy arrays, each of `shape`
+    velocity: Velocity
+    dt: float
+    nsteps: int
+    t0: float = 0.0
+    order_max: int = 2
+    limiter: bool = False
+    theta: float = 0.25
+    value_prec: str = "f64"  # "f64" or "f32" (FP32 values, FP64 positions)
+    integrator: int = 0      # 0 RK4, 1 Williamson low-storage RK3
+    reconstruct_every: int = 1
+
+    @property
+    def dim(self):
+        return len(self.shape)
+
+    @property
+    def nfields(self):
+        return len(self.fields)
+
+    @property
+    def nodes(self):
+        return int(np.prod(self.shape))
+
+
+def solid_body_gaussian(n: int = 64, steps: int = 100, order_max: int = 2) -> Workload:
+    """2-D solid-body rotation of a Gaussian hump (centre (0.5, 0.75), sigma
+    0.05) about (0.5, 0.5) at angular speed 2 pi: `steps` steps make one turn.
+    RK4 trajectories, FP64, limiter off."""
+    shape = (n, n)
+    f = gaussian(shape, (0.5, 0.75), 0.05)
+    vel = Velocity(VEL_SOLID_BODY, [2.0 * np.pi, 0.5, 0.5])
+    return Workload("sbr_gaussian_%d" % n, shape, (1.0, 1.0), [f], vel,
+                    dt=1.0 / steps, nsteps=steps, order_max=order_max,
+                    limiter=False, value_prec="f64")
+
+
+def solid_body_cosine_hill(n: int = 50, steps: int = 200, order_max: int = 2,
+                           limiter: bool = False) -> Workload:
+    """The cosine hill of eq. "alpha" (radius 0.1 at (0.25, 0.5)) under
+    solid-body rotation about the domain centre, one turn in `steps` steps."""
+    shape = (n, n)
+    f = cosine_bell(shape, (0.25, 0.5), 0.1)
+    vel = Velocity(VEL_SOLID_BODY, [2.0 * np.pi, 0.5, 0.5])
+    return Workload("sbr_cosine_hill_%d" % n, shape, (1.0, 1.0), [f], vel,
+                    dt=1.0 / steps, nsteps=steps, order_max=order_max,
+                    limiter=limiter, value_prec="f64")
+
+
+def swirl_three_fields(n: int = 1024, cfl: float = 4.0, period: float = 5.0,
+                       value_prec: str = "f32", nsteps: int | None = None) -> Workload:
+    """2-D reversing swirl (period T = 5, max speed 1) carrying a slotted disc
+    (R 0.15 at (0.5, 0.75), slot 0.05 x 0.25), a cosine bell (R 0.15 at
+    (0.25, 0.5)) and a Gaussian (sigma 0.05 at (0.5, 0.25)).  dt = cfl * h;
+    a full period is T / dt steps.  Limiter on."""
+    shape = (n, n)
+    fs = [slotted_disk(shape, (0.5, 0.75), 0.15, 0.05, 0.25),
+          cosine_bell(shape, (0.25, 0.5), 0.15),
+          gaussian(shape, (0.5, 0.25), 0.05)]
+    vel = Velocity(VEL_SWIRL2D, [period, 1.0])
+    dt = cfl / n
+    full = int(round(period / dt))
+    return Workload("swirl2d_%d_%s" % (n, value_prec), shape, (1.0, 1.0), fs, vel,
+                    dt=dt, nsteps=full if nsteps is None else nsteps,
+                    order_max=2, limiter=True, value_prec=value_prec)
+
+
+def fourier3d_three_fields(n: int = 256, seed: int = 0, cfl: float = 2.0,
+                           nsteps: int = 50, value_prec: str = "f32") -> Workload:
+    """3-D periodic box, divergence-free flow from 16 random Fourier modes
+    (|k| <= 4, amplitudes N(0,1)/|k|^2), carrying a slotted sphere, a cosine
+    bell and a Gaussian.  dt gives max-speed CFL = cfl at t = 0."""
+    shape = (n, n, n)
+    fs = [slotted_disk(shape, (0.5, 0.75, 0.5), 0.15, 0.05, 0.25),
+          cosine_bell(shape, (0.25, 0.5, 0.5), 0.15),
+          gaussian(shape, (0.5, 0.25, 0.5), 0.05)]
+    modes = fourier_modes(seed, 3)
+    umax = fourier_speed_max(modes, 3)
+    vel = Velocity(VEL_FOURIER, [1.0], modes)
+    return Workload("fourier3d_%d_%s" % (n, value_prec), shape, (1.0, 1.0, 1.0), fs,
+                    vel, dt=cfl / (n * umax), nsteps=nsteps, order_max=2,
+                    limiter=True, value_prec=value_prec)
+
+
+def deform3d_slotted_sphere(n: int = 512, period: float = 3.0, nsteps: int = 60,
+                            value_prec: str = "f64") -> Workload:
+    """3-D deformational flow (period T = 3, max speed 2) carrying one slotted
+    sphere (R 0.15 at (0.35, 0.35, 0.35)); dt = 3h/2 (CFL 3)."""
+    shape = (n, n, n)
+    fs = [slotted_disk(shape, (0.35, 0.35, 0.35), 0.15, 0.05, 0.25)]
+    vel = Velocity(VEL_DEFORM3D, [period, 1.0])
+    return Workload("deform3d_%d_%s" % (n, value_prec), shape, (1.0, 1.0, 1.0), fs,
+                    vel, dt=1.5 / n, nsteps=nsteps, order_max=2, limiter=True,
+                    value_prec=value_prec)
+
+
+def uniform_translation(shape, velocity, dt, fields, nsteps=1, order_max=2,
+                        limiter=False, value_prec="f64", length=None) -> Workload:
+    """Uniform flow: the building block of the identity, shift and
+    polynomial-reproduction checks."""
+    length = tuple(length) if length is not None else (1.0,) * len(shape)
+    vel = Velocity(VEL_UNIFORM, list(velocity))
+    return Workload("uniform", tuple(shape), length, list(fields), vel, dt=dt,
+                    nsteps=nsteps, order_max=order_max, limiter=limiter,
+                    value_prec=value_prec)
+
+
+# ---------------------------------------------------------------------------
+# Serving stream: many independent 2-D problems arriving over time.
+
+SERVING_SIDES = (128, 256, 512, 1024, 2048)
+
+
+@dataclass
+class Request:
+    rid: int
+    arrival: float        # seconds after the stream starts
+    workload: Workload
+
+
+def _mixture_field(g: np.random.Generator, shape) -> np.ndarray:
+    """Sum of 1-3 components, each a Gaussian (sigma ~ U[0.02, 0.1]) or a
+    step disc (R ~ U[0.05, 0.2]) at a uniform random centre."""
+    f = np.zeros(shape)
+    for _ in range(int(g.integers(1, 4))):
+        c = tuple(g.uniform(0.2, 0.8, 2))
+        if g.uniform() < 0.5:
+            f += gaussian(shape, c, g.uniform(0.02, 0.1))
+        else:
+            f += disk(shape, c, g.uniform(0.05, 0.2))
+    return f
+
+
+def serving_request(g: np.random.Generator, rid: int, arrival: float,
+                    sides=SERVING_SIDES, cfl: float = 2.0,
+                    steps_range=(10, 50)) -> Request:
+    n = int(g.choice(np.asarray(sides)))
+    nf = int(g.integers(1, 5))
+    nsteps = int(g.integers(steps_range[0], steps_range[1] + 1))
+    shape = (n, n)
+    fields = [_mixture_field(g, shape) for _ in range(nf)]
+    modes = fourier_modes(0, 2, gen=g)
+    umax = fourier_speed_max(modes, 2)
+    vel = Velocity(VEL_FOURIER, [1.0], modes)
+    wl = Workload("req%d_%d" % (rid, n), shape, (1.0, 1.0), fields, vel,
+                  dt=cfl / (n * umax), nsteps=nsteps, order_max=2, limiter=True,
+                  value_prec="f32")
+    return Request(rid, arrival, wl)
+
+
+def serving_stream(seed: int = 0, count: int = 512, rate: float = 100.0,
+                   sides=SERVING_SIDES, steps_range=(10, 50)) -> list:
+    """`count` requests with Poisson arrivals at `rate` per second."""
+    g = rng(seed)
+    gaps = g.exponential(1.0 / rate, count)
+    t = np.cumsum(gaps) - gaps[0]
+    return [serving_request(g, i, float(t[i]), sides=sides, steps_range=steps_range)
+            for i in range(count)]
