@@ -1,0 +1,202 @@
+"""Benchmark of the forward semi-Lagrangian step on one MI355X.
+
+Workload: the 2-D reversing swirl (period T = 5, max speed 1) on a 1024 x 1024
+periodic grid carrying three fields (slotted disc, cosine bell, Gaussian), FP32
+values with FP64 positions, Z2 with the jump limiter on, dt = 4h (CFL 4), so a
+full period is 1280 steps.  A step is one pass of the whole hot path: the
+lattice trajectories (sl_step) and the reconstruction of all three fields
+(sl_reconstruct).  Inputs are resident in HBM before timing starts.
+
+Prints one JSON line (metric, value, ms_per_step, roofline, cpu_baseline, ...).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "node-updates/s at fixed L1 error vs FP64 oracle; serving p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def recon_bytes_per_node(dim: int, nfields: int, value_bytes: int) -> int:
+    """Algorithmic HBM bytes of one mesh-node reconstruction: the lattice
+    displacement (FP64 per axis) plus every field value read once and written
+    once."""
+    return 8 * dim + 2 * value_bytes * nfields
+
+
+def traj_bytes_per_node(dim: int) -> int:
+    """Algorithmic bytes of one lattice-node trajectory: the FP64 displacement
+    written once (a fresh lattice reads nothing)."""
+    return 8 * dim
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1280)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n", type=int, default=1024, help="grid side")
+    ap.add_argument("--prec", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="wall-clock budget of the oracle sample")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain device copy of known size (for PMC scaling)")
+    return ap.parse_args()
+
+
+def calibrate_copy():
+    import torch
+    n = 64 * 1024 * 1024  # 256 MiB of FP32
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n,
+                      "dispatches": 5}), flush=True)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only; multi-GPU runs are not "
+              "supported (use --gpus 1)", file=sys.stderr, flush=True)
+        sys.exit(2)
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
+    import torch
+
+    from paper_1410_2817_amd import binding as B
+    from paper_1410_2817_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    wl = W.swirl_three_fields(args.n, value_prec=args.prec)
+    grid = B.Grid.from_workload(wl, device=dev)
+    stored = [np.asarray(f, np.float32 if args.prec == "f32" else np.float64) for f in wl.fields]
+    f0 = grid.new_fields(stored)
+    bufs = [grid.new_fields(stored), grid.new_fields()]
+    stream = torch.cuda.current_stream()
+    nodes = grid.nodes
+
+    def run(nsteps, t0, timed_events=None):
+        a, b = bufs
+        for s in range(nsteps):
+            t = t0 + s * wl.dt
+            grid.step(t, wl.dt, stream)
+            if timed_events is not None:
+                timed_events[s][0].record(stream)
+            grid.reconstruct(a, b, stream)
+            if timed_events is not None:
+                timed_events[s][1].record(stream)
+            a, b = b, a
+        return a, b
+
+    # Warm-up from the initial state (not timed).
+    for a_, b_ in zip(bufs[0], f0):
+        a_.copy_(b_)
+    bufs[:] = list(run(args.warmup, 0.0))
+    torch.cuda.synchronize()
+    rc, _ = grid.sync(stream)
+    if rc != 0:
+        raise B.SlError(rc, "warm-up")
+
+    # Timed region: K full steps from t = 0.
+    for a_, b_ in zip(bufs[0], f0):
+        a_.copy_(b_)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    final, _ = run(args.steps, 0.0, ev)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    rc, stats = grid.sync(stream)
+    if rc != 0:
+        raise B.SlError(rc, "timed run")
+    recon_ms = float(np.mean([e0.elapsed_time(e1) for e0, e1 in ev]))
+
+    value = nodes * args.steps / elapsed
+    vb = 4 if args.prec == "f32" else 8
+    per_node = recon_bytes_per_node(2, wl.nfields, vb)
+    achieved = per_node * nodes / (recon_ms * 1e-3) / 1e9
+
+    # Accuracy: after a whole period the exact solution is the initial state.
+    acc = {}
+    if args.steps * wl.dt >= wl.velocity.params[0] - 1e-9 and \
+            abs(args.steps * wl.dt - round(args.steps * wl.dt / wl.velocity.params[0]) * wl.velocity.params[0]) < 1e-9:
+        got = [f.double().cpu().numpy() for f in final]
+        acc["l1_rel_vs_exact_after_period"] = [
+            float(np.abs(g - np.asarray(s, np.float64)).sum() / np.abs(np.asarray(s, np.float64)).sum())
+            for g, s in zip(got, stored)]
+    acc["order_hist"] = stats["order_hist"]
+    acc["search_fail"] = stats["search_fail"]
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "node-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if args.prec == "f32" else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "swirl2d_%dx%d_3fields_%s_cfl4_limiter_z2" % (args.n, args.n, args.prec),
+            "nodes": nodes, "nfields": wl.nfields, "values": args.prec, "positions": "f64",
+            "dt": wl.dt, "t_end": args.steps * wl.dt,
+        },
+        "roofline": {
+            "kernel": "reconstruction (sl_reconstruct)",
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "bytes_per_node": per_node, "avg_ms": recon_ms,
+        },
+        "accuracy": acc,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = run_cpu_baseline(wl, stored, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+def run_cpu_baseline(wl, stored, seconds):
+    """Time the FP64 oracle (unchanged) on the host over the first steps of the
+    same workload; stop once `seconds` of wall time are spent."""
+    import oracle
+    prob = oracle.Problem(wl.shape, wl.nfields, wl.length, order_max=wl.order_max,
+                          limiter=wl.limiter, theta=wl.theta, integrator=wl.integrator,
+                          vel_kind=wl.velocity.kind, vp=wl.velocity.padded_params(),
+                          modes=wl.velocity.modes)
+    fields = [np.asarray(s, np.float64) for s in stored]
+    steps, spent = 0, 0.0
+    while spent < seconds:
+        t0 = time.perf_counter()
+        rc, fields, _ = oracle.run(prob, steps * wl.dt, wl.dt, 1, fields)
+        spent += time.perf_counter() - t0
+        steps += 1
+        if rc != 0:
+            break
+    return {"value": wl.nodes * steps / spent, "unit": "node-updates/s",
+            "cores": oracle.threads(), "kind": "oracle",
+            "sample": "first %d step(s) of the same %dx%d workload, %.1f s wall" % (
+                steps, wl.shape[1], wl.shape[0], spent)}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,199 @@
+/*
+ * sl.h - C ABI of the MI355X (gfx950) forward semi-Lagrangian advection library.
+ *
+ * The library advects N scalar fields by a prescribed velocity on a regular,
+ * periodic, node-centred reference grid in 2-D or 3-D, following the scheme of
+ * Becerra-Sagredo, Malaga & Mandujano ("Moments Preserving and high-resolution
+ * Semi-Lagrangian Advection Scheme"):
+ *
+ *   sl_step        integrates the trajectories of the material-lattice nodes
+ *                  over one time step (Sec. 2, eqs. "momento" and "vel": the
+ *                  lattice starts on the reference grid and moves with the
+ *                  flow; fourth-order Runge-Kutta or the low-storage
+ *                  third-order scheme of Williamson the paper cites);
+ *   sl_reconstruct reconstructs every field on the reference grid from the
+ *                  moved lattice (Sec. 2.1-2.3): per mesh node it finds the
+ *                  deformed host element, inverts the multilinear (Z0) element
+ *                  map with Newton's method (eq. "mapping1"), lowers the
+ *                  Z-spline order while a point flagged by the jump criterion
+ *                  lies in the stencil, and evaluates the tensor-product
+ *                  cardinal Z-spline sum (eq. "multiZ", Appendix).  The
+ *                  lattice is then reset onto the grid.
+ *
+ * Conventions
+ *   - Grid: n[a] nodes along axis a (a = 0 is x), spacing h_a = length[a]/n[a],
+ *     node positions x_i = i*h; every axis is periodic.
+ *   - Field arrays: one device array per field, n[0]*n[1](*n[2]) elements of
+ *     the value precision, x fastest (C order [z][y][x]).
+ *   - Lattice displacements: kept in the caller's workspace in FP64, in cell
+ *     units, structure-of-arrays; positions are never wrapped.
+ *   - Value precision SL_FP64: everything in FP64.  SL_FP32: field values,
+ *     Z-spline weights and sums in FP32; trajectories, the element search and
+ *     the Newton inversion in FP64; jump flags evaluated in FP64 from the
+ *     stored values.
+ *
+ * Ownership and errors
+ *   - The caller owns all device memory (fields and workspace) and streams.
+ *     The library never allocates device memory; it keeps only host-side
+ *     descriptors.  Device pointers must stay valid until the work queued on
+ *     the stream has completed (e.g. until sl_sync returns).
+ *   - Every call returns SL_OK (0) or a negative sl_status.  Launch calls are
+ *     asynchronous on the given HIP stream (NULL = the null stream); errors
+ *     found on the device (search or Newton failure, non-finite output) are
+ *     counted in the workspace and reported by sl_sync.  No call aborts or
+ *     throws across the ABI.
+ *   - A grid handle may be used from one host thread at a time.
+ */
+#ifndef SL_H
+#define SL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SL_MAX_DIM 3
+#define SL_MAX_FIELDS 8
+#define SL_MAX_MODES 32
+#define SL_VERSION 100
+
+typedef enum sl_status {
+  SL_OK = 0,
+  SL_EINVAL = -1,      /* invalid argument or descriptor */
+  SL_ENOMEM = -2,      /* host allocation failed */
+  SL_EHIP = -3,        /* a HIP runtime call failed */
+  SL_ESEARCH = -4,     /* a mesh node's host element was not found */
+  SL_ENEWTON = -5,     /* Newton did not converge in the host element */
+  SL_ENONFINITE = -6,  /* a reconstructed value is NaN or infinite */
+  SL_EBUSY = -7,       /* no room (serving: HBM budget or slots exhausted) */
+  SL_ESTATE = -8,      /* call out of order (e.g. reconstruct before step) */
+  SL_ENOTFOUND = -9    /* unknown request id */
+} sl_status;
+
+enum { SL_FP64 = 0, SL_FP32 = 1 };
+enum { SL_RK4 = 0, SL_RK3_WILLIAMSON = 1 };
+
+/* Prescribed velocity families, in physical coordinates (x, y, z):
+ *   SL_VEL_UNIFORM     u = (p0, p1, p2)
+ *   SL_VEL_SOLID_BODY  u = p0 * (-(y - p2), x - p1, 0): rotation about (p1, p2)
+ *   SL_VEL_SWIRL2D     u =  p1 sin^2(pi x) sin(2 pi y) cos(pi t / p0)
+ *                      v = -p1 sin^2(pi y) sin(2 pi x) cos(pi t / p0)
+ *   SL_VEL_DEFORM3D    u =  2 p1 sin^2(pi x) sin(2 pi y) sin(2 pi z) c
+ *                      v =   -p1 sin(2 pi x) sin^2(pi y) sin(2 pi z) c
+ *                      w =   -p1 sin(2 pi x) sin(2 pi y) sin^2(pi z) c,
+ *                      c = cos(pi t / p0)
+ *   SL_VEL_FOURIER     divergence-free sum of nmodes modes; mode q is the row
+ *                      modes[7q .. 7q+6] = (k_x, k_y, k_z, a_x, a_y, a_z, phase)
+ *                      with integer wave vector k, theta = 2 pi sum_a k_a x_a /
+ *                      length[a] + phase and |k|^2 = sum_a k_a^2:
+ *                      2-D: psi = sum a_x / |k|^2 sin(theta), u = (psi_y, -psi_x)
+ *                      3-D: A = sum a / |k|^2 sin(theta),     u = curl A
+ *                      all multiplied by p0.                                   */
+enum {
+  SL_VEL_UNIFORM = 0,
+  SL_VEL_SOLID_BODY = 1,
+  SL_VEL_SWIRL2D = 2,
+  SL_VEL_DEFORM3D = 3,
+  SL_VEL_FOURIER = 4
+};
+
+typedef struct sl_velocity {
+  int kind;
+  double p[8];
+  int nmodes;            /* SL_VEL_FOURIER: 1..SL_MAX_MODES */
+  const double *modes;   /* host memory, nmodes x 7 doubles; copied at create */
+} sl_velocity;
+
+typedef struct sl_grid_desc {
+  int dim;                /* 2 or 3 */
+  int64_t n[3];           /* nodes per axis, x first; n[a] >= 2*order_max+2 */
+  double length[3];       /* physical extent per axis, > 0 */
+  int nfields;            /* 1..SL_MAX_FIELDS */
+  int value_prec;         /* SL_FP64 or SL_FP32 */
+  int order_max;          /* highest Z-spline order m: 0 (linear), 1, 2 */
+  int limiter;            /* 1: jump criterion of Sec. 2.3 lowers the order */
+  double limiter_theta;   /* jump threshold, 0.25 in the paper */
+  int integrator;         /* SL_RK4 or SL_RK3_WILLIAMSON */
+  int reconstruct_every;  /* lattice steps between reconstructions, >= 1 */
+  sl_velocity vel;
+  int newton_max_iter;    /* Newton iterations per element, 20 */
+  double newton_tol;      /* stop when max |delta xi| <= tol (cells), 1e-14 */
+  int walk_max;           /* element-walk moves before the fallback scan, 32 */
+  int scan_radius;        /* half-width of the fallback scan box, 4 */
+  double eps_inside;      /* slack on the unit cube when accepting, 1e-12 */
+} sl_grid_desc;
+
+/* Counters accumulated on the device since the last sl_sync. */
+typedef struct sl_stats {
+  int64_t nodes;           /* mesh-node reconstructions */
+  int64_t search_fail;     /* nodes whose host element was not found */
+  int64_t newton_fail;     /* nodes whose Newton solve did not converge */
+  int64_t nonfinite;       /* field values reconstructed as NaN/Inf */
+  int64_t order_hist[3];   /* field-node reconstructions per order used */
+  int64_t walked;          /* nodes whose search left the start cell */
+  int64_t scanned;         /* nodes located by the fallback scan */
+  int64_t steps;           /* trajectory steps launched */
+  int64_t reconstructs;    /* reconstructions launched */
+} sl_stats;
+
+typedef struct sl_grid sl_grid;
+
+/* Fill a descriptor with the defaults listed above (2-D, FP64, Z2, limiter
+ * off, theta 0.25, RK4, K = 1, zero uniform velocity, unit lengths). */
+void sl_grid_desc_init(sl_grid_desc *desc);
+
+/* Validate a descriptor and create a grid handle (host only, no device work).
+ * Errors: SL_EINVAL (bad descriptor or NULL), SL_ENOMEM. */
+int sl_create_grid(const sl_grid_desc *desc, sl_grid **out);
+
+/* Destroy a handle; NULL is accepted. */
+int sl_destroy_grid(sl_grid *grid);
+
+/* Device bytes the caller must provide as `workspace` to the calls below
+ * (lattice displacements and device counters); 0 for a NULL handle. The
+ * workspace must be 256-byte aligned and zero-filled before its first use. */
+size_t sl_workspace_bytes(const sl_grid *grid);
+
+/* Integrate the lattice trajectories over [t, t+dt] (Sec. 2).  The first step
+ * after a reset starts every lattice node on its mesh node; later steps
+ * continue from the stored displacement.  Asynchronous on `stream`.
+ * Errors: SL_EINVAL, SL_EHIP. */
+int sl_step(sl_grid *grid, void *workspace, double t, double dt, void *stream);
+
+/* Reconstruct all fields on the mesh from the moved lattice and reset the
+ * lattice (Sec. 2.1-2.3).  fields_in / fields_out are host arrays of nfields
+ * device pointers to caller-owned arrays in the grid's value precision; an
+ * output array must not alias any input array.  Asynchronous on `stream`.
+ * Errors: SL_EINVAL, SL_ESTATE (no sl_step since the last reset), SL_EHIP. */
+int sl_reconstruct(sl_grid *grid, void *workspace, const void *const *fields_in,
+                   void *const *fields_out, void *stream);
+
+/* Wait for `stream`, copy the device counters into *stats (may be NULL) and
+ * clear them.  Returns the first device-side error class seen since the last
+ * sync (SL_ESEARCH, SL_ENEWTON, SL_ENONFINITE, in that priority), else SL_OK,
+ * or SL_EHIP / SL_EINVAL. */
+int sl_sync(sl_grid *grid, void *workspace, void *stream, sl_stats *stats);
+
+/* Device pointer to the lattice displacement along `axis` (0 = x) inside
+ * `workspace`: n[0]*n[1](*n[2]) doubles in cell units, x fastest, valid after
+ * sl_step and until the next sl_step after a reconstruction.  NULL on a bad
+ * argument. */
+const double *sl_displacement(const sl_grid *grid, const void *workspace, int axis);
+
+/* Static text for a status code. */
+const char *sl_strerror(int code);
+
+/* Text of the last HIP runtime error this thread saw inside the library
+ * (empty if none); the pointer stays valid for the thread's lifetime. */
+const char *sl_error_detail(void);
+
+/* SL_VERSION of the built library. */
+int sl_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SL_H */

@@ -102,6 +102,8 @@ def _load():
         lib.orc_run.argtypes = [P, C.c_double, C.c_double, C.c_int, C.c_int,
                                 C.POINTER(dp), C.POINTER(_Stats)]
         lib.orc_run.restype = C.c_int
+        lib.orc_threads.argtypes = []
+        lib.orc_threads.restype = C.c_int
         _lib = lib
     return _lib
 
@@ -321,3 +323,8 @@ def run(prob: Problem, t0: float, dt: float, nsteps: int, fields, kevery: int = 
     rc = _load().orc_run(C.byref(p), float(t0), float(dt), int(nsteps), int(kevery),
                          _fields_ptrs(fs), C.byref(st))
     return rc, fs, st.as_dict()
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's parallel loops use."""
+    return _load().orc_threads()

@@ -37,6 +37,7 @@
  * close to the tolerances this oracle is meant to certify.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -434,17 +435,24 @@ static int in_cube(const orc_problem *P, const double *xi) {
  *
  * Search (Sec. 2.2): start in the cell below target - d(target) and, while
  * the local coordinates fall outside the unit cube, move one cell per axis
- * toward the indicated side.  Where the lattice is so distorted that this
- * walk cycles (e.g. the corners of a periodic box swept by a non-periodic
- * solid-body rotation), the cells of the box of half-width scan_radius around
- * the start cell are tried in order, x fastest, and the first that contains
- * the point is taken.                                                       */
+ * toward the indicated side.  A cell is the host only when Newton converges
+ * to a point of its unit cube (the "bounded mapping" of the paper); where
+ * Newton does not converge, the root of the linear part of the map points the
+ * way.  Where the lattice is so distorted that this walk stalls or cycles
+ * (e.g. the corners of a periodic box swept by a non-periodic solid-body
+ * rotation, or a strongly twisted element whose linear root lies inside but
+ * whose Newton iteration wanders off), the cells of the box of half-width
+ * scan_radius around the start cell are tried in order, x fastest, and the
+ * first that holds the point is taken.  Failure is reported as ORC_ENEWTON
+ * if some visited cell had its linear root inside but no Newton solution,
+ * else as ORC_ESEARCH.                                                      */
 int orc_locate_cb(const orc_problem *P, orc_disp_fn get_disp, void *ctx,
                   const int64_t *target, int64_t *r, double *xi,
                   int *walk_steps, int *newton_iters) {
   int d = P->dim;
   double d0[3] = {0.0, 0.0, 0.0};
   int64_t start[3] = {0, 0, 0};
+  int newton_trouble = 0;
   get_disp(ctx, target, d0);
   for (int a = 0; a < d; ++a) start[a] = r[a] = (int64_t)floor((double)target[a] - d0[a]);
   *walk_steps = 0;
@@ -454,9 +462,12 @@ int orc_locate_cb(const orc_problem *P, orc_disp_fn get_disp, void *ctx,
     int rc = element_solve(P, get_disp, ctx, target, r, x, newton_iters);
     if (rc < 0) break;
     if (in_cube(P, x)) {
-      if (rc == 0) return ORC_ENEWTON;
-      for (int a = 0; a < d; ++a) xi[a] = x[a];
-      return ORC_OK;
+      if (rc == 1) {
+        for (int a = 0; a < d; ++a) xi[a] = x[a];
+        return ORC_OK;
+      }
+      newton_trouble = 1;
+      break;
     }
     for (int a = 0; a < d; ++a) {
       if (x[a] < -P->eps_inside) r[a] -= 1;
@@ -474,14 +485,17 @@ int orc_locate_cb(const orc_problem *P, orc_disp_fn get_disp, void *ctx,
       r[a] = start[a] - W + qq % span;
       qq /= span;
     }
-    if (element_solve(P, get_disp, ctx, target, r, x, newton_iters) == 1 &&
-        in_cube(P, x)) {
-      for (int a = 0; a < d; ++a) xi[a] = x[a];
-      ++*walk_steps;
-      return ORC_OK;
+    int rc = element_solve(P, get_disp, ctx, target, r, x, newton_iters);
+    if (in_cube(P, x)) {
+      if (rc == 1) {
+        for (int a = 0; a < d; ++a) xi[a] = x[a];
+        ++*walk_steps;
+        return ORC_OK;
+      }
+      if (rc == 0) newton_trouble = 1;
     }
   }
-  return ORC_ESEARCH;
+  return newton_trouble ? ORC_ENEWTON : ORC_ESEARCH;
 }
 
 /* Displacement providers: a stored SoA array, or on-demand trajectories. */
@@ -764,3 +778,6 @@ int orc_run(const orc_problem *P, double t0, double dt, int nsteps, int kevery,
   if (stats) *stats = tot;
   return rc;
 }
+
+/* Number of OpenMP threads the oracle's parallel loops use. */
+int orc_threads(void) { return omp_get_max_threads(); }

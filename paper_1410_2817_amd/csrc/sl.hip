@@ -1,0 +1,618 @@
+// Forward semi-Lagrangian advection on gfx950: kernels and the C ABI of sl.h.
+//
+// One step of the scheme (Sec. 2 of Becerra-Sagredo, Malaga & Mandujano):
+//   traj_kernel   one work-item per lattice node integrates its trajectory
+//                 (RK4 or Williamson's low-storage RK3) and stores the FP64
+//                 displacement in cell units, structure-of-arrays;
+//   flags_kernel  jump flags of Sec. 2.3, one bit per field per lattice node;
+//   recon_kernel  one work-item per mesh node: host-element walk + Newton on
+//                 the multilinear element map (eq. "mapping1"), order
+//                 selection from the flags, cardinal Z-spline weights
+//                 (Appendix) and the tensor-product gather-sum (eq. "multiZ").
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "sl.h"
+#include "sl_device.h"
+
+namespace sl {
+
+constexpr int kBlock = 256;
+
+template <int D>
+__device__ __forceinline__ void unflatten(const GridArgs& g, int lin, int* idx) {
+  idx[0] = lin % g.n[0];
+  if constexpr (D == 2) {
+    idx[1] = lin / g.n[0];
+  } else {
+    const int q = lin / g.n[0];
+    idx[1] = q % g.n[1];
+    idx[2] = q / g.n[1];
+  }
+}
+
+template <int D>
+__device__ __forceinline__ int flatten(const GridArgs& g, const int* w) {
+  if constexpr (D == 2)
+    return w[0] + g.n[0] * w[1];
+  else
+    return w[0] + g.n[0] * (w[1] + g.n[1] * w[2]);
+}
+
+// ---------------------------------------------------------------------------
+// Trajectories (Sec. 2, eq. "vel").
+
+template <int VK>
+__device__ __forceinline__ double time_factor(const VelArgs& v, double t) {
+  if constexpr (VK == SL_VEL_SWIRL2D || VK == SL_VEL_DEFORM3D)
+    return cospi(t / v.p[0]);
+  else
+    return 1.0;
+}
+
+template <int D, int VK>
+__global__ __launch_bounds__(kBlock) void traj_kernel(GridArgs g, VelArgs v,
+                                                      double* __restrict__ disp, double t,
+                                                      double dt, int accumulate,
+                                                      int integrator) {
+  const int lin = blockIdx.x * kBlock + threadIdx.x;
+  if (lin >= g.ntot) return;
+  int idx[D];
+  unflatten<D>(g, lin, idx);
+  double d[D], x[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    d[a] = accumulate ? disp[(size_t)a * g.ntot + lin] : 0.0;
+    x[a] = ((double)idx[a] + d[a]) * g.h[a];
+  }
+  if (integrator == SL_RK4) {
+    double k1[D], k2[D], k3[D], k4[D], y[D];
+    velocity<VK, D>(v, x, time_factor<VK>(v, t), k1);
+#pragma unroll
+    for (int a = 0; a < D; ++a) y[a] = x[a] + 0.5 * dt * k1[a];
+    const double tf_half = time_factor<VK>(v, t + 0.5 * dt);
+    velocity<VK, D>(v, y, tf_half, k2);
+#pragma unroll
+    for (int a = 0; a < D; ++a) y[a] = x[a] + 0.5 * dt * k2[a];
+    velocity<VK, D>(v, y, tf_half, k3);
+#pragma unroll
+    for (int a = 0; a < D; ++a) y[a] = x[a] + dt * k3[a];
+    velocity<VK, D>(v, y, time_factor<VK>(v, t + dt), k4);
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+      d[a] += dt * (k1[a] + 2.0 * k2[a] + 2.0 * k3[a] + k4[a]) / 6.0 / g.h[a];
+  } else {
+    // Williamson (1980) 2N-storage RK3: q = A_s q + dt u(x + dx, t + c_s dt),
+    // dx += B_s q with A = (0, -5/9, -153/128), B = (1/3, 15/16, 8/15),
+    // c = (0, 1/3, 3/4).
+    const double A[3] = {0.0, -5.0 / 9.0, -153.0 / 128.0};
+    const double B[3] = {1.0 / 3.0, 15.0 / 16.0, 8.0 / 15.0};
+    const double C[3] = {0.0, 1.0 / 3.0, 3.0 / 4.0};
+    double q[D], dx[D], y[D], u[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) q[a] = dx[a] = 0.0;
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+#pragma unroll
+      for (int a = 0; a < D; ++a) y[a] = x[a] + dx[a];
+      velocity<VK, D>(v, y, time_factor<VK>(v, t + C[s] * dt), u);
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        q[a] = A[s] * q[a] + dt * u[a];
+        dx[a] += B[s] * q[a];
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < D; ++a) d[a] += dx[a] / g.h[a];
+  }
+#pragma unroll
+  for (int a = 0; a < D; ++a) disp[(size_t)a * g.ntot + lin] = d[a];
+}
+
+// ---------------------------------------------------------------------------
+// Jump flags (Sec. 2.3): bit f of flags[node] is set when the criterion fires
+// for field f along any axis.
+
+template <int D, typename T>
+__global__ __launch_bounds__(kBlock) void flags_kernel(GridArgs g, FieldPtrs fp,
+                                                       uint8_t* __restrict__ flags) {
+  const int lin = blockIdx.x * kBlock + threadIdx.x;
+  if (lin >= g.ntot) return;
+  int idx[D];
+  unflatten<D>(g, lin, idx);
+  int nb[D][2];
+  const int stride[3] = {1, g.n[0], g.n[0] * g.n[1]};
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    const int up = idx[a] + 1 == g.n[a] ? -(g.n[a] - 1) : 1;
+    const int dn = idx[a] == 0 ? (g.n[a] - 1) : -1;
+    nb[a][0] = lin + dn * stride[a];
+    nb[a][1] = lin + up * stride[a];
+  }
+  unsigned bits = 0;
+  for (int f = 0; f < g.nfields; ++f) {
+    const T* __restrict__ h = static_cast<const T*>(fp.in[f]);
+    const double hc = (double)h[lin];
+    bool fl = false;
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+      fl = fl || jump_flag((double)h[nb[a][0]], hc, (double)h[nb[a][1]], g.theta);
+    bits |= (fl ? 1u : 0u) << f;
+  }
+  flags[lin] = (uint8_t)bits;
+}
+
+// ---------------------------------------------------------------------------
+// Reconstruction (Sec. 2.1-2.3).
+
+template <int D>
+struct GlobalDisp {
+  const double* __restrict__ disp;
+  GridArgs g;
+  __device__ __forceinline__ void operator()(const int* w, double* d) const {
+    const int lin = flatten<D>(g, w);
+#pragma unroll
+    for (int a = 0; a < D; ++a) d[a] = disp[(size_t)a * g.ntot + lin];
+  }
+};
+
+template <int D, typename T>
+__global__ __launch_bounds__(kBlock) void recon_kernel(GridArgs g, FieldPtrs fp,
+                                                       const double* __restrict__ disp,
+                                                       const uint8_t* __restrict__ flags,
+                                                       unsigned long long* __restrict__ stats) {
+  const int lin = blockIdx.x * kBlock + threadIdx.x;
+  if (lin >= g.ntot) return;
+  int tgt[D];
+  unflatten<D>(g, lin, tgt);
+  int r[D];
+  double xi[D];
+  int walked = 0;
+  const int loc = locate<D>(g, GlobalDisp<D>{disp, g}, tgt, r, xi, walked);
+  wave_count(stats + ST_SEARCH_FAIL, loc == LOC_SEARCH_FAIL);
+  wave_count(stats + ST_NEWTON_FAIL, loc == LOC_NEWTON_FAIL);
+  wave_count(stats + ST_WALKED, walked != 0);
+  wave_count(stats + ST_SCANNED, walked == 2);
+  if (loc != LOC_OK) {
+    for (int f = 0; f < g.nfields; ++f) static_cast<T*>(fp.out[f])[lin] = T(NAN);
+    return;
+  }
+  // Wrapped stencil indices, slot s <-> node r - 2 + s.
+  int ix[D][6];
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    int w = wrap_index(r[a] - 2, g.n[a]);
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+      ix[a][s] = w;
+      w = (w + 1 == g.n[a]) ? 0 : w + 1;
+    }
+  }
+  const int sy = g.n[0], sz = g.n[0] * g.n[1];
+  // Flags in the quintic (6^D) and cubic (4^D) stencils.
+  unsigned or6 = 0, or4 = 0;
+  if (g.limiter && g.order_max > 0) {
+    if constexpr (D == 2) {
+#pragma unroll
+      for (int ky = 0; ky < 6; ++ky)
+#pragma unroll
+        for (int kx = 0; kx < 6; ++kx) {
+          const unsigned fb = flags[ix[0][kx] + sy * ix[1][ky]];
+          or6 |= fb;
+          if (kx >= 1 && kx <= 4 && ky >= 1 && ky <= 4) or4 |= fb;
+        }
+    } else {
+      for (int kz = 0; kz < 6; ++kz)
+#pragma unroll
+        for (int ky = 0; ky < 6; ++ky)
+#pragma unroll
+          for (int kx = 0; kx < 6; ++kx) {
+            const unsigned fb = flags[ix[0][kx] + sy * ix[1][ky] + sz * ix[2][kz]];
+            or6 |= fb;
+            if (kx >= 1 && kx <= 4 && ky >= 1 && ky <= 4 && kz >= 1 && kz <= 4) or4 |= fb;
+          }
+    }
+  }
+  T t[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) t[a] = (T)xi[a];
+  T w[D][6];
+  int wm = -1;
+  int cnt0 = 0, cnt1 = 0, bad = 0;
+  for (int f = 0; f < g.nfields; ++f) {
+    int m = g.order_max;
+    if (m == 2 && ((or6 >> f) & 1u)) m = 1;
+    if (m == 1 && ((or4 >> f) & 1u)) m = 0;
+    cnt0 += m == 0;
+    cnt1 += m == 1;
+    if (m != wm) {
+#pragma unroll
+      for (int a = 0; a < D; ++a) zspline_weights<T>(m, t[a], w[a]);
+      wm = m;
+    }
+    const T* __restrict__ h = static_cast<const T*>(fp.in[f]);
+    T acc = T(0);
+    if constexpr (D == 2) {
+#pragma unroll
+      for (int ky = 0; ky < 6; ++ky) {
+        const T* row = h + (size_t)sy * ix[1][ky];
+        T s = T(0);
+#pragma unroll
+        for (int kx = 0; kx < 6; ++kx) s = fma(row[ix[0][kx]], w[0][kx], s);
+        acc = fma(s, w[1][ky], acc);
+      }
+    } else {
+      for (int kz = 0; kz < 6; ++kz) {
+        T pl = T(0);
+#pragma unroll
+        for (int ky = 0; ky < 6; ++ky) {
+          const T* row = h + (size_t)sz * ix[2][kz] + (size_t)sy * ix[1][ky];
+          T s = T(0);
+#pragma unroll
+          for (int kx = 0; kx < 6; ++kx) s = fma(row[ix[0][kx]], w[0][kx], s);
+          pl = fma(s, w[1][ky], pl);
+        }
+        acc = fma(pl, w[2][kz], acc);
+      }
+    }
+    bad += !isfinite(acc);
+    static_cast<T*>(fp.out[f])[lin] = acc;
+  }
+  // Per-field order counts: lanes contribute their counts one field at a time.
+  for (int f = 0; f < g.nfields; ++f) {
+    wave_count(stats + ST_ORDER0, f < cnt0);
+    wave_count(stats + ST_ORDER1, f < cnt1);
+    wave_count(stats + ST_NONFINITE, f < bad);
+  }
+}
+
+__global__ void zero_kernel(unsigned long long* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0ull;
+}
+
+}  // namespace sl
+
+// ===========================================================================
+// Host side: descriptors, validation, launches.
+
+struct sl_grid {
+  sl_grid_desc desc;
+  std::vector<double> modes;
+  sl::GridArgs g;
+  sl::VelArgs v;
+  int64_t ntot;
+  size_t off_stats, off_disp, off_flags, ws_bytes;
+  int steps_since_reset;
+  int64_t steps_launched, reconstructs_launched;
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr size_t kStatsBytes = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+int check_desc(const sl_grid_desc* d) {
+  if (!d) return SL_EINVAL;
+  if (d->dim != 2 && d->dim != 3) return SL_EINVAL;
+  if (d->nfields < 1 || d->nfields > SL_MAX_FIELDS) return SL_EINVAL;
+  if (d->value_prec != SL_FP64 && d->value_prec != SL_FP32) return SL_EINVAL;
+  if (d->order_max < 0 || d->order_max > 2) return SL_EINVAL;
+  if (d->integrator != SL_RK4 && d->integrator != SL_RK3_WILLIAMSON) return SL_EINVAL;
+  if (d->reconstruct_every < 1) return SL_EINVAL;
+  if (d->newton_max_iter < 1 || d->newton_max_iter > 1000) return SL_EINVAL;
+  if (!(d->newton_tol > 0.0) || !(d->eps_inside >= 0.0)) return SL_EINVAL;
+  if (d->walk_max < 0 || d->walk_max > 4096) return SL_EINVAL;
+  if (d->scan_radius < 0 || d->scan_radius > 16) return SL_EINVAL;
+  if (d->limiter != 0 && d->limiter != 1) return SL_EINVAL;
+  if (d->limiter && !(d->limiter_theta >= 0.0)) return SL_EINVAL;
+  int64_t tot = 1;
+  for (int a = 0; a < d->dim; ++a) {
+    // The quintic stencil must fit in the periodic grid once.
+    if (d->n[a] < 6 || d->n[a] > (1 << 24)) return SL_EINVAL;
+    if (!(d->length[a] > 0.0) || !isfinite(d->length[a])) return SL_EINVAL;
+    tot *= d->n[a];
+    if (tot > (int64_t)INT32_MAX / 2) return SL_EINVAL;
+  }
+  const sl_velocity& v = d->vel;
+  if (v.kind < SL_VEL_UNIFORM || v.kind > SL_VEL_FOURIER) return SL_EINVAL;
+  if (v.kind == SL_VEL_SWIRL2D && (d->dim != 2 || !(v.p[0] != 0.0))) return SL_EINVAL;
+  if (v.kind == SL_VEL_DEFORM3D && (d->dim != 3 || !(v.p[0] != 0.0))) return SL_EINVAL;
+  if (v.kind == SL_VEL_FOURIER) {
+    if (v.nmodes < 1 || v.nmodes > SL_MAX_MODES || !v.modes) return SL_EINVAL;
+    for (int q = 0; q < v.nmodes; ++q) {
+      double k2 = 0.0;
+      for (int a = 0; a < d->dim; ++a) k2 += v.modes[7 * q + a] * v.modes[7 * q + a];
+      if (!(k2 > 0.0)) return SL_EINVAL;
+      for (int c = 0; c < 7; ++c)
+        if (!isfinite(v.modes[7 * q + c])) return SL_EINVAL;
+    }
+  }
+  for (int c = 0; c < 8; ++c)
+    if (!isfinite(v.p[c])) return SL_EINVAL;
+  return SL_OK;
+}
+
+thread_local char g_detail[256] = "";
+
+int hip_status(hipError_t e) {
+  if (e == hipSuccess) return SL_OK;
+  snprintf(g_detail, sizeof(g_detail), "%s: %s", hipGetErrorName(e), hipGetErrorString(e));
+  return SL_EHIP;
+}
+
+// Launch errors are read back with hipGetLastError(); clear whatever another
+// library left behind first so it is not reported as ours.
+void clear_stale_error() { (void)hipGetLastError(); }
+
+template <int D>
+void launch_traj(sl_grid* gr, double* disp, double t, double dt, int accumulate,
+                 hipStream_t s) {
+  const int blocks = (int)((gr->ntot + sl::kBlock - 1) / sl::kBlock);
+  const int integ = gr->desc.integrator;
+  switch (gr->v.kind) {
+    case SL_VEL_UNIFORM:
+      sl::traj_kernel<D, SL_VEL_UNIFORM><<<blocks, sl::kBlock, 0, s>>>(gr->g, gr->v, disp, t, dt, accumulate, integ);
+      break;
+    case SL_VEL_SOLID_BODY:
+      sl::traj_kernel<D, SL_VEL_SOLID_BODY><<<blocks, sl::kBlock, 0, s>>>(gr->g, gr->v, disp, t, dt, accumulate, integ);
+      break;
+    case SL_VEL_SWIRL2D:
+      sl::traj_kernel<D, SL_VEL_SWIRL2D><<<blocks, sl::kBlock, 0, s>>>(gr->g, gr->v, disp, t, dt, accumulate, integ);
+      break;
+    case SL_VEL_DEFORM3D:
+      sl::traj_kernel<D, SL_VEL_DEFORM3D><<<blocks, sl::kBlock, 0, s>>>(gr->g, gr->v, disp, t, dt, accumulate, integ);
+      break;
+    default:
+      sl::traj_kernel<D, SL_VEL_FOURIER><<<blocks, sl::kBlock, 0, s>>>(gr->g, gr->v, disp, t, dt, accumulate, integ);
+      break;
+  }
+}
+
+template <int D, typename T>
+void launch_recon(sl_grid* gr, const sl::FieldPtrs& fp, char* ws, hipStream_t s) {
+  const int blocks = (int)((gr->ntot + sl::kBlock - 1) / sl::kBlock);
+  uint8_t* flags = reinterpret_cast<uint8_t*>(ws + gr->off_flags);
+  const double* disp = reinterpret_cast<const double*>(ws + gr->off_disp);
+  auto* stats = reinterpret_cast<unsigned long long*>(ws + gr->off_stats);
+  if (gr->g.limiter && gr->g.order_max > 0)
+    sl::flags_kernel<D, T><<<blocks, sl::kBlock, 0, s>>>(gr->g, fp, flags);
+  sl::recon_kernel<D, T><<<blocks, sl::kBlock, 0, s>>>(gr->g, fp, disp, flags, stats);
+}
+
+}  // namespace
+
+extern "C" {
+
+void sl_grid_desc_init(sl_grid_desc* d) {
+  if (!d) return;
+  memset(d, 0, sizeof(*d));
+  d->dim = 2;
+  d->n[0] = d->n[1] = d->n[2] = 64;
+  d->length[0] = d->length[1] = d->length[2] = 1.0;
+  d->nfields = 1;
+  d->value_prec = SL_FP64;
+  d->order_max = 2;
+  d->limiter = 0;
+  d->limiter_theta = 0.25;
+  d->integrator = SL_RK4;
+  d->reconstruct_every = 1;
+  d->vel.kind = SL_VEL_UNIFORM;
+  d->newton_max_iter = 20;
+  d->newton_tol = 1e-14;
+  d->walk_max = 32;
+  d->scan_radius = 4;
+  d->eps_inside = 1e-12;
+}
+
+int sl_create_grid(const sl_grid_desc* desc, sl_grid** out) {
+  if (!out) return SL_EINVAL;
+  *out = nullptr;
+  const int rc = check_desc(desc);
+  if (rc != SL_OK) return rc;
+  sl_grid* gr = new (std::nothrow) sl_grid();
+  if (!gr) return SL_ENOMEM;
+  gr->desc = *desc;
+  const int D = desc->dim;
+  if (desc->vel.kind == SL_VEL_FOURIER) {
+    gr->modes.assign(desc->vel.modes, desc->vel.modes + 7 * desc->vel.nmodes);
+    gr->desc.vel.modes = gr->modes.data();
+  } else {
+    gr->desc.vel.modes = nullptr;
+    gr->desc.vel.nmodes = 0;
+  }
+  sl::GridArgs& g = gr->g;
+  memset(&g, 0, sizeof(g));
+  gr->ntot = 1;
+  for (int a = 0; a < 3; ++a) {
+    g.n[a] = a < D ? (int)desc->n[a] : 1;
+    g.h[a] = a < D ? desc->length[a] / (double)desc->n[a] : 1.0;
+    if (a < D) gr->ntot *= desc->n[a];
+  }
+  g.ntot = (int)gr->ntot;
+  g.nfields = desc->nfields;
+  g.order_max = desc->order_max;
+  g.limiter = desc->limiter;
+  g.theta = desc->limiter_theta;
+  g.newton_max_iter = desc->newton_max_iter;
+  g.newton_tol = desc->newton_tol;
+  g.walk_max = desc->walk_max;
+  g.scan_radius = desc->scan_radius;
+  g.eps = desc->eps_inside;
+
+  sl::VelArgs& v = gr->v;
+  memset(&v, 0, sizeof(v));
+  v.kind = desc->vel.kind;
+  for (int c = 0; c < 8; ++c) v.p[c] = desc->vel.p[c];
+  if (v.kind == SL_VEL_FOURIER) {
+    v.nmodes = desc->vel.nmodes;
+    const double pi = M_PI;
+    for (int q = 0; q < v.nmodes; ++q) {
+      const double* md = gr->modes.data() + 7 * q;
+      double k2 = 0.0, kp[3] = {0.0, 0.0, 0.0};
+      for (int a = 0; a < D; ++a) {
+        k2 += md[a] * md[a];
+        kp[a] = md[a] / desc->length[a];
+        v.mode[q].c[a] = 2.0 * kp[a];
+      }
+      v.mode[q].phase_over_pi = md[6] / pi;
+      const double s = desc->vel.p[0] * 2.0 * pi / k2;
+      if (D == 2) {
+        v.mode[q].amp[0] = s * md[3] * kp[1];
+        v.mode[q].amp[1] = -s * md[3] * kp[0];
+      } else {
+        // curl(a sin(theta)) = cos(theta) grad(theta) x a
+        v.mode[q].amp[0] = s * (kp[1] * md[5] - kp[2] * md[4]);
+        v.mode[q].amp[1] = s * (kp[2] * md[3] - kp[0] * md[5]);
+        v.mode[q].amp[2] = s * (kp[0] * md[4] - kp[1] * md[3]);
+      }
+    }
+  }
+  gr->off_stats = 0;
+  gr->off_disp = align_up(kStatsBytes);
+  gr->off_flags = align_up(gr->off_disp + sizeof(double) * (size_t)D * (size_t)gr->ntot);
+  gr->ws_bytes = align_up(gr->off_flags + (size_t)gr->ntot);
+  gr->steps_since_reset = 0;
+  *out = gr;
+  return SL_OK;
+}
+
+int sl_destroy_grid(sl_grid* grid) {
+  delete grid;
+  return SL_OK;
+}
+
+size_t sl_workspace_bytes(const sl_grid* grid) { return grid ? grid->ws_bytes : 0; }
+
+int sl_step(sl_grid* gr, void* workspace, double t, double dt, void* stream) {
+  if (!gr || !workspace || !isfinite(t) || !isfinite(dt)) return SL_EINVAL;
+  if (((uintptr_t)workspace) % kAlign) return SL_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  double* disp = reinterpret_cast<double*>(static_cast<char*>(workspace) + gr->off_disp);
+  const int acc = gr->steps_since_reset > 0;
+  clear_stale_error();
+  if (gr->desc.dim == 2)
+    launch_traj<2>(gr, disp, t, dt, acc, s);
+  else
+    launch_traj<3>(gr, disp, t, dt, acc, s);
+  const int rc = hip_status(hipGetLastError());
+  if (rc == SL_OK) {
+    gr->steps_since_reset++;
+    gr->steps_launched++;
+  }
+  return rc;
+}
+
+int sl_reconstruct(sl_grid* gr, void* workspace, const void* const* fields_in,
+                   void* const* fields_out, void* stream) {
+  if (!gr || !workspace || !fields_in || !fields_out) return SL_EINVAL;
+  if (((uintptr_t)workspace) % kAlign) return SL_EINVAL;
+  if (gr->steps_since_reset < 1) return SL_ESTATE;
+  sl::FieldPtrs fp;
+  memset(&fp, 0, sizeof(fp));
+  const int nf = gr->desc.nfields;
+  for (int f = 0; f < nf; ++f) {
+    if (!fields_in[f] || !fields_out[f]) return SL_EINVAL;
+    fp.in[f] = fields_in[f];
+    fp.out[f] = fields_out[f];
+  }
+  for (int f = 0; f < nf; ++f)
+    for (int q = 0; q < nf; ++q)
+      if (fp.out[f] == fp.in[q]) return SL_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* ws = static_cast<char*>(workspace);
+  const bool f32 = gr->desc.value_prec == SL_FP32;
+  clear_stale_error();
+  if (gr->desc.dim == 2) {
+    if (f32)
+      launch_recon<2, float>(gr, fp, ws, s);
+    else
+      launch_recon<2, double>(gr, fp, ws, s);
+  } else {
+    if (f32)
+      launch_recon<3, float>(gr, fp, ws, s);
+    else
+      launch_recon<3, double>(gr, fp, ws, s);
+  }
+  const int rc = hip_status(hipGetLastError());
+  if (rc == SL_OK) {
+    gr->steps_since_reset = 0;
+    gr->reconstructs_launched++;
+  }
+  return rc;
+}
+
+int sl_sync(sl_grid* gr, void* workspace, void* stream, sl_stats* out) {
+  if (!gr || !workspace) return SL_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  unsigned long long host[sl::ST_COUNT];
+  auto* dev = reinterpret_cast<unsigned long long*>(static_cast<char*>(workspace) + gr->off_stats);
+  clear_stale_error();
+  int rc = hip_status(hipMemcpyAsync(host, dev, sizeof(host), hipMemcpyDeviceToHost, s));
+  if (rc != SL_OK) return rc;
+  sl::zero_kernel<<<1, 64, 0, s>>>(dev, sl::ST_COUNT);
+  rc = hip_status(hipGetLastError());
+  if (rc != SL_OK) return rc;
+  rc = hip_status(hipStreamSynchronize(s));
+  if (rc != SL_OK) return rc;
+  const int64_t recs = gr->reconstructs_launched;
+  const int64_t nodes = recs * gr->ntot;
+  if (out) {
+    memset(out, 0, sizeof(*out));
+    out->nodes = nodes;
+    out->search_fail = (int64_t)host[sl::ST_SEARCH_FAIL];
+    out->newton_fail = (int64_t)host[sl::ST_NEWTON_FAIL];
+    out->nonfinite = (int64_t)host[sl::ST_NONFINITE];
+    out->order_hist[0] = (int64_t)host[sl::ST_ORDER0];
+    out->order_hist[1] = (int64_t)host[sl::ST_ORDER1];
+    const int64_t located = nodes - out->search_fail - out->newton_fail;
+    out->order_hist[2] = located * gr->desc.nfields - out->order_hist[0] - out->order_hist[1];
+    out->walked = (int64_t)host[sl::ST_WALKED];
+    out->scanned = (int64_t)host[sl::ST_SCANNED];
+    out->steps = gr->steps_launched;
+    out->reconstructs = recs;
+  }
+  gr->steps_launched = 0;
+  gr->reconstructs_launched = 0;
+  if (host[sl::ST_SEARCH_FAIL]) return SL_ESEARCH;
+  if (host[sl::ST_NEWTON_FAIL]) return SL_ENEWTON;
+  if (host[sl::ST_NONFINITE]) return SL_ENONFINITE;
+  return SL_OK;
+}
+
+const double* sl_displacement(const sl_grid* gr, const void* workspace, int axis) {
+  if (!gr || !workspace || axis < 0 || axis >= gr->desc.dim) return nullptr;
+  return reinterpret_cast<const double*>(static_cast<const char*>(workspace) + gr->off_disp) +
+         (size_t)axis * (size_t)gr->ntot;
+}
+
+const char* sl_strerror(int code) {
+  switch (code) {
+    case SL_OK: return "ok";
+    case SL_EINVAL: return "invalid argument";
+    case SL_ENOMEM: return "out of host memory";
+    case SL_EHIP: return "HIP runtime error";
+    case SL_ESEARCH: return "host element not found";
+    case SL_ENEWTON: return "Newton iteration did not converge";
+    case SL_ENONFINITE: return "non-finite reconstructed value";
+    case SL_EBUSY: return "resources exhausted";
+    case SL_ESTATE: return "call out of order";
+    case SL_ENOTFOUND: return "unknown request";
+    default: return "unknown status";
+  }
+}
+
+int sl_version(void) { return SL_VERSION; }
+
+const char* sl_error_detail(void) { return g_detail; }
+
+}  // extern "C"

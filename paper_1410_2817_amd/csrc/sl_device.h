@@ -1,0 +1,420 @@
+// Device building blocks of the forward semi-Lagrangian step for gfx950:
+// prescribed velocities, cardinal Z-spline weights, the element map inversion
+// and the host-element search.  Everything here is header-only so that the
+// kernels in sl.hip inline it.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sl.h"
+
+namespace sl {
+
+// ---------------------------------------------------------------------------
+// Kernel argument blocks (passed by value; they live in the kernarg segment).
+
+struct GridArgs {
+  int n[3];
+  int ntot;
+  double h[3];
+  int nfields;
+  int order_max;
+  int limiter;
+  double theta;
+  int newton_max_iter;
+  double newton_tol;
+  int walk_max;
+  int scan_radius;
+  double eps;
+};
+
+// Fourier mode q: theta/pi = c[0] x + c[1] y + c[2] z + phase/pi, and the mode
+// adds amp * cos(theta) to the velocity.
+struct Mode {
+  double c[3];
+  double amp[3];
+  double phase_over_pi;
+  double pad;
+};
+
+struct VelArgs {
+  int kind;
+  int nmodes;
+  double p[8];
+  Mode mode[SL_MAX_MODES];
+};
+
+struct FieldPtrs {
+  const void* in[SL_MAX_FIELDS];
+  void* out[SL_MAX_FIELDS];
+};
+
+// Slots of the device counter block at the start of the workspace.
+enum StatSlot {
+  ST_NODES = 0,
+  ST_SEARCH_FAIL,
+  ST_NEWTON_FAIL,
+  ST_NONFINITE,
+  ST_ORDER0,
+  ST_ORDER1,
+  ST_ORDER2,
+  ST_WALKED,
+  ST_SCANNED,
+  ST_COUNT
+};
+
+__device__ __forceinline__ int wrap_index(int i, int n) {
+  int r = i % n;
+  return r < 0 ? r + n : r;
+}
+
+// Adds the number of active lanes with `pred` to *ctr, one atomic per wave and
+// only when the count is non-zero.  Must be reached by all active lanes.
+__device__ __forceinline__ void wave_count(unsigned long long* ctr, bool pred) {
+  unsigned long long m = __ballot(pred);
+  if (m) {
+    unsigned long long act = __ballot(1);
+    if ((int)__lane_id() == __ffsll((long long)act) - 1)
+      atomicAdd(ctr, (unsigned long long)__popcll(m));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Prescribed velocity u(x, t) (physical units).  `tf` is the time factor
+// cos(pi t / p0) of the periodic families, evaluated once per stage.
+
+template <int VK, int D>
+__device__ __forceinline__ void velocity(const VelArgs& v, const double* x, double tf,
+                                         double* u) {
+  if constexpr (VK == SL_VEL_UNIFORM) {
+    for (int a = 0; a < D; ++a) u[a] = v.p[a];
+  } else if constexpr (VK == SL_VEL_SOLID_BODY) {
+    u[0] = -v.p[0] * (x[1] - v.p[2]);
+    u[1] = v.p[0] * (x[0] - v.p[1]);
+    if constexpr (D == 3) u[2] = 0.0;
+  } else if constexpr (VK == SL_VEL_SWIRL2D) {
+    double sx, cx, sy, cy;
+    sincospi(x[0], &sx, &cx);
+    sincospi(x[1], &sy, &cy);
+    const double s = v.p[1] * tf;
+    // sin(2 pi y) = 2 sin(pi y) cos(pi y)
+    u[0] = s * sx * sx * (2.0 * sy * cy);
+    u[1] = -s * sy * sy * (2.0 * sx * cx);
+    if constexpr (D == 3) u[2] = 0.0;
+  } else if constexpr (VK == SL_VEL_DEFORM3D && D == 3) {
+    double sx, cx, sy, cy, sz, cz;
+    sincospi(x[0], &sx, &cx);
+    sincospi(x[1], &sy, &cy);
+    sincospi(x[2], &sz, &cz);
+    const double s = v.p[1] * tf;
+    const double s2x = 2.0 * sx * cx, s2y = 2.0 * sy * cy, s2z = 2.0 * sz * cz;
+    u[0] = 2.0 * s * sx * sx * s2y * s2z;
+    u[1] = -s * s2x * sy * sy * s2z;
+    u[2] = -s * s2x * s2y * sz * sz;
+  } else if constexpr (VK == SL_VEL_FOURIER) {
+    for (int a = 0; a < D; ++a) u[a] = 0.0;
+    for (int q = 0; q < v.nmodes; ++q) {
+      const Mode& md = v.mode[q];
+      double th = md.phase_over_pi;
+      for (int a = 0; a < D; ++a) th += md.c[a] * x[a];
+      const double cs = cospi(th);
+      for (int a = 0; a < D; ++a) u[a] += md.amp[a] * cs;
+    }
+  } else {
+    // Combinations rejected at grid creation (a 3-D family on a 2-D grid).
+    for (int a = 0; a < D; ++a) u[a] = 0.0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Cardinal Z-spline weights (Appendix).  For a point r + t, slot s = k + 2
+// holds the weight Z_m(t - k) of node r + k, k = -2..3; slots outside the
+// order-m stencil are zero.  The factored forms below are those polynomials
+// with their roots at the knots pulled out, so t = 0 gives exactly the
+// unit weight on slot 2 and zeros elsewhere.
+
+template <typename T>
+__device__ __forceinline__ void zspline_weights(int m, T t, T* w) {
+  // The 1/12 and 1/24 factors are folded into the coefficients; the only
+  // non-zero weight at t = 0 has constant term exactly 1.
+  const T one = T(1);
+  const T u = t - one;  // t - 1
+  if (m == 2) {
+    const T t2 = t * t;
+    // Z2(t + 2) = -t (t-1)^3 (5t + 2) / 24
+    w[0] = t * (u * u * u) * (T(-5.0 / 24.0) * t - T(2.0 / 24.0));
+    // Z2(t + 1) = t (t-1) (25t^3 - 39t^2 + 16) / 24
+    w[1] = t * u * ((T(25.0 / 24.0) * t - T(39.0 / 24.0)) * t2 + T(16.0 / 24.0));
+    // Z2(t) = -(t-1) (25t^4 - 38t^3 - 3t^2 + 12t + 12) / 12
+    w[2] = -u * ((((T(25.0 / 12.0) * t - T(38.0 / 12.0)) * t - T(3.0 / 12.0)) * t + one) * t +
+                 one);
+    // Z2(1 - t) = t (25t^4 - 62t^3 + 33t^2 + 8t + 8) / 12
+    w[3] = t * ((((T(25.0 / 12.0) * t - T(62.0 / 12.0)) * t + T(33.0 / 12.0)) * t +
+                 T(8.0 / 12.0)) * t + T(8.0 / 12.0));
+    // Z2(2 - t) = -t (t-1) (25t^3 - 36t^2 - 3t - 2) / 24
+    w[4] = -t * u * (((T(25.0 / 24.0) * t - T(36.0 / 24.0)) * t - T(3.0 / 24.0)) * t -
+                     T(2.0 / 24.0));
+    // Z2(3 - t) = t^3 (t-1) (5t - 7) / 24
+    w[5] = t2 * t * u * (T(5.0 / 24.0) * t - T(7.0 / 24.0));
+  } else if (m == 1) {
+    w[0] = T(0);
+    // Z1(t + 1) = -t (t-1)^2 / 2
+    w[1] = -t * u * u * T(0.5);
+    // Z1(t) = (t-1) (3t^2 - 2t - 2) / 2
+    w[2] = u * ((T(3) * t - T(2)) * t - T(2)) * T(0.5);
+    // Z1(1 - t) = -t (3t^2 - 4t - 1) / 2
+    w[3] = -t * ((T(3) * t - T(4)) * t - one) * T(0.5);
+    // Z1(2 - t) = t^2 (t-1) / 2
+    w[4] = t * t * u * T(0.5);
+    w[5] = T(0);
+  } else {
+    w[0] = T(0);
+    w[1] = T(0);
+    w[2] = one - t;
+    w[3] = t;
+    w[4] = T(0);
+    w[5] = T(0);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Inversion of the multilinear (Z0) map of one deformed element (Sec. 2.2).
+//
+// V[e] = X(r + e) - x' are the element's vertex positions relative to the
+// target mesh point, e in {0,1}^D with bit a for axis a.  Expanding the map
+// about vertex r gives the finite series of eq. "mapping1":
+//   F(xi) = V0 + sum_a A_a xi_a + sum_{a<b} B_ab xi_a xi_b (+ C xi_0 xi_1 xi_2).
+// Newton's method solves F = 0 starting from the root of the linear part.
+// Returns 1 if Newton converged (xi = solution), 0 if only the linear root is
+// available (xi = that), -1 if the linear part is singular.
+
+template <int D>
+struct Element;
+
+template <>
+struct Element<2> {
+  double v0[2], a[2], b[2], c[2];
+
+  __device__ __forceinline__ void set(const double (*V)[2]) {
+    for (int i = 0; i < 2; ++i) {
+      v0[i] = V[0][i];
+      a[i] = V[1][i] - V[0][i];
+      b[i] = V[2][i] - V[0][i];
+      c[i] = (V[3][i] - V[1][i]) - (V[2][i] - V[0][i]);
+    }
+  }
+
+  __device__ __forceinline__ int solve(const GridArgs& g, double* xi) const {
+    double det = a[0] * b[1] - b[0] * a[1];
+    if (!(det != 0.0) || !isfinite(det)) return -1;
+    double inv = 1.0 / det;
+    const double xl = (-v0[0] * b[1] + b[0] * v0[1]) * inv;
+    const double yl = (-a[0] * v0[1] + v0[0] * a[1]) * inv;
+    double x = xl, y = yl;
+    for (int it = 0; it < g.newton_max_iter; ++it) {
+      const double f0 = v0[0] + a[0] * x + b[0] * y + c[0] * (x * y);
+      const double f1 = v0[1] + a[1] * x + b[1] * y + c[1] * (x * y);
+      const double j00 = a[0] + c[0] * y, j01 = b[0] + c[0] * x;
+      const double j10 = a[1] + c[1] * y, j11 = b[1] + c[1] * x;
+      const double dj = j00 * j11 - j01 * j10;
+      if (!(dj != 0.0) || !isfinite(dj)) break;
+      const double ij = 1.0 / dj;
+      const double dx = (f0 * j11 - j01 * f1) * ij;
+      const double dy = (j00 * f1 - f0 * j10) * ij;
+      x -= dx;
+      y -= dy;
+      const double mx = fmax(fabs(dx), fabs(dy));
+      if (!isfinite(mx)) break;
+      if (mx <= g.newton_tol) {
+        xi[0] = x;
+        xi[1] = y;
+        return 1;
+      }
+    }
+    xi[0] = xl;
+    xi[1] = yl;
+    return 0;
+  }
+};
+
+template <>
+struct Element<3> {
+  double v0[3], a[3], b[3], c[3], ab[3], ac[3], bc[3], abc[3];
+
+  __device__ __forceinline__ void set(const double (*V)[3]) {
+    for (int i = 0; i < 3; ++i) {
+      v0[i] = V[0][i];
+      a[i] = V[1][i] - V[0][i];
+      b[i] = V[2][i] - V[0][i];
+      c[i] = V[4][i] - V[0][i];
+      ab[i] = (V[3][i] - V[1][i]) - (V[2][i] - V[0][i]);
+      ac[i] = (V[5][i] - V[1][i]) - (V[4][i] - V[0][i]);
+      bc[i] = (V[6][i] - V[2][i]) - (V[4][i] - V[0][i]);
+      abc[i] = ((V[7][i] - V[6][i]) - (V[5][i] - V[4][i])) -
+               ((V[3][i] - V[2][i]) - (V[1][i] - V[0][i]));
+    }
+  }
+
+  // Solve M d = f for the 3x3 matrix with columns c0, c1, c2 (Cramer).
+  __device__ __forceinline__ static bool solve3(const double* c0, const double* c1,
+                                                const double* c2, const double* f,
+                                                double* d) {
+    const double x12[3] = {c1[1] * c2[2] - c1[2] * c2[1], c1[2] * c2[0] - c1[0] * c2[2],
+                           c1[0] * c2[1] - c1[1] * c2[0]};
+    const double det = c0[0] * x12[0] + c0[1] * x12[1] + c0[2] * x12[2];
+    if (!(det != 0.0) || !isfinite(det)) return false;
+    const double x20[3] = {c2[1] * c0[2] - c2[2] * c0[1], c2[2] * c0[0] - c2[0] * c0[2],
+                           c2[0] * c0[1] - c2[1] * c0[0]};
+    const double x01[3] = {c0[1] * c1[2] - c0[2] * c1[1], c0[2] * c1[0] - c0[0] * c1[2],
+                           c0[0] * c1[1] - c0[1] * c1[0]};
+    const double inv = 1.0 / det;
+    d[0] = (f[0] * x12[0] + f[1] * x12[1] + f[2] * x12[2]) * inv;
+    d[1] = (f[0] * x20[0] + f[1] * x20[1] + f[2] * x20[2]) * inv;
+    d[2] = (f[0] * x01[0] + f[1] * x01[1] + f[2] * x01[2]) * inv;
+    return true;
+  }
+
+  __device__ __forceinline__ int solve(const GridArgs& g, double* xi) const {
+    const double mv0[3] = {-v0[0], -v0[1], -v0[2]};
+    double xl[3];
+    if (!solve3(a, b, c, mv0, xl)) return -1;
+    double x = xl[0], y = xl[1], z = xl[2];
+    for (int it = 0; it < g.newton_max_iter; ++it) {
+      double f[3], j0[3], j1[3], j2[3];
+      for (int i = 0; i < 3; ++i) {
+        f[i] = v0[i] + a[i] * x + b[i] * y + c[i] * z + ab[i] * (x * y) + ac[i] * (x * z) +
+               bc[i] * (y * z) + abc[i] * (x * y * z);
+        j0[i] = a[i] + ab[i] * y + ac[i] * z + abc[i] * (y * z);
+        j1[i] = b[i] + ab[i] * x + bc[i] * z + abc[i] * (x * z);
+        j2[i] = c[i] + ac[i] * x + bc[i] * y + abc[i] * (x * y);
+      }
+      double dl[3];
+      if (!solve3(j0, j1, j2, f, dl)) break;
+      x -= dl[0];
+      y -= dl[1];
+      z -= dl[2];
+      const double mx = fmax(fabs(dl[0]), fmax(fabs(dl[1]), fabs(dl[2])));
+      if (!isfinite(mx)) break;
+      if (mx <= g.newton_tol) {
+        xi[0] = x;
+        xi[1] = y;
+        xi[2] = z;
+        return 1;
+      }
+    }
+    xi[0] = xl[0];
+    xi[1] = xl[1];
+    xi[2] = xl[2];
+    return 0;
+  }
+};
+
+// Result codes of locate().
+enum { LOC_OK = 0, LOC_SEARCH_FAIL = 1, LOC_NEWTON_FAIL = 2 };
+
+// Element with lower vertex r for target mesh node tgt; `disp(idx, d)` returns
+// the displacement (cells) of the wrapped lattice node idx.
+template <int D, class DispFn>
+__device__ __forceinline__ int element_solve(const GridArgs& g, const DispFn& disp,
+                                             const int* tgt, const int* r, double* xi) {
+  double V[1 << D][D];
+#pragma unroll
+  for (int e = 0; e < (1 << D); ++e) {
+    int v[D], w[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      v[a] = r[a] + ((e >> a) & 1);
+      w[a] = wrap_index(v[a], g.n[a]);
+    }
+    double d[D];
+    disp(w, d);
+#pragma unroll
+    for (int a = 0; a < D; ++a) V[e][a] = (double)(v[a] - tgt[a]) + d[a];
+  }
+  Element<D> el;
+  el.set(V);
+  return el.solve(g, xi);
+}
+
+template <int D>
+__device__ __forceinline__ bool in_cube(const GridArgs& g, const double* xi) {
+  bool ok = true;
+#pragma unroll
+  for (int a = 0; a < D; ++a) ok = ok && (xi[a] >= -g.eps) && (xi[a] <= 1.0 + g.eps);
+  return ok;
+}
+
+// Host-element search (Sec. 2.2): start in the cell below tgt - d(tgt), move
+// one cell per axis toward the side an out-of-range local coordinate points
+// to.  A cell is accepted only when Newton converges inside its unit cube;
+// when Newton does not converge the linear root points the way.  If the walk
+// stalls (linear root inside, Newton not converging) or does not settle within
+// walk_max moves, the cells of the box of half-width scan_radius around the
+// start cell are tried in order, x fastest.  `walked` reports 0 (start cell),
+// 1 (walked), 2 (fallback scan).
+template <int D, class DispFn>
+__device__ __forceinline__ int locate(const GridArgs& g, const DispFn& disp, const int* tgt,
+                                      int* r, double* xi, int& walked) {
+  int start[D];
+  {
+    double d0[D];
+    disp(tgt, d0);
+#pragma unroll
+    for (int a = 0; a < D; ++a) start[a] = r[a] = (int)floor((double)tgt[a] - d0[a]);
+  }
+  walked = 0;
+  bool newton_trouble = false;
+  for (int walk = 0; walk < g.walk_max; ++walk) {
+    double x[D];
+    const int rc = element_solve<D>(g, disp, tgt, r, x);
+    if (rc < 0) break;
+    if (in_cube<D>(g, x)) {
+      if (rc == 1) {
+#pragma unroll
+        for (int a = 0; a < D; ++a) xi[a] = x[a];
+        return LOC_OK;
+      }
+      newton_trouble = true;
+      break;
+    }
+#pragma unroll
+    for (int a = 0; a < D; ++a) r[a] += (x[a] < -g.eps) ? -1 : ((x[a] > 1.0 + g.eps) ? 1 : 0);
+    walked = 1;
+  }
+  const int W = g.scan_radius, span = 2 * g.scan_radius + 1;
+  int cnt = 1;
+  for (int a = 0; a < D; ++a) cnt *= span;
+  for (int q = 0; q < cnt; ++q) {
+    int qq = q;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      r[a] = start[a] - W + qq % span;
+      qq /= span;
+    }
+    double x[D];
+    const int rc = element_solve<D>(g, disp, tgt, r, x);
+    if (rc >= 0 && in_cube<D>(g, x)) {
+      if (rc == 1) {
+#pragma unroll
+        for (int a = 0; a < D; ++a) xi[a] = x[a];
+        walked = 2;
+        return LOC_OK;
+      }
+      newton_trouble = true;
+    }
+  }
+  return newton_trouble ? LOC_NEWTON_FAIL : LOC_SEARCH_FAIL;
+}
+
+// Jump criterion of Sec. 2.3 on one axis, evaluated in FP64 from the stored
+// values: |h+ - 2h + h-| > theta * max(|h+ - h|, |h - h-|).
+__device__ __forceinline__ bool jump_flag(double hm, double hc, double hp, double theta) {
+#pragma clang fp contract(off)
+  const double d2 = (hp - 2.0 * hc) + hm;
+  const double dp = hp - hc;
+  const double dm = hc - hm;
+  return fabs(d2) > theta * fmax(fabs(dp), fabs(dm));
+}
+
+}  // namespace sl
