@@ -176,6 +176,33 @@ int sl_reconstruct(sl_grid *grid, void *workspace, const void *const *fields_in,
  * or SL_EHIP / SL_EINVAL. */
 int sl_sync(sl_grid *grid, void *workspace, void *stream, sl_stats *stats);
 
+/* Run nsteps steps from t0 with a constant dt: every reconstruct_every steps
+ * the lattice is reconstructed onto the mesh and reset.  The fields ping-pong
+ * between the caller-owned sets fields_a (initial values) and fields_b;
+ * *result_in_b (may be NULL) tells which set holds the result.  nsteps must be
+ * a multiple of reconstruct_every and the lattice must be reset (no pending
+ * sl_step).  Asynchronous on `stream`; equivalent to the sequence of sl_step /
+ * sl_reconstruct calls but without per-call host overhead.
+ * Errors: SL_EINVAL, SL_ESTATE, SL_EHIP. */
+int sl_advance(sl_grid *grid, void *workspace, void *const *fields_a,
+               void *const *fields_b, double t0, double dt, int nsteps,
+               void *stream, int *result_in_b);
+
+/* Kernel timing: when enabled, every trajectory and reconstruction launch of
+ * the grid carries HIP events in its dispatch packet. */
+typedef struct sl_profile {
+  int64_t traj_launches;
+  double traj_ms;          /* summed kernel time of the trajectory launches */
+  int64_t recon_launches;
+  double recon_ms;         /* summed kernel time of the reconstruction launches */
+} sl_profile;
+
+/* Switch event timing on (1) or off (0) for later launches. */
+int sl_profile_enable(sl_grid *grid, int on);
+
+/* Wait for the timed launches, report their totals and clear them. */
+int sl_profile_read(sl_grid *grid, sl_profile *out);
+
 /* Device pointer to the lattice displacement along `axis` (0 = x) inside
  * `workspace`: n[0]*n[1](*n[2]) doubles in cell units, x fastest, valid after
  * sl_step and until the next sl_step after a reconstruction.  NULL on a bad

@@ -55,6 +55,15 @@ class SlStats(C.Structure):
                 "reconstructs": self.reconstructs}
 
 
+class SlProfile(C.Structure):
+    _fields_ = [("traj_launches", C.c_int64), ("traj_ms", C.c_double),
+                ("recon_launches", C.c_int64), ("recon_ms", C.c_double)]
+
+    def as_dict(self) -> dict:
+        return {"traj_launches": self.traj_launches, "traj_ms": self.traj_ms,
+                "recon_launches": self.recon_launches, "recon_ms": self.recon_ms}
+
+
 # Every symbol include/sl.h declares, with its ctypes signature.
 _VP = C.c_void_p
 SIGNATURES = {
@@ -65,6 +74,10 @@ SIGNATURES = {
     "sl_step": (C.c_int, [_VP, _VP, C.c_double, C.c_double, _VP]),
     "sl_reconstruct": (C.c_int, [_VP, _VP, C.POINTER(_VP), C.POINTER(_VP), _VP]),
     "sl_sync": (C.c_int, [_VP, _VP, _VP, C.POINTER(SlStats)]),
+    "sl_advance": (C.c_int, [_VP, _VP, C.POINTER(_VP), C.POINTER(_VP), C.c_double,
+                             C.c_double, C.c_int, _VP, C.POINTER(C.c_int)]),
+    "sl_profile_enable": (C.c_int, [_VP, C.c_int]),
+    "sl_profile_read": (C.c_int, [_VP, C.POINTER(SlProfile)]),
     "sl_displacement": (C.c_void_p, [_VP, _VP, C.c_int]),
     "sl_strerror": (C.c_char_p, [C.c_int]),
     "sl_version": (C.c_int, []),
@@ -247,17 +260,27 @@ class Grid:
         nbytes = 8 * dim * self.nodes
         return self.workspace[off:off + nbytes].view(torch.float64).view(dim, *self.shape)
 
-    def advance(self, fields, t0: float, dt: float, nsteps: int, kevery: int = 1,
-                out=None, stream=None):
-        """nsteps steps from t0 (lattice reset every `kevery` steps); returns the
-        final fields (one of two ping-pong buffer sets)."""
-        if nsteps % kevery:
-            raise ValueError("nsteps must be a multiple of kevery")
+    def profile(self, on: bool = True):
+        check(load().sl_profile_enable(self._h, int(bool(on))), "sl_profile_enable")
+
+    def profile_read(self) -> dict:
+        p = SlProfile()
+        check(load().sl_profile_read(self._h, C.byref(p)), "sl_profile_read")
+        return p.as_dict()
+
+    def advance(self, fields, t0: float, dt: float, nsteps: int, out=None, stream=None):
+        """nsteps steps from t0 (one sl_advance call; the lattice is reset every
+        reconstruct_every steps); returns the set of buffers holding the result,
+        which is either `fields` or `out` (allocated when not given)."""
         a = list(fields)
-        b = out if out is not None else self.new_fields()
-        for s in range(0, nsteps, kevery):
-            for k in range(kevery):
-                self.step(t0 + (s + k) * dt, dt, stream)
-            self.reconstruct(a, b, stream)
-            a, b = b, a
-        return a
+        b = list(out) if out is not None else self.new_fields()
+        self._check_fields(a)
+        self._check_fields(b)
+        pa = (_VP * self.nfields)(*[f.data_ptr() for f in a])
+        pb = (_VP * self.nfields)(*[f.data_ptr() for f in b])
+        in_b = C.c_int(0)
+        check(load().sl_advance(self._h, C.c_void_p(self.workspace.data_ptr()), pa, pb,
+                                float(t0), float(dt), int(nsteps),
+                                C.c_void_p(_stream_handle(stream)), C.byref(in_b)),
+              "sl_advance")
+        return b if in_b.value else a

@@ -9,6 +9,7 @@
 //                 the multilinear element map (eq. "mapping1"), order
 //                 selection from the flags, cardinal Z-spline weights
 //                 (Appendix) and the tensor-product gather-sum (eq. "multiZ").
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <math.h>
@@ -17,10 +18,13 @@
 #include <string.h>
 
 #include <new>
+#include <tuple>
+#include <utility>
 #include <vector>
 
 #include "sl.h"
 #include "sl_device.h"
+#include "sl_recon2d.h"
 
 namespace sl {
 
@@ -57,15 +61,21 @@ __device__ __forceinline__ double time_factor(const VelArgs& v, double t) {
     return 1.0;
 }
 
+// Launched on a (ceil(nx/64), ceil(ny/4), nz) grid of 64 x 4 work-items, so
+// node coordinates come without integer division.
+constexpr int kTrajBX = 64, kTrajBY = 4;
+
 template <int D, int VK>
 __global__ __launch_bounds__(kBlock) void traj_kernel(GridArgs g, VelArgs v,
                                                       double* __restrict__ disp, double t,
                                                       double dt, int accumulate,
                                                       int integrator) {
-  const int lin = blockIdx.x * kBlock + threadIdx.x;
-  if (lin >= g.ntot) return;
   int idx[D];
-  unflatten<D>(g, lin, idx);
+  idx[0] = blockIdx.x * kTrajBX + threadIdx.x;
+  idx[1] = blockIdx.y * kTrajBY + threadIdx.y;
+  if constexpr (D == 3) idx[2] = blockIdx.z;
+  if (idx[0] >= g.n[0] || idx[1] >= g.n[1]) return;
+  const int lin = flatten<D>(g, idx);
   double d[D], x[D];
 #pragma unroll
   for (int a = 0; a < D; ++a) {
@@ -152,11 +162,15 @@ __global__ __launch_bounds__(kBlock) void flags_kernel(GridArgs g, FieldPtrs fp,
 // ---------------------------------------------------------------------------
 // Reconstruction (Sec. 2.1-2.3).
 
+// Displacement of the lattice node with unwrapped index v, from global memory.
 template <int D>
 struct GlobalDisp {
   const double* __restrict__ disp;
   GridArgs g;
-  __device__ __forceinline__ void operator()(const int* w, double* d) const {
+  __device__ __forceinline__ void operator()(const int* v, double* d) const {
+    int w[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) w[a] = wrap_index(v[a], g.n[a]);
     const int lin = flatten<D>(g, w);
 #pragma unroll
     for (int a = 0; a < D; ++a) d[a] = disp[(size_t)a * g.ntot + lin];
@@ -173,9 +187,11 @@ __global__ __launch_bounds__(kBlock) void recon_kernel(GridArgs g, FieldPtrs fp,
   int tgt[D];
   unflatten<D>(g, lin, tgt);
   int r[D];
-  double xi[D];
+  double xi[D], d0[D];
   int walked = 0;
-  const int loc = locate<D>(g, GlobalDisp<D>{disp, g}, tgt, r, xi, walked);
+  const GlobalDisp<D> gd{disp, g};
+  gd(tgt, d0);
+  const int loc = locate<D>(g, gd, tgt, d0, r, xi, walked);
   wave_count(stats + ST_SEARCH_FAIL, loc == LOC_SEARCH_FAIL);
   wave_count(stats + ST_NEWTON_FAIL, loc == LOC_NEWTON_FAIL);
   wave_count(stats + ST_WALKED, walked != 0);
@@ -283,6 +299,11 @@ __global__ void zero_kernel(unsigned long long* p, int n) {
 // ===========================================================================
 // Host side: descriptors, validation, launches.
 
+struct sl_prof_pair {
+  int kind;  // 0 trajectories, 1 reconstruction
+  hipEvent_t start, stop;
+};
+
 struct sl_grid {
   sl_grid_desc desc;
   std::vector<double> modes;
@@ -292,6 +313,12 @@ struct sl_grid {
   size_t off_stats, off_disp, off_flags, ws_bytes;
   int steps_since_reset;
   int64_t steps_launched, reconstructs_launched;
+  // Kernel timing with events attached to the dispatch packets.
+  bool prof_on;
+  std::vector<hipEvent_t> ev_free;
+  std::vector<sl_prof_pair> pending;
+  double prof_ms[2];
+  int64_t prof_n[2];
 };
 
 namespace {
@@ -300,6 +327,83 @@ constexpr size_t kAlign = 256;
 constexpr size_t kStatsBytes = 256;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+constexpr size_t kMaxPendingPairs = 8192;
+
+// Launch through hipExtLaunchKernel so that timing events (when given) are
+// part of the dispatch packet rather than extra packets on the stream.
+template <typename... KArgs, typename... Args, size_t... I>
+hipError_t launch_impl(void (*kernel)(KArgs...), dim3 grid, dim3 block, uint32_t shmem,
+                       hipStream_t s, hipEvent_t e0, hipEvent_t e1,
+                       std::index_sequence<I...>, Args&&... args) {
+  std::tuple<KArgs...> tup(std::forward<Args>(args)...);
+  void* argv[sizeof...(KArgs) > 0 ? sizeof...(KArgs) : 1] = {
+      static_cast<void*>(&std::get<I>(tup))...};
+  return hipExtLaunchKernel(reinterpret_cast<const void*>(kernel), grid, block, argv, shmem,
+                            s, e0, e1, 0);
+}
+
+template <typename... KArgs, typename... Args>
+hipError_t launch(void (*kernel)(KArgs...), dim3 grid, dim3 block, uint32_t shmem,
+                  hipStream_t s, hipEvent_t e0, hipEvent_t e1, Args&&... args) {
+  static_assert(sizeof...(KArgs) == sizeof...(Args), "kernel argument count");
+  return launch_impl(kernel, grid, block, shmem, s, e0, e1,
+                     std::index_sequence_for<KArgs...>{}, std::forward<Args>(args)...);
+}
+
+void prof_fold(sl_grid* gr) {
+  for (const sl_prof_pair& p : gr->pending) {
+    float ms = 0.0f;
+    if (hipEventSynchronize(p.stop) == hipSuccess &&
+        hipEventElapsedTime(&ms, p.start, p.stop) == hipSuccess) {
+      gr->prof_ms[p.kind] += ms;
+      gr->prof_n[p.kind] += 1;
+    }
+    gr->ev_free.push_back(p.start);
+    gr->ev_free.push_back(p.stop);
+  }
+  gr->pending.clear();
+}
+
+hipEvent_t prof_event(sl_grid* gr) {
+  if (!gr->ev_free.empty()) {
+    hipEvent_t e = gr->ev_free.back();
+    gr->ev_free.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Events for the next launch of `kind` (null events when profiling is off).
+struct ProfSlot {
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+
+ProfSlot prof_begin(sl_grid* gr) {
+  ProfSlot ps;
+  if (!gr->prof_on) return ps;
+  if (gr->pending.size() >= kMaxPendingPairs) prof_fold(gr);
+  ps.start = prof_event(gr);
+  ps.stop = prof_event(gr);
+  if (!ps.start || !ps.stop) {
+    if (ps.start) gr->ev_free.push_back(ps.start);
+    if (ps.stop) gr->ev_free.push_back(ps.stop);
+    ps.start = ps.stop = nullptr;
+  }
+  return ps;
+}
+
+void prof_end(sl_grid* gr, const ProfSlot& ps, int kind, hipError_t launched) {
+  if (!ps.start) return;
+  if (launched == hipSuccess) {
+    gr->pending.push_back({kind, ps.start, ps.stop});
+  } else {
+    gr->ev_free.push_back(ps.start);
+    gr->ev_free.push_back(ps.stop);
+  }
+}
 
 int check_desc(const sl_grid_desc* d) {
   if (!d) return SL_EINVAL;
@@ -323,6 +427,8 @@ int check_desc(const sl_grid_desc* d) {
     tot *= d->n[a];
     if (tot > (int64_t)INT32_MAX / 2) return SL_EINVAL;
   }
+  // Launch-grid limits of the y and z grid dimensions.
+  if (d->n[1] > 4 * 65535 || (d->dim == 3 && d->n[2] > 65535)) return SL_EINVAL;
   const sl_velocity& v = d->vel;
   if (v.kind < SL_VEL_UNIFORM || v.kind > SL_VEL_FOURIER) return SL_EINVAL;
   if (v.kind == SL_VEL_SWIRL2D && (d->dim != 2 || !(v.p[0] != 0.0))) return SL_EINVAL;
@@ -355,38 +461,68 @@ int hip_status(hipError_t e) {
 void clear_stale_error() { (void)hipGetLastError(); }
 
 template <int D>
-void launch_traj(sl_grid* gr, double* disp, double t, double dt, int accumulate,
-                 hipStream_t s) {
-  const int blocks = (int)((gr->ntot + sl::kBlock - 1) / sl::kBlock);
+hipError_t launch_traj(sl_grid* gr, double* disp, double t, double dt, int accumulate,
+                       hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  const dim3 blocks((unsigned)((gr->g.n[0] + sl::kTrajBX - 1) / sl::kTrajBX),
+                    (unsigned)((gr->g.n[1] + sl::kTrajBY - 1) / sl::kTrajBY),
+                    (unsigned)gr->g.n[2]);
+  const dim3 threads(sl::kTrajBX, sl::kTrajBY);
   const int integ = gr->desc.integrator;
   switch (gr->v.kind) {
     case SL_VEL_UNIFORM:
-      sl::traj_kernel<D, SL_VEL_UNIFORM><<<blocks, sl::kBlock, 0, s>>>(gr->g, gr->v, disp, t, dt, accumulate, integ);
-      break;
+      return launch(sl::traj_kernel<D, SL_VEL_UNIFORM>, blocks, threads, 0, s, e0, e1, gr->g, gr->v, disp, t, dt, accumulate, integ);
     case SL_VEL_SOLID_BODY:
-      sl::traj_kernel<D, SL_VEL_SOLID_BODY><<<blocks, sl::kBlock, 0, s>>>(gr->g, gr->v, disp, t, dt, accumulate, integ);
-      break;
+      return launch(sl::traj_kernel<D, SL_VEL_SOLID_BODY>, blocks, threads, 0, s, e0, e1, gr->g, gr->v, disp, t, dt, accumulate, integ);
     case SL_VEL_SWIRL2D:
-      sl::traj_kernel<D, SL_VEL_SWIRL2D><<<blocks, sl::kBlock, 0, s>>>(gr->g, gr->v, disp, t, dt, accumulate, integ);
-      break;
+      return launch(sl::traj_kernel<D, SL_VEL_SWIRL2D>, blocks, threads, 0, s, e0, e1, gr->g, gr->v, disp, t, dt, accumulate, integ);
     case SL_VEL_DEFORM3D:
-      sl::traj_kernel<D, SL_VEL_DEFORM3D><<<blocks, sl::kBlock, 0, s>>>(gr->g, gr->v, disp, t, dt, accumulate, integ);
-      break;
+      return launch(sl::traj_kernel<D, SL_VEL_DEFORM3D>, blocks, threads, 0, s, e0, e1, gr->g, gr->v, disp, t, dt, accumulate, integ);
     default:
-      sl::traj_kernel<D, SL_VEL_FOURIER><<<blocks, sl::kBlock, 0, s>>>(gr->g, gr->v, disp, t, dt, accumulate, integ);
-      break;
+      return launch(sl::traj_kernel<D, SL_VEL_FOURIER>, blocks, threads, 0, s, e0, e1, gr->g, gr->v, disp, t, dt, accumulate, integ);
   }
 }
 
 template <int D, typename T>
-void launch_recon(sl_grid* gr, const sl::FieldPtrs& fp, char* ws, hipStream_t s) {
-  const int blocks = (int)((gr->ntot + sl::kBlock - 1) / sl::kBlock);
-  uint8_t* flags = reinterpret_cast<uint8_t*>(ws + gr->off_flags);
+hipError_t launch_recon(sl_grid* gr, const sl::FieldPtrs& fp, char* ws, hipStream_t s,
+                        hipEvent_t e0, hipEvent_t e1) {
   const double* disp = reinterpret_cast<const double*>(ws + gr->off_disp);
   auto* stats = reinterpret_cast<unsigned long long*>(ws + gr->off_stats);
-  if (gr->g.limiter && gr->g.order_max > 0)
-    sl::flags_kernel<D, T><<<blocks, sl::kBlock, 0, s>>>(gr->g, fp, flags);
-  sl::recon_kernel<D, T><<<blocks, sl::kBlock, 0, s>>>(gr->g, fp, disp, flags, stats);
+  if constexpr (D == 2) {
+    using C = sl::Tile2D<T>;
+    const int tiles_x = (gr->g.n[0] + C::TX - 1) / C::TX;
+    const int tiles_y = (gr->g.n[1] + C::TY - 1) / C::TY;
+    const int ntiles = tiles_x * tiles_y;
+    const dim3 grid(ntiles), block(sl::kTileThreads);
+    const uint32_t lds = (uint32_t)C::LDS_BYTES;
+#define SL_RECON2D(NF)                                                                       \
+  case NF:                                                                                   \
+    return launch(sl::recon2d_tiled_kernel<T, NF>, grid, block, lds, s, e0, e1, gr->g, fp, \
+                  disp, stats, tiles_x, ntiles);
+    switch (gr->g.nfields) {
+      SL_RECON2D(1)
+      SL_RECON2D(2)
+      SL_RECON2D(3)
+      SL_RECON2D(4)
+      SL_RECON2D(5)
+      SL_RECON2D(6)
+      SL_RECON2D(7)
+      default:
+        return launch(sl::recon2d_tiled_kernel<T, 8>, grid, block, lds, s, e0, e1, gr->g, fp,
+                      disp, stats, tiles_x, ntiles);
+    }
+#undef SL_RECON2D
+  } else {
+    const dim3 blocks((unsigned)((gr->ntot + sl::kBlock - 1) / sl::kBlock)), threads(sl::kBlock);
+    uint8_t* flags = reinterpret_cast<uint8_t*>(ws + gr->off_flags);
+    if (gr->g.limiter && gr->g.order_max > 0) {
+      const hipError_t e = launch(sl::flags_kernel<D, T>, blocks, threads, 0, s, e0, nullptr,
+                                  gr->g, fp, flags);
+      if (e != hipSuccess) return e;
+      e0 = nullptr;
+    }
+    return launch(sl::recon_kernel<D, T>, blocks, threads, 0, s, e0, e1, gr->g, fp,
+                  (const double*)disp, (const uint8_t*)flags, stats);
+  }
 }
 
 }  // namespace
@@ -487,6 +623,13 @@ int sl_create_grid(const sl_grid_desc* desc, sl_grid** out) {
 }
 
 int sl_destroy_grid(sl_grid* grid) {
+  if (!grid) return SL_OK;
+  for (const sl_prof_pair& p : grid->pending) {
+    (void)hipEventSynchronize(p.stop);
+    grid->ev_free.push_back(p.start);
+    grid->ev_free.push_back(p.stop);
+  }
+  for (hipEvent_t e : grid->ev_free) (void)hipEventDestroy(e);
   delete grid;
   return SL_OK;
 }
@@ -500,11 +643,12 @@ int sl_step(sl_grid* gr, void* workspace, double t, double dt, void* stream) {
   double* disp = reinterpret_cast<double*>(static_cast<char*>(workspace) + gr->off_disp);
   const int acc = gr->steps_since_reset > 0;
   clear_stale_error();
-  if (gr->desc.dim == 2)
-    launch_traj<2>(gr, disp, t, dt, acc, s);
-  else
-    launch_traj<3>(gr, disp, t, dt, acc, s);
-  const int rc = hip_status(hipGetLastError());
+  const ProfSlot ps = prof_begin(gr);
+  const hipError_t e = gr->desc.dim == 2
+                           ? launch_traj<2>(gr, disp, t, dt, acc, s, ps.start, ps.stop)
+                           : launch_traj<3>(gr, disp, t, dt, acc, s, ps.start, ps.stop);
+  prof_end(gr, ps, 0, e);
+  const int rc = hip_status(e);
   if (rc == SL_OK) {
     gr->steps_since_reset++;
     gr->steps_launched++;
@@ -532,18 +676,16 @@ int sl_reconstruct(sl_grid* gr, void* workspace, const void* const* fields_in,
   char* ws = static_cast<char*>(workspace);
   const bool f32 = gr->desc.value_prec == SL_FP32;
   clear_stale_error();
-  if (gr->desc.dim == 2) {
-    if (f32)
-      launch_recon<2, float>(gr, fp, ws, s);
-    else
-      launch_recon<2, double>(gr, fp, ws, s);
-  } else {
-    if (f32)
-      launch_recon<3, float>(gr, fp, ws, s);
-    else
-      launch_recon<3, double>(gr, fp, ws, s);
-  }
-  const int rc = hip_status(hipGetLastError());
+  const ProfSlot ps = prof_begin(gr);
+  hipError_t e;
+  if (gr->desc.dim == 2)
+    e = f32 ? launch_recon<2, float>(gr, fp, ws, s, ps.start, ps.stop)
+            : launch_recon<2, double>(gr, fp, ws, s, ps.start, ps.stop);
+  else
+    e = f32 ? launch_recon<3, float>(gr, fp, ws, s, ps.start, ps.stop)
+            : launch_recon<3, double>(gr, fp, ws, s, ps.start, ps.stop);
+  prof_end(gr, ps, 1, e);
+  const int rc = hip_status(e);
   if (rc == SL_OK) {
     gr->steps_since_reset = 0;
     gr->reconstructs_launched++;
@@ -586,6 +728,51 @@ int sl_sync(sl_grid* gr, void* workspace, void* stream, sl_stats* out) {
   if (host[sl::ST_SEARCH_FAIL]) return SL_ESEARCH;
   if (host[sl::ST_NEWTON_FAIL]) return SL_ENEWTON;
   if (host[sl::ST_NONFINITE]) return SL_ENONFINITE;
+  return SL_OK;
+}
+
+int sl_advance(sl_grid* gr, void* workspace, void* const* fields_a, void* const* fields_b,
+               double t0, double dt, int nsteps, void* stream, int* result_in_b) {
+  if (!gr || !workspace || !fields_a || !fields_b || nsteps < 0) return SL_EINVAL;
+  const int K = gr->desc.reconstruct_every;
+  if (nsteps % K) return SL_EINVAL;
+  if (gr->steps_since_reset != 0) return SL_ESTATE;
+  void* const* cur = fields_a;
+  void* const* nxt = fields_b;
+  int in_b = 0;
+  for (int s = 0; s < nsteps; s += K) {
+    for (int k = 0; k < K; ++k) {
+      const int rc = sl_step(gr, workspace, t0 + (double)(s + k) * dt, dt, stream);
+      if (rc != SL_OK) return rc;
+    }
+    const int rc = sl_reconstruct(gr, workspace, (const void* const*)cur, nxt, stream);
+    if (rc != SL_OK) return rc;
+    void* const* tmp = cur;
+    cur = nxt;
+    nxt = tmp;
+    in_b ^= 1;
+  }
+  if (result_in_b) *result_in_b = in_b;
+  return SL_OK;
+}
+
+int sl_profile_enable(sl_grid* gr, int on) {
+  if (!gr) return SL_EINVAL;
+  gr->prof_on = on != 0;
+  return SL_OK;
+}
+
+int sl_profile_read(sl_grid* gr, sl_profile* out) {
+  if (!gr) return SL_EINVAL;
+  prof_fold(gr);
+  if (out) {
+    out->traj_launches = gr->prof_n[0];
+    out->traj_ms = gr->prof_ms[0];
+    out->recon_launches = gr->prof_n[1];
+    out->recon_ms = gr->prof_ms[1];
+  }
+  gr->prof_n[0] = gr->prof_n[1] = 0;
+  gr->prof_ms[0] = gr->prof_ms[1] = 0.0;
   return SL_OK;
 }
 

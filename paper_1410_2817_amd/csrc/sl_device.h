@@ -5,6 +5,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <limits.h>
 #include <stdint.h>
 
 #include "sl.h"
@@ -192,6 +193,12 @@ __device__ __forceinline__ void zspline_weights(int m, T t, T* w) {
 template <int D>
 struct Element;
 
+// Newton iterations run unconditionally by the fast path.  In a cell whose
+// element is close to a parallelogram (the common case) Newton from the
+// linear root converges in about three; further iterations only add
+// rounding-level corrections.
+constexpr int kFastNewton = 4;
+
 template <>
 struct Element<2> {
   double v0[2], a[2], b[2], c[2];
@@ -236,6 +243,10 @@ struct Element<2> {
     xi[1] = yl;
     return 0;
   }
+
+  // kFastNewton iterations without early exit; true if one of them moved by
+  // at most the tolerance (then xi is the converged root).
+  __device__ __forceinline__ bool solve_fixed(const GridArgs& g, double* xi) const;
 };
 
 template <>
@@ -310,31 +321,79 @@ struct Element<3> {
   }
 };
 
+__device__ __forceinline__ bool Element<2>::solve_fixed(const GridArgs& g, double* xi) const {
+  const double det = a[0] * b[1] - b[0] * a[1];
+  const double inv = 1.0 / det;
+  double x = (-v0[0] * b[1] + b[0] * v0[1]) * inv;
+  double y = (-a[0] * v0[1] + v0[0] * a[1]) * inv;
+  bool conv = false;
+#pragma unroll
+  for (int it = 0; it < kFastNewton; ++it) {
+    const double f0 = v0[0] + a[0] * x + b[0] * y + c[0] * (x * y);
+    const double f1 = v0[1] + a[1] * x + b[1] * y + c[1] * (x * y);
+    const double j00 = a[0] + c[0] * y, j01 = b[0] + c[0] * x;
+    const double j10 = a[1] + c[1] * y, j11 = b[1] + c[1] * x;
+    const double ij = 1.0 / (j00 * j11 - j01 * j10);
+    const double dx = (f0 * j11 - j01 * f1) * ij;
+    const double dy = (j00 * f1 - f0 * j10) * ij;
+    x -= dx;
+    y -= dy;
+    conv = conv || fmax(fabs(dx), fabs(dy)) <= g.newton_tol;
+  }
+  xi[0] = x;
+  xi[1] = y;
+  // A singular or non-finite system leaves NaNs, which fail the cube test.
+  return conv && det != 0.0 && isfinite(x) && isfinite(y);
+}
+
 // Result codes of locate().
 enum { LOC_OK = 0, LOC_SEARCH_FAIL = 1, LOC_NEWTON_FAIL = 2 };
 
-// Element with lower vertex r for target mesh node tgt; `disp(idx, d)` returns
-// the displacement (cells) of the wrapped lattice node idx.
+// Element with lower vertex r for target mesh node tgt; `disp(v, d)` returns
+// the displacement (cells) of the lattice node with unwrapped index v.
 template <int D, class DispFn>
 __device__ __forceinline__ int element_solve(const GridArgs& g, const DispFn& disp,
                                              const int* tgt, const int* r, double* xi) {
   double V[1 << D][D];
 #pragma unroll
   for (int e = 0; e < (1 << D); ++e) {
-    int v[D], w[D];
+    int v[D];
 #pragma unroll
-    for (int a = 0; a < D; ++a) {
-      v[a] = r[a] + ((e >> a) & 1);
-      w[a] = wrap_index(v[a], g.n[a]);
-    }
+    for (int a = 0; a < D; ++a) v[a] = r[a] + ((e >> a) & 1);
     double d[D];
-    disp(w, d);
+    disp(v, d);
 #pragma unroll
     for (int a = 0; a < D; ++a) V[e][a] = (double)(v[a] - tgt[a]) + d[a];
   }
   Element<D> el;
   el.set(V);
   return el.solve(g, xi);
+}
+
+template <int D>
+__device__ __forceinline__ bool in_cube(const GridArgs& g, const double* xi);
+
+// Start-cell attempt with kFastNewton unconditional Newton iterations (no
+// data-dependent branches).  True when Newton converged (some iteration's
+// step was within tolerance) to a point of the unit cube: the same acceptance
+// test locate() applies to its first cell.
+template <int D, class DispFn>
+__device__ __forceinline__ bool element_solve_fast(const GridArgs& g, const DispFn& disp,
+                                                   const int* tgt, const int* r, double* xi) {
+  double V[1 << D][D];
+#pragma unroll
+  for (int e = 0; e < (1 << D); ++e) {
+    int v[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) v[a] = r[a] + ((e >> a) & 1);
+    double d[D];
+    disp(v, d);
+#pragma unroll
+    for (int a = 0; a < D; ++a) V[e][a] = (double)(v[a] - tgt[a]) + d[a];
+  }
+  Element<D> el;
+  el.set(V);
+  return el.solve_fixed(g, xi) && in_cube<D>(g, xi);
 }
 
 template <int D>
@@ -353,16 +412,13 @@ __device__ __forceinline__ bool in_cube(const GridArgs& g, const double* xi) {
 // walk_max moves, the cells of the box of half-width scan_radius around the
 // start cell are tried in order, x fastest.  `walked` reports 0 (start cell),
 // 1 (walked), 2 (fallback scan).
+// d0 is the displacement of the lattice node with the target's own index.
 template <int D, class DispFn>
 __device__ __forceinline__ int locate(const GridArgs& g, const DispFn& disp, const int* tgt,
-                                      int* r, double* xi, int& walked) {
+                                      const double* d0, int* r, double* xi, int& walked) {
   int start[D];
-  {
-    double d0[D];
-    disp(tgt, d0);
 #pragma unroll
-    for (int a = 0; a < D; ++a) start[a] = r[a] = (int)floor((double)tgt[a] - d0[a]);
-  }
+  for (int a = 0; a < D; ++a) start[a] = r[a] = (int)floor((double)tgt[a] - d0[a]);
   walked = 0;
   bool newton_trouble = false;
   for (int walk = 0; walk < g.walk_max; ++walk) {

@@ -1,0 +1,397 @@
+// Tiled 2-D reconstruction kernel for gfx950 (Sec. 2.1-2.3).
+//
+// A workgroup of 256 work-items owns a TX x TY tile of mesh nodes.  It reads
+// the displacement of its own nodes (the start guesses of the element walk),
+// reduces their departure cells to a bounding box, and stages into LDS the
+// lattice displacements of that box (plus a margin for the walk) and the field
+// values of the box grown by one node (the jump criterion needs neighbours).
+// The jump flags of the box are computed once from the staged values and
+// OR-reduced over the quintic and cubic stencil windows by separable passes,
+// so each node reads its order mask with two LDS loads.  Every node then runs
+// the walk + Newton, picks its order per field and evaluates the separable
+// Z-spline sum from LDS.  A node whose walk leaves the staged box (or a tile
+// whose box does not fit in LDS) takes the same arithmetic through global
+// memory, so the result does not depend on the path.
+//
+// Tiles are assigned XCD by XCD: consecutive workgroups are dispatched
+// round-robin over the 8 XCDs, and the mapping below gives each XCD a
+// contiguous run of tiles so that neighbouring halos meet in the same L2.
+#pragma once
+
+#include "sl_device.h"
+
+namespace sl {
+
+constexpr int kTileThreads = 256;
+constexpr int kWalkMargin = 1;   // extra cells staged around the start cells
+constexpr int kNumXcd = 8;
+
+// 16 x 16 tiles, one mesh node per work-item: small LDS boxes and few live
+// registers keep four workgroups resident per CU, which hides the latency of
+// the staging loads behind other workgroups' arithmetic.
+template <typename T>
+struct Tile2D {
+  static constexpr int TX = 16;
+  static constexpr int TY = 16;
+  static constexpr int NPT = TX * TY / kTileThreads;  // nodes per work-item
+  static constexpr int LDS_BYTES = 40 * 1024;
+};
+
+__device__ __forceinline__ int xcd_tile(int b, int nblocks) {
+  const int xcd = b % kNumXcd, local = b / kNumXcd;
+  const int q = nblocks / kNumXcd, rem = nblocks % kNumXcd;
+  return xcd * q + (xcd < rem ? xcd : rem) + local;
+}
+
+// Displacement accessor: LDS box first, global memory outside it.
+struct BoxDisp2D {
+  const double* __restrict__ ldx;
+  const double* __restrict__ ldy;
+  int bx0, by0, BX, BY;
+  const double* __restrict__ gdisp;
+  GridArgs g;
+  __device__ __forceinline__ void operator()(const int* v, double* d) const {
+    const int lx = v[0] - bx0, ly = v[1] - by0;
+    if ((unsigned)lx < (unsigned)BX && (unsigned)ly < (unsigned)BY) {
+      const int i = lx + BX * ly;
+      d[0] = ldx[i];
+      d[1] = ldy[i];
+    } else {
+      const int lin = wrap_index(v[0], g.n[0]) + g.n[0] * wrap_index(v[1], g.n[1]);
+      d[0] = gdisp[lin];
+      d[1] = gdisp[(size_t)g.ntot + lin];
+    }
+  }
+};
+
+// Jump-flag bits (all fields) of the lattice node at wrapped (x, y), from
+// global memory.
+template <typename T>
+__device__ __forceinline__ unsigned global_flag_bits(const GridArgs& g, const FieldPtrs& fp,
+                                                     int x, int y) {
+  const int xm = x == 0 ? g.n[0] - 1 : x - 1, xp = x + 1 == g.n[0] ? 0 : x + 1;
+  const int ym = y == 0 ? g.n[1] - 1 : y - 1, yp = y + 1 == g.n[1] ? 0 : y + 1;
+  unsigned bits = 0;
+  for (int f = 0; f < g.nfields; ++f) {
+    const T* __restrict__ h = static_cast<const T*>(fp.in[f]);
+    const double hc = (double)h[x + g.n[0] * y];
+    const bool fl = jump_flag((double)h[xm + g.n[0] * y], hc, (double)h[xp + g.n[0] * y], g.theta) ||
+                    jump_flag((double)h[x + g.n[0] * ym], hc, (double)h[x + g.n[0] * yp], g.theta);
+    bits |= (fl ? 1u : 0u) << f;
+  }
+  return bits;
+}
+
+// Order of field f from the OR of the flags in its quintic / cubic stencils.
+__device__ __forceinline__ int pick_order(int order_max, unsigned or6, unsigned or4, int f) {
+  int m = order_max;
+  if (m == 2 && ((or6 >> f) & 1u)) m = 1;
+  if (m == 1 && ((or4 >> f) & 1u)) m = 0;
+  return m;
+}
+
+// Wrapped stencil indices and flag masks through global memory, for nodes
+// whose stencil is not in the staged box.
+template <typename T>
+__device__ __forceinline__ void stencil_global(const GridArgs& g, const FieldPtrs& fp,
+                                                         const int* r, bool lim, int* ix,
+                                                         int* iy, unsigned& or6,
+                                                         unsigned& or4) {
+  int wx = wrap_index(r[0] - 2, g.n[0]), wy = wrap_index(r[1] - 2, g.n[1]);
+  for (int s = 0; s < 6; ++s) {
+    ix[s] = wx;
+    iy[s] = wy;
+    wx = wx + 1 == g.n[0] ? 0 : wx + 1;
+    wy = wy + 1 == g.n[1] ? 0 : wy + 1;
+  }
+  or6 = or4 = 0;
+  if (lim) {
+    for (int ky = 0; ky < 6; ++ky)
+      for (int kx = 0; kx < 6; ++kx) {
+        const unsigned fb = global_flag_bits<T>(g, fp, ix[kx], iy[ky]);
+        or6 |= fb;
+        if (kx >= 1 && kx <= 4 && ky >= 1 && ky <= 4) or4 |= fb;
+      }
+  }
+}
+
+// Separable Z-spline sum over the 6x6 stencil; val(kx, ky) returns the value
+// of node (r - 2 + kx, r - 2 + ky).  The same operation order is used on the
+// LDS and the global path.
+template <typename T, class Val>
+__device__ __forceinline__ T zsum2d(const T* wx, const T* wy, const Val& val) {
+  T acc = T(0);
+#pragma unroll 2
+  for (int ky = 0; ky < 6; ++ky) {
+    T s = T(0);
+#pragma unroll
+    for (int kx = 0; kx < 6; ++kx) s = fma(val(kx, ky), wx[kx], s);
+    acc = fma(s, wy[ky], acc);
+  }
+  return acc;
+}
+
+// NF is the number of fields (a compile-time constant so that the per-field
+// loops unroll without exec-mask bookkeeping).
+template <typename T, int NF>
+__global__ __launch_bounds__(kTileThreads) void recon2d_tiled_kernel(
+    GridArgs g, FieldPtrs fp, const double* __restrict__ gdisp,
+    unsigned long long* __restrict__ stats, int tiles_x, int ntiles) {
+  using C = Tile2D<T>;
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int s_box[4];  // min rx, min ry, max rx, max ry
+  __shared__ unsigned s_cnt[ST_COUNT];
+
+  const int tile = xcd_tile(blockIdx.x, ntiles);
+  const int tx0 = (tile % tiles_x) * C::TX, ty0 = (tile / tiles_x) * C::TY;
+  const int lx = threadIdx.x % C::TX, ly0 = threadIdx.x / C::TX;
+  constexpr int ROWS = kTileThreads / C::TX;  // rows covered per pass
+
+  if (threadIdx.x == 0) {
+    s_box[0] = s_box[1] = INT_MAX;
+    s_box[2] = s_box[3] = INT_MIN;
+  }
+  if (threadIdx.x < ST_COUNT) s_cnt[threadIdx.x] = 0u;
+  __syncthreads();
+
+  // 1. Own displacements (start guesses) and the bounding box of start cells.
+  double d0[C::NPT][2];
+  int rs[C::NPT][2];
+  bool act[C::NPT];
+  int mn[2] = {INT_MAX, INT_MAX}, mx[2] = {INT_MIN, INT_MIN};
+#pragma unroll
+  for (int k = 0; k < C::NPT; ++k) {
+    const int x = tx0 + lx, y = ty0 + ly0 + ROWS * k;
+    act[k] = x < g.n[0] && y < g.n[1];
+    d0[k][0] = d0[k][1] = 0.0;
+    rs[k][0] = rs[k][1] = 0;
+    if (act[k]) {
+      const int lin = x + g.n[0] * y;
+      d0[k][0] = gdisp[lin];
+      d0[k][1] = gdisp[(size_t)g.ntot + lin];
+      rs[k][0] = (int)floor((double)x - d0[k][0]);
+      rs[k][1] = (int)floor((double)y - d0[k][1]);
+      mn[0] = min(mn[0], rs[k][0]);
+      mn[1] = min(mn[1], rs[k][1]);
+      mx[0] = max(mx[0], rs[k][0]);
+      mx[1] = max(mx[1], rs[k][1]);
+    }
+  }
+  atomicMin(&s_box[0], mn[0]);
+  atomicMin(&s_box[1], mn[1]);
+  atomicMax(&s_box[2], mx[0]);
+  atomicMax(&s_box[3], mx[1]);
+  __syncthreads();
+
+  // Departure box [bx0, bx0+BX) x [by0, by0+BY): every start cell's quintic
+  // stencil plus the walk margin.  Values are staged one node wider.
+  // Extents are formed in 64-bit and capped so that garbage displacements
+  // (NaN or huge values) can only send the tile down the global path.
+  const long long ex = (long long)s_box[2] - (long long)s_box[0] + 6 + 2 * kWalkMargin;
+  const long long ey = (long long)s_box[3] - (long long)s_box[1] + 6 + 2 * kWalkMargin;
+  const bool sane = ex > 0 && ey > 0 && ex <= 1024 && ey <= 1024;
+  const int bx0 = sane ? s_box[0] - 2 - kWalkMargin : 0;
+  const int by0 = sane ? s_box[1] - 2 - kWalkMargin : 0;
+  const int BX = sane ? (int)ex : 0;
+  const int BY = sane ? (int)ey : 0;
+  const int VX = BX + 2, VY = BY + 2;
+  const int nbox = BX * BY, nval = VX * VY;
+  constexpr int nf = NF;
+  // LDS layout: disp x | disp y | values (nf planes) | flags | row-OR | OR
+  const size_t off_dy = (size_t)nbox * 8;
+  const size_t off_val = off_dy + (size_t)nbox * 8;
+  const size_t off_flag = off_val + (((size_t)nf * nval * sizeof(T) + 15) & ~(size_t)15);
+  const size_t off_row = off_flag + (((size_t)nbox + 15) & ~(size_t)15);
+  const size_t off_or = off_row + (((size_t)nbox * 2 + 15) & ~(size_t)15);
+  const size_t need = off_or + (size_t)nbox * 2;
+  const bool staged = sane && need <= (size_t)C::LDS_BYTES;
+
+  double* ldx = reinterpret_cast<double*>(smem);
+  double* ldy = reinterpret_cast<double*>(smem + off_dy);
+  T* lval = reinterpret_cast<T*>(smem + off_val);
+  unsigned char* lflag = smem + off_flag;
+  unsigned char* lrow = smem + off_row;  // 2 bytes per node: quintic, cubic
+  unsigned char* lor = smem + off_or;
+
+  if (staged) {
+    // 2. Stage displacements and values.  Work-items cover the box as rows of
+    // 32 (one wave = two rows), so no integer division is needed; wrapped
+    // coordinates are advanced incrementally from the box origin.
+    const int sx_lane = threadIdx.x % 32, sy_lane = threadIdx.x / 32;
+    constexpr int SROWS = kTileThreads / 32;
+    const int nx = g.n[0], ny = g.n[1];
+    const int wx0 = wrap_index(bx0 - 1, nx), wy0 = wrap_index(by0 - 1, ny);
+    const bool narrow = VX <= nx && VY <= ny;  // then one wrap suffices
+    for (int vy = sy_lane; vy < VY; vy += SROWS) {
+      int gy = wy0 + vy;
+      if (narrow) {
+        gy = gy >= ny ? gy - ny : gy;
+      } else {
+        while (gy >= ny) gy -= ny;
+      }
+      const size_t row = (size_t)nx * gy;
+      for (int vx = sx_lane; vx < VX; vx += 32) {
+        int gx = wx0 + vx;
+        if (narrow) {
+          gx = gx >= nx ? gx - nx : gx;
+        } else {
+          while (gx >= nx) gx -= nx;
+        }
+        const size_t lin = row + gx;
+        const int vi = vx + VX * vy;
+#pragma unroll
+        for (int f = 0; f < nf; ++f)
+          lval[(size_t)f * nval + vi] = static_cast<const T*>(fp.in[f])[lin];
+        // The displacement box is the value box without its one-node rim.
+        const int bx = vx - 1, by = vy - 1;
+        if (bx >= 0 && by >= 0 && bx < BX && by < BY) {
+          const int i = bx + BX * by;
+          ldx[i] = gdisp[lin];
+          ldy[i] = gdisp[(size_t)g.ntot + lin];
+        }
+      }
+    }
+    __syncthreads();
+    // 3. Jump flags of the box nodes from the staged values.
+    if (g.limiter && g.order_max > 0) {
+      for (int by = sy_lane; by < BY; by += SROWS)
+        for (int bx = sx_lane; bx < BX; bx += 32) {
+          const int c = (bx + 1) + VX * (by + 1);
+          unsigned bits = 0;
+#pragma unroll
+          for (int f = 0; f < nf; ++f) {
+            const T* lv = lval + (size_t)f * nval;
+            const double hc = (double)lv[c];
+            const bool fl = jump_flag((double)lv[c - 1], hc, (double)lv[c + 1], g.theta) ||
+                            jump_flag((double)lv[c - VX], hc, (double)lv[c + VX], g.theta);
+            bits |= (fl ? 1u : 0u) << f;
+          }
+          lflag[bx + BX * by] = (unsigned char)bits;
+        }
+      __syncthreads();
+      // Row pass: OR over x in [bx-2, bx+3] and [bx-1, bx+2].
+      for (int by = sy_lane; by < BY; by += SROWS)
+        for (int bx = sx_lane; bx < BX; bx += 32) {
+          const int i = bx + BX * by;
+          unsigned o6 = 0, o4 = 0;
+          if (bx >= 2 && bx + 3 < BX) {
+#pragma unroll
+            for (int k = -2; k <= 3; ++k) {
+              const unsigned fb = lflag[i + k];
+              o6 |= fb;
+              if (k >= -1 && k <= 2) o4 |= fb;
+            }
+          }
+          lrow[2 * i] = (unsigned char)o6;
+          lrow[2 * i + 1] = (unsigned char)o4;
+        }
+      __syncthreads();
+      // Column pass.
+      for (int by = sy_lane; by < BY; by += SROWS)
+        for (int bx = sx_lane; bx < BX; bx += 32) {
+          const int i = bx + BX * by;
+          unsigned o6 = 0, o4 = 0;
+          if (by >= 2 && by + 3 < BY) {
+#pragma unroll
+            for (int k = -2; k <= 3; ++k) {
+              o6 |= lrow[2 * (i + k * BX)];
+              if (k >= -1 && k <= 2) o4 |= lrow[2 * (i + k * BX) + 1];
+            }
+          }
+          lor[2 * i] = (unsigned char)o6;
+          lor[2 * i + 1] = (unsigned char)o4;
+        }
+    }
+    __syncthreads();
+  }
+
+  const BoxDisp2D acc{ldx, ldy, bx0, by0, staged ? BX : 0, staged ? BY : 0, gdisp, g};
+  int walked_any = 0, scanned_any = 0, sfail = 0, nfail = 0, c0 = 0, c1 = 0, bad = 0;
+
+#pragma unroll 1
+  for (int k = 0; k < C::NPT; ++k) {
+    if (!act[k]) continue;
+    const int x = tx0 + lx, y = ty0 + ly0 + ROWS * k;
+    const int tgt[2] = {x, y};
+    const int lin = x + g.n[0] * y;
+    // Fast path: the start cell with a fixed number of Newton iterations.
+    // Lanes it does not settle run the full walk (the same arithmetic).
+    int r[2] = {rs[k][0], rs[k][1]};
+    double xi[2];
+    int walked = 0;
+    int loc = LOC_OK;
+    if (!element_solve_fast<2>(g, acc, tgt, r, xi)) {
+      loc = locate<2>(g, acc, tgt, d0[k], r, xi, walked);
+    }
+    walked_any += walked != 0;
+    scanned_any += walked == 2;
+    if (loc != LOC_OK) {
+      sfail += loc == LOC_SEARCH_FAIL;
+      nfail += loc == LOC_NEWTON_FAIL;
+#pragma unroll
+      for (int f = 0; f < nf; ++f) static_cast<T*>(fp.out[f])[lin] = T(NAN);
+      continue;
+    }
+    const int sx = r[0] - 2 - bx0, sy = r[1] - 2 - by0;  // stencil origin in box
+    const bool inbox = staged && sx >= 0 && sy >= 0 && sx + 6 <= BX && sy + 6 <= BY;
+    const bool lim = g.limiter && g.order_max > 0;
+    unsigned or6 = 0, or4 = 0;
+    int ix[6], iy[6];
+    if (inbox) {
+      if (lim) {
+        const int c = (sx + 2) + BX * (sy + 2);
+        or6 = lor[2 * c];
+        or4 = lor[2 * c + 1];
+      }
+    } else {
+      stencil_global<T>(g, fp, r, lim, ix, iy, or6, or4);
+    }
+    // Weights of every order the limiter may pick, then a select per field.
+    const T tx = (T)xi[0], ty = (T)xi[1];
+    T w2x[6], w2y[6], w1x[6], w1y[6], w0x[6], w0y[6];
+    zspline_weights<T>(g.order_max, tx, w2x);
+    zspline_weights<T>(g.order_max, ty, w2y);
+    if (lim) {
+      zspline_weights<T>(g.order_max > 1 ? 1 : 0, tx, w1x);
+      zspline_weights<T>(g.order_max > 1 ? 1 : 0, ty, w1y);
+      zspline_weights<T>(0, tx, w0x);
+      zspline_weights<T>(0, ty, w0y);
+    }
+#pragma unroll
+    for (int f = 0; f < nf; ++f) {
+      const int m = pick_order(g.order_max, or6, or4, f);
+      const int drop = g.order_max - m;  // 0, 1 or 2 orders below the top
+      c0 += m == 0;
+      c1 += m == 1;
+      T wx[6], wy[6];
+#pragma unroll
+      for (int q = 0; q < 6; ++q) {
+        wx[q] = drop == 0 ? w2x[q] : (drop == 1 ? w1x[q] : w0x[q]);
+        wy[q] = drop == 0 ? w2y[q] : (drop == 1 ? w1y[q] : w0y[q]);
+      }
+      T v;
+      if (inbox) {
+        const T* lv = lval + (size_t)f * nval + (sx + 1) + VX * (sy + 1);
+        v = zsum2d<T>(wx, wy, [&](int kx, int ky) { return lv[kx + VX * ky]; });
+      } else {
+        const T* __restrict__ h = static_cast<const T*>(fp.in[f]);
+        v = zsum2d<T>(wx, wy, [&](int kx, int ky) { return h[ix[kx] + g.n[0] * iy[ky]]; });
+      }
+      bad += !isfinite(v);
+      static_cast<T*>(fp.out[f])[lin] = v;
+    }
+  }
+  // Counters: summed in LDS, one global atomic per workgroup and counter.
+  if (walked_any) atomicAdd(&s_cnt[ST_WALKED], (unsigned)walked_any);
+  if (scanned_any) atomicAdd(&s_cnt[ST_SCANNED], (unsigned)scanned_any);
+  if (sfail) atomicAdd(&s_cnt[ST_SEARCH_FAIL], (unsigned)sfail);
+  if (nfail) atomicAdd(&s_cnt[ST_NEWTON_FAIL], (unsigned)nfail);
+  if (c0) atomicAdd(&s_cnt[ST_ORDER0], (unsigned)c0);
+  if (c1) atomicAdd(&s_cnt[ST_ORDER1], (unsigned)c1);
+  if (bad) atomicAdd(&s_cnt[ST_NONFINITE], (unsigned)bad);
+  __syncthreads();
+  if (threadIdx.x < ST_COUNT && s_cnt[threadIdx.x])
+    atomicAdd(stats + threadIdx.x, (unsigned long long)s_cnt[threadIdx.x]);
+}
+
+}  // namespace sl

@@ -36,9 +36,9 @@ def B():
 def gpu_run(B, torch, wl, nsteps=1, t0=0.0, kevery=1, **over):
     """Run nsteps GPU steps from wl's stored initial values; returns (fields as
     FP64 numpy, stats, status, grid)."""
-    g = B.Grid.from_workload(wl, **over)
+    g = B.Grid.from_workload(wl, reconstruct_every=kevery, **over)
     fin = g.new_fields(stored_values(wl))
-    out = g.advance(fin, t0, wl.dt, nsteps, kevery=kevery)
+    out = g.advance(fin, t0, wl.dt, nsteps)
     rc, st = g.sync()
     res = [f.double().cpu().numpy() for f in out]
     return res, st, rc, g
@@ -198,6 +198,20 @@ def test_minimum_grid_and_max_fields(B, torch, orc, dim):
     assert st["order_hist"] == ost["order_hist"]
 
 
+def test_box_too_large_for_lds_takes_global_path(B, torch, orc):
+    """Eight FP64 fields do not fit a tile's staging box in LDS: every tile
+    takes the global-memory path, with the same results."""
+    wl = W.swirl_three_fields(64, value_prec="f64")
+    g = np.random.Generator(np.random.PCG64(6))
+    wl.fields = wl.fields + [g.uniform(0, 1, wl.shape) for _ in range(5)]
+    say("8 fields f64")
+    out, st, rc, _ = gpu_run(B, torch, wl, nsteps=2, t0=0.3)
+    want, ost, orc_rc = oracle_run(orc, wl, nsteps=2, t0=0.3)
+    assert rc == 0 and orc_rc == 0
+    for a, b in zip(out, want):
+        assert l1_rel(a, b) <= 1e-12
+
+
 def test_search_failure_is_reported_like_the_oracle(B, torch, orc):
     """A folded lattice (solid-body rotation with a huge step, corners of the
     periodic box) with the fallback scan disabled: the same nodes fail on both
@@ -213,6 +227,28 @@ def test_search_failure_is_reported_like_the_oracle(B, torch, orc):
     assert np.array_equal(np.isnan(out[0]), np.isnan(want[0]))
     ok = ~np.isnan(want[0])
     assert l1_rel(out[0][ok], want[0][ok]) <= 1e-12
+
+
+def test_per_call_path_equals_advance(B, torch):
+    """sl_step / sl_reconstruct called one by one give the same bits as
+    sl_advance, and kernel events do not change results."""
+    wl = W.swirl_three_fields(96, value_prec="f32")
+    a, _, _, _ = gpu_run(B, torch, wl, nsteps=4, t0=0.6)
+    g = B.Grid.from_workload(wl)
+    g.profile(True)
+    x = g.new_fields(stored_values(wl))
+    y = g.new_fields()
+    for s in range(4):
+        g.step(0.6 + s * wl.dt, wl.dt)
+        g.reconstruct(x, y)
+        x, y = y, x
+    prof = g.profile_read()
+    assert prof["recon_launches"] == 4 and prof["traj_launches"] == 4
+    assert prof["recon_ms"] > 0 and prof["traj_ms"] > 0
+    rc, _ = g.sync()
+    assert rc == 0
+    for p, q in zip(a, x):
+        assert np.array_equal(p, q.double().cpu().numpy())
 
 
 def test_repeatable_bitwise(B, torch):
