@@ -488,16 +488,17 @@ hipError_t launch_recon(sl_grid* gr, const sl::FieldPtrs& fp, char* ws, hipStrea
   const double* disp = reinterpret_cast<const double*>(ws + gr->off_disp);
   auto* stats = reinterpret_cast<unsigned long long*>(ws + gr->off_stats);
   if constexpr (D == 2) {
-    using C = sl::Tile2D<T>;
+    // Tile shape does not depend on the field count.
+    using C = sl::Tile2D<T, 1>;
     const int tiles_x = (gr->g.n[0] + C::TX - 1) / C::TX;
     const int tiles_y = (gr->g.n[1] + C::TY - 1) / C::TY;
     const int ntiles = tiles_x * tiles_y;
     const dim3 grid(ntiles), block(sl::kTileThreads);
-    const uint32_t lds = (uint32_t)C::LDS_BYTES;
-#define SL_RECON2D(NF)                                                                       \
-  case NF:                                                                                   \
-    return launch(sl::recon2d_tiled_kernel<T, NF>, grid, block, lds, s, e0, e1, gr->g, fp, \
-                  disp, stats, tiles_x, ntiles);
+#define SL_RECON2D(NF)                                                                    \
+  case NF:                                                                                \
+    return launch(sl::recon2d_tiled_kernel<T, NF>, grid, block,                          \
+                  (uint32_t)sl::Tile2D<T, NF>::LDS_BYTES, s, e0, e1, gr->g, fp, disp, \
+                  stats, tiles_x, ntiles);
     switch (gr->g.nfields) {
       SL_RECON2D(1)
       SL_RECON2D(2)
@@ -507,8 +508,9 @@ hipError_t launch_recon(sl_grid* gr, const sl::FieldPtrs& fp, char* ws, hipStrea
       SL_RECON2D(6)
       SL_RECON2D(7)
       default:
-        return launch(sl::recon2d_tiled_kernel<T, 8>, grid, block, lds, s, e0, e1, gr->g, fp,
-                      disp, stats, tiles_x, ntiles);
+        return launch(sl::recon2d_tiled_kernel<T, 8>, grid, block,
+                      (uint32_t)sl::Tile2D<T, 8>::LDS_BYTES, s, e0, e1, gr->g, fp, disp,
+                      stats, tiles_x, ntiles);
     }
 #undef SL_RECON2D
   } else {

@@ -29,12 +29,20 @@ constexpr int kNumXcd = 8;
 // 16 x 16 tiles, one mesh node per work-item: small LDS boxes and few live
 // registers keep four workgroups resident per CU, which hides the latency of
 // the staging loads behind other workgroups' arithmetic.
-template <typename T>
+template <typename T, int NF>
 struct Tile2D {
   static constexpr int TX = 16;
   static constexpr int TY = 16;
   static constexpr int NPT = TX * TY / kTileThreads;  // nodes per work-item
-  static constexpr int LDS_BYTES = 40 * 1024;
+  // Dynamic LDS sized for a departure box of up to BOX x BOX nodes (the tile,
+  // the quintic stencil, the walk margin and a few cells of spread in the
+  // start cells); larger boxes take the global path.  Keeping the allocation
+  // tight lets up to six workgroups share a CU's 160 KB.
+  static constexpr int BOX = TX + 5 + 2 * kWalkMargin + 3;
+  static constexpr int RAW = BOX * BOX * 16 + (BOX + 2) * (BOX + 2) * NF * (int)sizeof(T) +
+                             BOX * BOX * 5 + 64;
+  static constexpr int CAP = 60 * 1024;  // stay under the 64 KB workgroup limit
+  static constexpr int LDS_BYTES = (RAW + 255) / 256 * 256 < CAP ? (RAW + 255) / 256 * 256 : CAP;
 };
 
 __device__ __forceinline__ int xcd_tile(int b, int nblocks) {
@@ -137,7 +145,7 @@ template <typename T, int NF>
 __global__ __launch_bounds__(kTileThreads) void recon2d_tiled_kernel(
     GridArgs g, FieldPtrs fp, const double* __restrict__ gdisp,
     unsigned long long* __restrict__ stats, int tiles_x, int ntiles) {
-  using C = Tile2D<T>;
+  using C = Tile2D<T, NF>;
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int s_box[4];  // min rx, min ry, max rx, max ry
   __shared__ unsigned s_cnt[ST_COUNT];
@@ -177,10 +185,17 @@ __global__ __launch_bounds__(kTileThreads) void recon2d_tiled_kernel(
       mx[1] = max(mx[1], rs[k][1]);
     }
   }
-  atomicMin(&s_box[0], mn[0]);
-  atomicMin(&s_box[1], mn[1]);
-  atomicMax(&s_box[2], mx[0]);
-  atomicMax(&s_box[3], mx[1]);
+  // Wave reductions first: LDS atomics from every lane would be serialised.
+  mn[0] = wave_min(mn[0]);
+  mn[1] = wave_min(mn[1]);
+  mx[0] = wave_max(mx[0]);
+  mx[1] = wave_max(mx[1]);
+  if (__lane_id() == 0) {
+    atomicMin(&s_box[0], mn[0]);
+    atomicMin(&s_box[1], mn[1]);
+    atomicMax(&s_box[2], mx[0]);
+    atomicMax(&s_box[3], mx[1]);
+  }
   __syncthreads();
 
   // Departure box [bx0, bx0+BX) x [by0, by0+BY): every start cell's quintic
@@ -382,13 +397,21 @@ __global__ __launch_bounds__(kTileThreads) void recon2d_tiled_kernel(
     }
   }
   // Counters: summed in LDS, one global atomic per workgroup and counter.
-  if (walked_any) atomicAdd(&s_cnt[ST_WALKED], (unsigned)walked_any);
-  if (scanned_any) atomicAdd(&s_cnt[ST_SCANNED], (unsigned)scanned_any);
-  if (sfail) atomicAdd(&s_cnt[ST_SEARCH_FAIL], (unsigned)sfail);
-  if (nfail) atomicAdd(&s_cnt[ST_NEWTON_FAIL], (unsigned)nfail);
-  if (c0) atomicAdd(&s_cnt[ST_ORDER0], (unsigned)c0);
-  if (c1) atomicAdd(&s_cnt[ST_ORDER1], (unsigned)c1);
-  if (bad) atomicAdd(&s_cnt[ST_NONFINITE], (unsigned)bad);
+  // Per-wave sums of pairs packed 16 + 16 bits (a wave's count of any of them
+  // is at most 64 * 8), then one LDS atomic per wave.
+  const unsigned p0 = wave_sum((unsigned)walked_any | ((unsigned)scanned_any << 16));
+  const unsigned p1 = wave_sum((unsigned)sfail | ((unsigned)nfail << 16));
+  const unsigned p2 = wave_sum((unsigned)c0 | ((unsigned)c1 << 16));
+  const unsigned p3 = wave_sum((unsigned)bad);
+  if (__lane_id() == 0) {
+    if (p0 & 0xffffu) atomicAdd(&s_cnt[ST_WALKED], p0 & 0xffffu);
+    if (p0 >> 16) atomicAdd(&s_cnt[ST_SCANNED], p0 >> 16);
+    if (p1 & 0xffffu) atomicAdd(&s_cnt[ST_SEARCH_FAIL], p1 & 0xffffu);
+    if (p1 >> 16) atomicAdd(&s_cnt[ST_NEWTON_FAIL], p1 >> 16);
+    if (p2 & 0xffffu) atomicAdd(&s_cnt[ST_ORDER0], p2 & 0xffffu);
+    if (p2 >> 16) atomicAdd(&s_cnt[ST_ORDER1], p2 >> 16);
+    if (p3) atomicAdd(&s_cnt[ST_NONFINITE], p3);
+  }
   __syncthreads();
   if (threadIdx.x < ST_COUNT && s_cnt[threadIdx.x])
     atomicAdd(stats + threadIdx.x, (unsigned long long)s_cnt[threadIdx.x]);
