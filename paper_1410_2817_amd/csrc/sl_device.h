@@ -150,43 +150,38 @@ __device__ __forceinline__ void velocity(const VelArgs& v, const double* x, doub
 // ---------------------------------------------------------------------------
 // Cardinal Z-spline weights (Appendix).  For a point r + t, slot s = k + 2
 // holds the weight Z_m(t - k) of node r + k, k = -2..3; slots outside the
-// order-m stencil are zero.  The factored forms below are those polynomials
-// with their roots at the knots pulled out, so t = 0 gives exactly the
-// unit weight on slot 2 and zeros elsewhere.
+// order-m stencil are zero.
 
 template <typename T>
 __device__ __forceinline__ void zspline_weights(int m, T t, T* w) {
-  // The 1/12 and 1/24 factors are folded into the coefficients; the only
-  // non-zero weight at t = 0 has constant term exactly 1.
+  // Each weight is its degree-(2m+1) polynomial in t in Horner form, with the
+  // Appendix's rational coefficients; every weight but the node's own has no
+  // constant term, so t = 0 gives exactly the unit weight on slot 2.
   const T one = T(1);
-  const T u = t - one;  // t - 1
+  const T t2 = t * t;
   if (m == 2) {
-    const T t2 = t * t;
     // Z2(t + 2) = -t (t-1)^3 (5t + 2) / 24
-    w[0] = t * (u * u * u) * (T(-5.0 / 24.0) * t - T(2.0 / 24.0));
+    w[0] = t * (T(1.0 / 12) + t * (T(-1.0 / 24) + t * (T(-3.0 / 8) + t * (T(13.0 / 24) + t * T(-5.0 / 24)))));
     // Z2(t + 1) = t (t-1) (25t^3 - 39t^2 + 16) / 24
-    w[1] = t * u * ((T(25.0 / 24.0) * t - T(39.0 / 24.0)) * t2 + T(16.0 / 24.0));
+    w[1] = t * (T(-2.0 / 3) + t * (T(2.0 / 3) + t * (T(13.0 / 8) + t * (T(-8.0 / 3) + t * T(25.0 / 24)))));
     // Z2(t) = -(t-1) (25t^4 - 38t^3 - 3t^2 + 12t + 12) / 12
-    w[2] = -u * ((((T(25.0 / 12.0) * t - T(38.0 / 12.0)) * t - T(3.0 / 12.0)) * t + one) * t +
-                 one);
+    w[2] = one + t2 * (T(-5.0 / 4) + t * (T(-35.0 / 12) + t * (T(21.0 / 4) + t * T(-25.0 / 12))));
     // Z2(1 - t) = t (25t^4 - 62t^3 + 33t^2 + 8t + 8) / 12
-    w[3] = t * ((((T(25.0 / 12.0) * t - T(62.0 / 12.0)) * t + T(33.0 / 12.0)) * t +
-                 T(8.0 / 12.0)) * t + T(8.0 / 12.0));
+    w[3] = t * (T(2.0 / 3) + t * (T(2.0 / 3) + t * (T(11.0 / 4) + t * (T(-31.0 / 6) + t * T(25.0 / 12)))));
     // Z2(2 - t) = -t (t-1) (25t^3 - 36t^2 - 3t - 2) / 24
-    w[4] = -t * u * (((T(25.0 / 24.0) * t - T(36.0 / 24.0)) * t - T(3.0 / 24.0)) * t -
-                     T(2.0 / 24.0));
+    w[4] = t * (T(-1.0 / 12) + t * (T(-1.0 / 24) + t * (T(-11.0 / 8) + t * (T(61.0 / 24) + t * T(-25.0 / 24)))));
     // Z2(3 - t) = t^3 (t-1) (5t - 7) / 24
-    w[5] = t2 * t * u * (T(5.0 / 24.0) * t - T(7.0 / 24.0));
+    w[5] = t2 * t * (T(7.0 / 24) + t * (T(-1.0 / 2) + t * T(5.0 / 24)));
   } else if (m == 1) {
     w[0] = T(0);
     // Z1(t + 1) = -t (t-1)^2 / 2
-    w[1] = -t * u * u * T(0.5);
+    w[1] = t * (T(-0.5) + t * (one + t * T(-0.5)));
     // Z1(t) = (t-1) (3t^2 - 2t - 2) / 2
-    w[2] = u * ((T(3) * t - T(2)) * t - T(2)) * T(0.5);
+    w[2] = one + t2 * (T(-2.5) + t * T(1.5));
     // Z1(1 - t) = -t (3t^2 - 4t - 1) / 2
-    w[3] = -t * ((T(3) * t - T(4)) * t - one) * T(0.5);
+    w[3] = t * (T(0.5) + t * (T(2) + t * T(-1.5)));
     // Z1(2 - t) = t^2 (t-1) / 2
-    w[4] = t * t * u * T(0.5);
+    w[4] = t2 * (T(-0.5) + t * T(0.5));
     w[5] = T(0);
   } else {
     w[0] = T(0);
@@ -216,7 +211,7 @@ struct Element;
 // element is close to a parallelogram (the common case) Newton from the
 // linear root converges in about three; further iterations only add
 // rounding-level corrections.
-constexpr int kFastNewton = 4;
+constexpr int kFastNewton = 3;
 
 template <>
 struct Element<2> {
@@ -263,8 +258,9 @@ struct Element<2> {
     return 0;
   }
 
-  // kFastNewton iterations without early exit; true if one of them moved by
-  // at most the tolerance (then xi is the converged root).
+  // kFastNewton iterations without early exit, then more while any lane of
+  // the wave is unconverged; true if one of them moved by at most the
+  // tolerance (then xi is the converged root).
   __device__ __forceinline__ bool solve_fixed(const GridArgs& g, double* xi) const;
 };
 
@@ -340,25 +336,39 @@ struct Element<3> {
   }
 };
 
+// Reciprocal for the fixed-iteration Newton path: the hardware estimate
+// refined by one Newton-Raphson step (exact for powers of two; any residual
+// error is absorbed by the next Newton iteration).  A zero argument yields a
+// NaN, which fails the acceptance test.
+__device__ __forceinline__ double rcp_refined(double d) {
+  const double r = __builtin_amdgcn_rcp(d);
+  return fma(r, fma(-d, r, 1.0), r);
+}
+
 __device__ __forceinline__ bool Element<2>::solve_fixed(const GridArgs& g, double* xi) const {
   const double det = a[0] * b[1] - b[0] * a[1];
-  const double inv = 1.0 / det;
+  const double inv = rcp_refined(det);
   double x = (-v0[0] * b[1] + b[0] * v0[1]) * inv;
   double y = (-a[0] * v0[1] + v0[0] * a[1]) * inv;
   bool conv = false;
-#pragma unroll
-  for (int it = 0; it < kFastNewton; ++it) {
+  auto iterate = [&]() {
     const double f0 = v0[0] + a[0] * x + b[0] * y + c[0] * (x * y);
     const double f1 = v0[1] + a[1] * x + b[1] * y + c[1] * (x * y);
     const double j00 = a[0] + c[0] * y, j01 = b[0] + c[0] * x;
     const double j10 = a[1] + c[1] * y, j11 = b[1] + c[1] * x;
-    const double ij = 1.0 / (j00 * j11 - j01 * j10);
+    const double ij = rcp_refined(j00 * j11 - j01 * j10);
     const double dx = (f0 * j11 - j01 * f1) * ij;
     const double dy = (j00 * f1 - f0 * j10) * ij;
     x -= dx;
     y -= dy;
     conv = conv || fmax(fabs(dx), fabs(dy)) <= g.newton_tol;
-  }
+  };
+#pragma unroll
+  for (int it = 0; it < kFastNewton; ++it) iterate();
+  // Continue while any lane of the wave has not converged (a wave-uniform
+  // loop; lanes that have converged only pick up rounding-level steps).
+  for (int it = kFastNewton; it < g.newton_max_iter && __ballot(!conv) != 0ull; ++it)
+    iterate();
   xi[0] = x;
   xi[1] = y;
   // A singular or non-finite system leaves NaNs, which fail the cube test.

@@ -18,6 +18,8 @@
 // contiguous run of tiles so that neighbouring halos meet in the same L2.
 #pragma once
 
+#include <type_traits>
+
 #include "sl_device.h"
 
 namespace sl {
@@ -25,6 +27,12 @@ namespace sl {
 constexpr int kTileThreads = 256;
 constexpr int kWalkMargin = 1;   // extra cells staged around the start cells
 constexpr int kNumXcd = 8;
+#ifndef SL_STAGE_DISP
+#define SL_STAGE_DISP 0
+#endif
+// Stage the departure box's displacements in LDS (1) or let the element
+// solves read them through the caches (0).
+constexpr bool kStageDisp = SL_STAGE_DISP;
 
 // 16 x 16 tiles, one mesh node per work-item: small LDS boxes and few live
 // registers keep four workgroups resident per CU, which hides the latency of
@@ -37,10 +45,10 @@ struct Tile2D {
   // Dynamic LDS sized for a departure box of up to BOX x BOX nodes (the tile,
   // the quintic stencil, the walk margin and a few cells of spread in the
   // start cells); larger boxes take the global path.  Keeping the allocation
-  // tight lets up to six workgroups share a CU's 160 KB.
+  // tight lets many workgroups share a CU's 160 KB.
   static constexpr int BOX = TX + 5 + 2 * kWalkMargin + 3;
-  static constexpr int RAW = BOX * BOX * 16 + (BOX + 2) * (BOX + 2) * NF * (int)sizeof(T) +
-                             BOX * BOX * 5 + 64;
+  static constexpr int RAW = (kStageDisp ? BOX * BOX * 16 : 0) +
+                             (BOX + 2) * (BOX + 2) * NF * (int)sizeof(T) + NF * BOX * 4 + 64;
   static constexpr int CAP = 60 * 1024;  // stay under the 64 KB workgroup limit
   static constexpr int LDS_BYTES = (RAW + 255) / 256 * 256 < CAP ? (RAW + 255) / 256 * 256 : CAP;
 };
@@ -71,6 +79,38 @@ struct BoxDisp2D {
     }
   }
 };
+
+// Wrap an index known to lie near [0, n) without integer division; far
+// indices (only from pathological walks) take the general path.
+__device__ __forceinline__ int wrap_near(int v, int n) {
+  v = v < 0 ? v + n : v;
+  v = v >= n ? v - n : v;
+  return (unsigned)v < (unsigned)n ? v : wrap_index(v, n);
+}
+
+// Displacement accessor reading global memory (through L1/L2).
+struct NearDisp2D {
+  const double* __restrict__ gdisp;
+  GridArgs g;
+  __device__ __forceinline__ void operator()(const int* v, double* d) const {
+    const int lin = wrap_near(v[0], g.n[0]) + g.n[0] * wrap_near(v[1], g.n[1]);
+    d[0] = gdisp[lin];
+    d[1] = gdisp[(size_t)g.ntot + lin];
+  }
+};
+
+__device__ __forceinline__ BoxDisp2D make_disp_accessor(std::true_type, const double* ldx,
+                                                        const double* ldy, int bx0, int by0,
+                                                        int BX, int BY, const double* gdisp,
+                                                        const GridArgs& g) {
+  return BoxDisp2D{ldx, ldy, bx0, by0, BX, BY, gdisp, g};
+}
+
+__device__ __forceinline__ NearDisp2D make_disp_accessor(std::false_type, const double*,
+                                                         const double*, int, int, int, int,
+                                                         const double* gdisp, const GridArgs& g) {
+  return NearDisp2D{gdisp, g};
+}
 
 // Jump-flag bits (all fields) of the lattice node at wrapped (x, y), from
 // global memory.
@@ -213,20 +253,18 @@ __global__ __launch_bounds__(kTileThreads) void recon2d_tiled_kernel(
   const int nbox = BX * BY, nval = VX * VY;
   constexpr int nf = NF;
   // LDS layout: disp x | disp y | values (nf planes) | flags | row-OR | OR
-  const size_t off_dy = (size_t)nbox * 8;
-  const size_t off_val = off_dy + (size_t)nbox * 8;
-  const size_t off_flag = off_val + (((size_t)nf * nval * sizeof(T) + 15) & ~(size_t)15);
-  const size_t off_row = off_flag + (((size_t)nbox + 15) & ~(size_t)15);
-  const size_t off_or = off_row + (((size_t)nbox * 2 + 15) & ~(size_t)15);
-  const size_t need = off_or + (size_t)nbox * 2;
-  const bool staged = sane && need <= (size_t)C::LDS_BYTES;
+  const size_t off_dy = kStageDisp ? (size_t)nbox * 8 : 0;
+  const size_t off_val = kStageDisp ? off_dy + (size_t)nbox * 8 : 0;
+  // Jump flags are kept as one 32-bit word per field and box row (bit x set
+  // when node (x, row) is flagged), so the box may be at most 32 wide.
+  const size_t off_bits = off_val + (((size_t)nf * nval * sizeof(T) + 15) & ~(size_t)15);
+  const size_t need = off_bits + (size_t)nf * BY * 4;
+  const bool staged = sane && BX <= 32 && need <= (size_t)C::LDS_BYTES;
 
   double* ldx = reinterpret_cast<double*>(smem);
   double* ldy = reinterpret_cast<double*>(smem + off_dy);
   T* lval = reinterpret_cast<T*>(smem + off_val);
-  unsigned char* lflag = smem + off_flag;
-  unsigned char* lrow = smem + off_row;  // 2 bytes per node: quintic, cubic
-  unsigned char* lor = smem + off_or;
+  unsigned* lbits = reinterpret_cast<unsigned*>(smem + off_bits);  // [f][row]
 
   if (staged) {
     // 2. Stage displacements and values.  Work-items cover the box as rows of
@@ -259,7 +297,7 @@ __global__ __launch_bounds__(kTileThreads) void recon2d_tiled_kernel(
           lval[(size_t)f * nval + vi] = static_cast<const T*>(fp.in[f])[lin];
         // The displacement box is the value box without its one-node rim.
         const int bx = vx - 1, by = vy - 1;
-        if (bx >= 0 && by >= 0 && bx < BX && by < BY) {
+        if (kStageDisp && bx >= 0 && by >= 0 && bx < BX && by < BY) {
           const int i = bx + BX * by;
           ldx[i] = gdisp[lin];
           ldy[i] = gdisp[(size_t)g.ntot + lin];
@@ -267,60 +305,41 @@ __global__ __launch_bounds__(kTileThreads) void recon2d_tiled_kernel(
       }
     }
     __syncthreads();
-    // 3. Jump flags of the box nodes from the staged values.
+    // 3. Jump flags of the box nodes from the staged values.  Each wave takes
+    // two box rows at a time (lanes 0-31 the first, 32-63 the second, lane =
+    // x), evaluates the criterion in FP64 and packs the flags of each field
+    // into row words with one ballot.
     if (g.limiter && g.order_max > 0) {
-      for (int by = sy_lane; by < BY; by += SROWS)
-        for (int bx = sx_lane; bx < BX; bx += 32) {
-          const int c = (bx + 1) + VX * (by + 1);
-          unsigned bits = 0;
+      const int lane = __lane_id(), wave = threadIdx.x / 64;
+      const int bx = lane & 31;
+      for (int by2 = 2 * wave; by2 < BY; by2 += 2 * (kTileThreads / 64)) {
+        const int by = by2 + (lane >> 5);
+        const bool in = bx < BX && by < BY;
+        const int c = (bx + 1) + VX * (by + 1);
 #pragma unroll
-          for (int f = 0; f < nf; ++f) {
-            const T* lv = lval + (size_t)f * nval;
+        for (int f = 0; f < nf; ++f) {
+          const T* lv = lval + (size_t)f * nval;
+          // FP64 issues at the FP32 (non-packed) rate on CDNA4, so the exact
+          // criterion on the stored values costs no more than a screen.
+          bool fx = false, fy = false;
+          if (in) {
             const double hc = (double)lv[c];
-            const bool fl = jump_flag((double)lv[c - 1], hc, (double)lv[c + 1], g.theta) ||
-                            jump_flag((double)lv[c - VX], hc, (double)lv[c + VX], g.theta);
-            bits |= (fl ? 1u : 0u) << f;
+            fx = jump_flag((double)lv[c - 1], hc, (double)lv[c + 1], g.theta);
+            fy = jump_flag((double)lv[c - VX], hc, (double)lv[c + VX], g.theta);
           }
-          lflag[bx + BX * by] = (unsigned char)bits;
-        }
-      __syncthreads();
-      // Row pass: OR over x in [bx-2, bx+3] and [bx-1, bx+2].
-      for (int by = sy_lane; by < BY; by += SROWS)
-        for (int bx = sx_lane; bx < BX; bx += 32) {
-          const int i = bx + BX * by;
-          unsigned o6 = 0, o4 = 0;
-          if (bx >= 2 && bx + 3 < BX) {
-#pragma unroll
-            for (int k = -2; k <= 3; ++k) {
-              const unsigned fb = lflag[i + k];
-              o6 |= fb;
-              if (k >= -1 && k <= 2) o4 |= fb;
-            }
+          const unsigned long long m = __ballot(in && (fx || fy));
+          if (lane == 0) {
+            lbits[f * BY + by2] = (unsigned)m;
+            if (by2 + 1 < BY) lbits[f * BY + by2 + 1] = (unsigned)(m >> 32);
           }
-          lrow[2 * i] = (unsigned char)o6;
-          lrow[2 * i + 1] = (unsigned char)o4;
         }
-      __syncthreads();
-      // Column pass.
-      for (int by = sy_lane; by < BY; by += SROWS)
-        for (int bx = sx_lane; bx < BX; bx += 32) {
-          const int i = bx + BX * by;
-          unsigned o6 = 0, o4 = 0;
-          if (by >= 2 && by + 3 < BY) {
-#pragma unroll
-            for (int k = -2; k <= 3; ++k) {
-              o6 |= lrow[2 * (i + k * BX)];
-              if (k >= -1 && k <= 2) o4 |= lrow[2 * (i + k * BX) + 1];
-            }
-          }
-          lor[2 * i] = (unsigned char)o6;
-          lor[2 * i + 1] = (unsigned char)o4;
-        }
+      }
     }
     __syncthreads();
   }
 
-  const BoxDisp2D acc{ldx, ldy, bx0, by0, staged ? BX : 0, staged ? BY : 0, gdisp, g};
+  const auto acc = make_disp_accessor(std::integral_constant<bool, kStageDisp>{}, ldx, ldy, bx0,
+                                      by0, staged ? BX : 0, staged ? BY : 0, gdisp, g);
   int walked_any = 0, scanned_any = 0, sfail = 0, nfail = 0, c0 = 0, c1 = 0, bad = 0;
 
 #pragma unroll 1
@@ -354,36 +373,32 @@ __global__ __launch_bounds__(kTileThreads) void recon2d_tiled_kernel(
     int ix[6], iy[6];
     if (inbox) {
       if (lim) {
-        const int c = (sx + 2) + BX * (sy + 2);
-        or6 = lor[2 * c];
-        or4 = lor[2 * c + 1];
+#pragma unroll
+        for (int f = 0; f < nf; ++f) {
+          const unsigned* rb = lbits + f * BY + sy;
+          unsigned w6 = 0, w4 = 0;
+#pragma unroll
+          for (int q = 0; q < 6; ++q) {
+            const unsigned row = rb[q] >> sx;  // bit j: node (sx + j, sy + q)
+            w6 |= row & 0x3fu;
+            if (q >= 1 && q <= 4) w4 |= row & 0x1eu;
+          }
+          or6 |= (w6 != 0u ? 1u : 0u) << f;
+          or4 |= (w4 != 0u ? 1u : 0u) << f;
+        }
       }
     } else {
       stencil_global<T>(g, fp, r, lim, ix, iy, or6, or4);
     }
-    // Weights of every order the limiter may pick, then a select per field.
+    // Weights of the top order; the lower orders and the per-field select
+    // only run when some lane of the wave needs them (a wave-uniform branch).
     const T tx = (T)xi[0], ty = (T)xi[1];
-    T w2x[6], w2y[6], w1x[6], w1y[6], w0x[6], w0y[6];
+    T w2x[6], w2y[6];
     zspline_weights<T>(g.order_max, tx, w2x);
     zspline_weights<T>(g.order_max, ty, w2y);
-    if (lim) {
-      zspline_weights<T>(g.order_max > 1 ? 1 : 0, tx, w1x);
-      zspline_weights<T>(g.order_max > 1 ? 1 : 0, ty, w1y);
-      zspline_weights<T>(0, tx, w0x);
-      zspline_weights<T>(0, ty, w0y);
-    }
-#pragma unroll
-    for (int f = 0; f < nf; ++f) {
-      const int m = pick_order(g.order_max, or6, or4, f);
-      const int drop = g.order_max - m;  // 0, 1 or 2 orders below the top
-      c0 += m == 0;
-      c1 += m == 1;
-      T wx[6], wy[6];
-#pragma unroll
-      for (int q = 0; q < 6; ++q) {
-        wx[q] = drop == 0 ? w2x[q] : (drop == 1 ? w1x[q] : w0x[q]);
-        wy[q] = drop == 0 ? w2y[q] : (drop == 1 ? w1y[q] : w0y[q]);
-      }
+    const unsigned fmask = nf >= 32 ? 0xffffffffu : ((1u << nf) - 1u);
+    const bool low = lim && (((or6 | or4) & fmask) != 0u);
+    auto field_value = [&](int f, const T* wx, const T* wy) {
       T v;
       if (inbox) {
         const T* lv = lval + (size_t)f * nval + (sx + 1) + VX * (sy + 1);
@@ -394,6 +409,30 @@ __global__ __launch_bounds__(kTileThreads) void recon2d_tiled_kernel(
       }
       bad += !isfinite(v);
       static_cast<T*>(fp.out[f])[lin] = v;
+    };
+    if (__ballot(low) == 0ull) {
+#pragma unroll
+      for (int f = 0; f < nf; ++f) field_value(f, w2x, w2y);
+    } else {
+      T w1x[6], w1y[6], w0x[6], w0y[6];
+      zspline_weights<T>(g.order_max > 1 ? 1 : 0, tx, w1x);
+      zspline_weights<T>(g.order_max > 1 ? 1 : 0, ty, w1y);
+      zspline_weights<T>(0, tx, w0x);
+      zspline_weights<T>(0, ty, w0y);
+#pragma unroll
+      for (int f = 0; f < nf; ++f) {
+        const int m = pick_order(g.order_max, or6, or4, f);
+        const int drop = g.order_max - m;  // 0, 1 or 2 orders below the top
+        c0 += m == 0;
+        c1 += m == 1;
+        T wx[6], wy[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+          wx[q] = drop == 0 ? w2x[q] : (drop == 1 ? w1x[q] : w0x[q]);
+          wy[q] = drop == 0 ? w2y[q] : (drop == 1 ? w1y[q] : w0y[q]);
+        }
+        field_value(f, wx, wy);
+      }
     }
   }
   // Counters: summed in LDS, one global atomic per workgroup and counter.

@@ -229,6 +229,39 @@ def test_search_failure_is_reported_like_the_oracle(B, torch, orc):
     assert l1_rel(out[0][ok], want[0][ok]) <= 1e-12
 
 
+@pytest.mark.parametrize("theta", [0.25, 0.1])
+def test_jump_flags_at_ties_fp32(B, torch, orc, theta):
+    """FP32 fields built so that the jump criterion sits at or within a few
+    ulps of its threshold at most nodes: the GPU's screened FP32 evaluation
+    must take exactly the oracle's FP64 decision everywhere (same orders,
+    same values)."""
+    g = np.random.Generator(np.random.PCG64(12))
+    n = 64
+    # Along x, triples (a, 0, c) with c - 2*0 + a = theta * max(|c|, |a|)
+    # exactly in reals, then nudged by -2..2 ulps.
+    # Constant along y, so only the x test can fire at the middle nodes.
+    c = g.uniform(0.5, 2.0, n).astype(np.float32)
+    a = (np.float32(theta) * c - c).astype(np.float32)
+    row = np.zeros(n, np.float32)
+    row[0::3] = a[0::3]
+    row[2::3] = c[2::3]
+    ulps = g.integers(-2, 3, n).astype(np.int32)
+    row = (row.view(np.int32) + np.where(row != 0, ulps, 0)).view(np.float32)
+    f = np.tile(row, (n, 1))
+    f2 = np.ascontiguousarray(f.T)
+    wl = W.uniform_translation((n, n), [0.37 / n, -0.21 / n], 1.0,
+                               [f.astype(np.float64), f2.astype(np.float64)],
+                               limiter=True, value_prec="f32")
+    wl.theta = theta
+    say("ties", theta)
+    out, st, rc, _ = gpu_run(B, torch, wl)
+    want, ost, orc_rc = oracle_run(orc, wl)
+    assert rc == 0 and orc_rc == 0
+    assert st["order_hist"] == ost["order_hist"]
+    for a_, b_ in zip(out, want):
+        assert np.abs(a_ - b_).max() <= 1e-5 * np.abs(b_).max()
+
+
 def test_per_call_path_equals_advance(B, torch):
     """sl_step / sl_reconstruct called one by one give the same bits as
     sl_advance, and kernel events do not change results."""
