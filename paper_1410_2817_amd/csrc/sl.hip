@@ -53,13 +53,11 @@ __device__ __forceinline__ int flatten(const GridArgs& g, const int* w) {
 // ---------------------------------------------------------------------------
 // Trajectories (Sec. 2, eq. "vel").
 
-template <int VK>
-__device__ __forceinline__ double time_factor(const VelArgs& v, double t) {
-  if constexpr (VK == SL_VEL_SWIRL2D || VK == SL_VEL_DEFORM3D)
-    return cospi(t / v.p[0]);
-  else
-    return 1.0;
-}
+// Time factors cos(pi t_s / p0) of the periodic families at the stage times,
+// computed on the host (1 for the steady families).
+struct StageTimes {
+  double tf[4];
+};
 
 // Launched on a (ceil(nx/64), ceil(ny/4), nz) grid of 64 x 4 work-items, so
 // node coordinates come without integer division.
@@ -67,7 +65,7 @@ constexpr int kTrajBX = 64, kTrajBY = 4;
 
 template <int D, int VK>
 __global__ __launch_bounds__(kBlock) void traj_kernel(GridArgs g, VelArgs v,
-                                                      double* __restrict__ disp, double t,
+                                                      double* __restrict__ disp, StageTimes st,
                                                       double dt, int accumulate,
                                                       int integrator) {
   int idx[D];
@@ -82,19 +80,20 @@ __global__ __launch_bounds__(kBlock) void traj_kernel(GridArgs g, VelArgs v,
     d[a] = accumulate ? disp[(size_t)a * g.ntot + lin] : 0.0;
     x[a] = ((double)idx[a] + d[a]) * g.h[a];
   }
+  NodeVelocity<VK, D> vel;
+  vel.init(x);
   if (integrator == SL_RK4) {
-    double k1[D], k2[D], k3[D], k4[D], y[D];
-    velocity<VK, D>(v, x, time_factor<VK>(v, t), k1);
+    double k1[D], k2[D], k3[D], k4[D], o[D];
+    vel.eval(v, x, nullptr, st.tf[0], k1);
 #pragma unroll
-    for (int a = 0; a < D; ++a) y[a] = x[a] + 0.5 * dt * k1[a];
-    const double tf_half = time_factor<VK>(v, t + 0.5 * dt);
-    velocity<VK, D>(v, y, tf_half, k2);
+    for (int a = 0; a < D; ++a) o[a] = 0.5 * dt * k1[a];
+    vel.eval(v, x, o, st.tf[1], k2);
 #pragma unroll
-    for (int a = 0; a < D; ++a) y[a] = x[a] + 0.5 * dt * k2[a];
-    velocity<VK, D>(v, y, tf_half, k3);
+    for (int a = 0; a < D; ++a) o[a] = 0.5 * dt * k2[a];
+    vel.eval(v, x, o, st.tf[1], k3);
 #pragma unroll
-    for (int a = 0; a < D; ++a) y[a] = x[a] + dt * k3[a];
-    velocity<VK, D>(v, y, time_factor<VK>(v, t + dt), k4);
+    for (int a = 0; a < D; ++a) o[a] = dt * k3[a];
+    vel.eval(v, x, o, st.tf[2], k4);
 #pragma unroll
     for (int a = 0; a < D; ++a)
       d[a] += dt * (k1[a] + 2.0 * k2[a] + 2.0 * k3[a] + k4[a]) / 6.0 / g.h[a];
@@ -104,15 +103,12 @@ __global__ __launch_bounds__(kBlock) void traj_kernel(GridArgs g, VelArgs v,
     // c = (0, 1/3, 3/4).
     const double A[3] = {0.0, -5.0 / 9.0, -153.0 / 128.0};
     const double B[3] = {1.0 / 3.0, 15.0 / 16.0, 8.0 / 15.0};
-    const double C[3] = {0.0, 1.0 / 3.0, 3.0 / 4.0};
-    double q[D], dx[D], y[D], u[D];
+    double q[D], dx[D], u[D];
 #pragma unroll
     for (int a = 0; a < D; ++a) q[a] = dx[a] = 0.0;
 #pragma unroll
     for (int s = 0; s < 3; ++s) {
-#pragma unroll
-      for (int a = 0; a < D; ++a) y[a] = x[a] + dx[a];
-      velocity<VK, D>(v, y, time_factor<VK>(v, t + C[s] * dt), u);
+      vel.eval(v, x, s == 0 ? nullptr : dx, st.tf[s], u);
 #pragma unroll
       for (int a = 0; a < D; ++a) {
         q[a] = A[s] * q[a] + dt * u[a];
@@ -463,6 +459,13 @@ void clear_stale_error() { (void)hipGetLastError(); }
 template <int D>
 hipError_t launch_traj(sl_grid* gr, double* disp, double t, double dt, int accumulate,
                        hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  sl::StageTimes st;
+  {
+    const bool periodic = gr->v.kind == SL_VEL_SWIRL2D || gr->v.kind == SL_VEL_DEFORM3D;
+    const double ts[4] = {t, gr->desc.integrator == SL_RK4 ? t + 0.5 * dt : t + dt / 3.0,
+                          gr->desc.integrator == SL_RK4 ? t + dt : t + 0.75 * dt, t + dt};
+    for (int i = 0; i < 4; ++i) st.tf[i] = periodic ? cos(M_PI * ts[i] / gr->v.p[0]) : 1.0;
+  }
   const dim3 blocks((unsigned)((gr->g.n[0] + sl::kTrajBX - 1) / sl::kTrajBX),
                     (unsigned)((gr->g.n[1] + sl::kTrajBY - 1) / sl::kTrajBY),
                     (unsigned)gr->g.n[2]);
@@ -470,15 +473,15 @@ hipError_t launch_traj(sl_grid* gr, double* disp, double t, double dt, int accum
   const int integ = gr->desc.integrator;
   switch (gr->v.kind) {
     case SL_VEL_UNIFORM:
-      return launch(sl::traj_kernel<D, SL_VEL_UNIFORM>, blocks, threads, 0, s, e0, e1, gr->g, gr->v, disp, t, dt, accumulate, integ);
+      return launch(sl::traj_kernel<D, SL_VEL_UNIFORM>, blocks, threads, 0, s, e0, e1, gr->g, gr->v, disp, st, dt, accumulate, integ);
     case SL_VEL_SOLID_BODY:
-      return launch(sl::traj_kernel<D, SL_VEL_SOLID_BODY>, blocks, threads, 0, s, e0, e1, gr->g, gr->v, disp, t, dt, accumulate, integ);
+      return launch(sl::traj_kernel<D, SL_VEL_SOLID_BODY>, blocks, threads, 0, s, e0, e1, gr->g, gr->v, disp, st, dt, accumulate, integ);
     case SL_VEL_SWIRL2D:
-      return launch(sl::traj_kernel<D, SL_VEL_SWIRL2D>, blocks, threads, 0, s, e0, e1, gr->g, gr->v, disp, t, dt, accumulate, integ);
+      return launch(sl::traj_kernel<D, SL_VEL_SWIRL2D>, blocks, threads, 0, s, e0, e1, gr->g, gr->v, disp, st, dt, accumulate, integ);
     case SL_VEL_DEFORM3D:
-      return launch(sl::traj_kernel<D, SL_VEL_DEFORM3D>, blocks, threads, 0, s, e0, e1, gr->g, gr->v, disp, t, dt, accumulate, integ);
+      return launch(sl::traj_kernel<D, SL_VEL_DEFORM3D>, blocks, threads, 0, s, e0, e1, gr->g, gr->v, disp, st, dt, accumulate, integ);
     default:
-      return launch(sl::traj_kernel<D, SL_VEL_FOURIER>, blocks, threads, 0, s, e0, e1, gr->g, gr->v, disp, t, dt, accumulate, integ);
+      return launch(sl::traj_kernel<D, SL_VEL_FOURIER>, blocks, threads, 0, s, e0, e1, gr->g, gr->v, disp, st, dt, accumulate, integ);
   }
 }
 

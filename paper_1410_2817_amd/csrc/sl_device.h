@@ -148,6 +148,84 @@ __device__ __forceinline__ void velocity(const VelArgs& v, const double* x, doub
 }
 
 // ---------------------------------------------------------------------------
+// Velocity at the Runge-Kutta stage points of one lattice node.  The stage
+// points are x0 + delta with delta a few cells at most, so the periodic
+// families evaluate sin/cos(pi x0) once and reach each stage point by angle
+// addition with sin/cos(pi delta) from short Taylor series; `tf` is the time
+// factor cos(pi t / p0) of the stage, computed on the host.
+
+// sin(pi d) and cos(pi d): Taylor series to z^9 / z^10 (z = pi d) for
+// |d| <= 1/32, where the truncation error is below 2e-19; sincospi beyond.
+__device__ __forceinline__ void sincospi_near0(double d, double* s, double* c) {
+  if (fabs(d) <= 0.03125) {
+    const double z = 3.141592653589793 * d, z2 = z * z;
+    *s = z * (1.0 + z2 * (-1.0 / 6 + z2 * (1.0 / 120 + z2 * (-1.0 / 5040 + z2 * (1.0 / 362880)))));
+    *c = 1.0 + z2 * (-0.5 + z2 * (1.0 / 24 + z2 * (-1.0 / 720 + z2 * (1.0 / 40320 +
+                                                                    z2 * (-1.0 / 3628800)))));
+  } else {
+    sincospi(d, s, c);
+  }
+}
+
+// sin/cos(pi (x0 + d)) from s0 = sin(pi x0), c0 = cos(pi x0).
+__device__ __forceinline__ void sincospi_shift(double s0, double c0, double d, double* s,
+                                               double* c) {
+  double sd, cd;
+  sincospi_near0(d, &sd, &cd);
+  *s = s0 * cd + c0 * sd;
+  *c = c0 * cd - s0 * sd;
+}
+
+template <int VK, int D>
+struct NodeVelocity {
+  double s0[3], c0[3];
+
+  __device__ __forceinline__ void init(const double* x0) {
+    if constexpr (VK == SL_VEL_SWIRL2D || (VK == SL_VEL_DEFORM3D && D == 3)) {
+      constexpr int NA = VK == SL_VEL_SWIRL2D ? 2 : 3;
+#pragma unroll
+      for (int a = 0; a < NA; ++a) sincospi(x0[a], &s0[a], &c0[a]);
+    }
+  }
+
+  // Velocity at x0 + delta (delta == nullptr: at x0 itself).
+  __device__ __forceinline__ void eval(const VelArgs& v, const double* x0, const double* delta,
+                                       double tf, double* u) const {
+    if constexpr (VK == SL_VEL_SWIRL2D || (VK == SL_VEL_DEFORM3D && D == 3)) {
+      constexpr int NA = VK == SL_VEL_SWIRL2D ? 2 : 3;
+      double sn[3], cs[3];
+#pragma unroll
+      for (int a = 0; a < NA; ++a) {
+        if (delta) {
+          sincospi_shift(s0[a], c0[a], delta[a], &sn[a], &cs[a]);
+        } else {
+          sn[a] = s0[a];
+          cs[a] = c0[a];
+        }
+      }
+      const double s = v.p[1] * tf;
+      if constexpr (VK == SL_VEL_SWIRL2D) {
+        // sin(2 pi y) = 2 sin(pi y) cos(pi y)
+        u[0] = s * sn[0] * sn[0] * (2.0 * sn[1] * cs[1]);
+        u[1] = -s * sn[1] * sn[1] * (2.0 * sn[0] * cs[0]);
+        if constexpr (D == 3) u[2] = 0.0;
+      } else {
+        const double s2x = 2.0 * sn[0] * cs[0], s2y = 2.0 * sn[1] * cs[1],
+                     s2z = 2.0 * sn[2] * cs[2];
+        u[0] = 2.0 * s * sn[0] * sn[0] * s2y * s2z;
+        u[1] = -s * s2x * sn[1] * sn[1] * s2z;
+        u[2] = -s * s2x * s2y * sn[2] * sn[2];
+      }
+    } else {
+      double x[D];
+#pragma unroll
+      for (int a = 0; a < D; ++a) x[a] = delta ? x0[a] + delta[a] : x0[a];
+      velocity<VK, D>(v, x, tf, u);
+    }
+  }
+};
+
+// ---------------------------------------------------------------------------
 // Cardinal Z-spline weights (Appendix).  For a point r + t, slot s = k + 2
 // holds the weight Z_m(t - k) of node r + k, k = -2..3; slots outside the
 // order-m stencil are zero.

@@ -96,8 +96,10 @@ def test_integer_translation_bitwise(B, torch, orc, shape, shift, prec):
 def _traj_cases():
     yield "uniform2d", W.uniform_translation((24, 20), [0.3, -0.2], 0.05, [np.zeros((24, 20))])
     yield "sbr", W.solid_body_gaussian(48, 100)
-    yield "swirl", W.swirl_three_fields(40, value_prec="f64")
+    yield "swirl", W.swirl_three_fields(40, value_prec="f64")  # large stage offsets
+    yield "swirl256", W.swirl_three_fields(256, value_prec="f64")  # small offsets
     yield "deform3d", W.deform3d_slotted_sphere(16, nsteps=4)
+    yield "deform3d64", W.deform3d_slotted_sphere(64, nsteps=4)
     w = W.fourier3d_three_fields(12, seed=3)
     yield "fourier3d", w
     w2 = W.serving_request(W.rng(5), 0, 0.0, sides=(64,)).workload
