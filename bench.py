@@ -25,6 +25,66 @@ if ROOT not in sys.path:
 
 METRIC = "node-updates/s at fixed L1 error vs FP64 oracle; serving p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
+PROFILES = os.path.join(ROOT, "profiles")
+TRAFFIC_JSON = os.path.join(PROFILES, "recon2d_swirl1024_traffic.json")
+RECON_KERNEL = "recon2d_tiled_kernel<float, 3>"
+
+
+def source_hash() -> str:
+    """Hash of the HIP sources, to tell whether recorded counters still apply."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1410_2817_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".h", ".hip")):
+            h.update(name.encode())
+            with open(os.path.join(csrc, name), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _pmc_mean(csv_path: str, kernel_sub: str, counter: str):
+    import csv
+    vals = []
+    with open(csv_path) as fh:
+        for row in csv.DictReader(fh):
+            if kernel_sub in row["Kernel_Name"] and row["Counter_Name"] == counter:
+                vals.append(float(row["Counter_Value"]))
+    return sum(vals) / len(vals) if vals else None
+
+
+def record_traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, command):
+    """Turn four rocprofv3 --pmc runs (FETCH_SIZE / WRITE_SIZE of the benchmark
+    and of the plain 256 MiB copy) into the traffic record bench.py reports."""
+    f = _pmc_mean(os.path.join(fetch_dir, "run_counter_collection.csv"), RECON_KERNEL, "FETCH_SIZE")
+    w = _pmc_mean(os.path.join(write_dir, "run_counter_collection.csv"), RECON_KERNEL, "WRITE_SIZE")
+    cf = _pmc_mean(os.path.join(copy_fetch_dir, "run_counter_collection.csv"), "copyBuffer", "FETCH_SIZE")
+    cw = _pmc_mean(os.path.join(copy_write_dir, "run_counter_collection.csv"), "copyBuffer", "WRITE_SIZE")
+    copy_kib = 64 * 1024 * 1024 * 4 / 1024.0
+    ff, fw = copy_kib / cf, copy_kib / cw
+    rec = {"kernel": RECON_KERNEL, "workload": "swirl2d_1024x1024_3fields_f32",
+           "fetch_kib_per_dispatch": f, "write_kib_per_dispatch": w,
+           "copy_fetch_kib": cf, "copy_write_kib": cw, "copy_kib": copy_kib,
+           "fetch_factor": ff, "write_factor": fw,
+           "traffic_bytes_per_launch": (f * ff + w * fw) * 1024.0,
+           "source_hash": source_hash(), "command": command}
+    os.makedirs(PROFILES, exist_ok=True)
+    with open(TRAFFIC_JSON, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(json.dumps(rec))
+
+
+def recorded_traffic():
+    """Traffic bytes per reconstruction launch from the committed counter
+    record, or None when the kernel sources changed since it was taken."""
+    try:
+        with open(TRAFFIC_JSON) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_hash") != source_hash():
+        return None
+    return rec.get("traffic_bytes_per_launch")
 
 
 def recon_bytes_per_node(dim: int, nfields: int, value_bytes: int) -> int:
@@ -54,6 +114,10 @@ def parse():
                     help="wall-clock budget of the oracle sample")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of known size (for PMC scaling)")
+    ap.add_argument("--record-traffic", nargs=4, metavar="DIR",
+                    help="write the traffic record from rocprofv3 --pmc output directories: "
+                         "FETCH, WRITE, copy FETCH, copy WRITE")
+    ap.add_argument("--record-command", default="", help="command line stored in the record")
     return ap.parse_args()
 
 
@@ -77,6 +141,9 @@ def main():
         sys.exit(2)
     if args.calibrate_copy:
         calibrate_copy()
+        return
+    if args.record_traffic:
+        record_traffic(*args.record_traffic, command=args.record_command)
         return
     import torch
 
@@ -156,7 +223,8 @@ def main():
         "roofline": {
             "kernel": "reconstruction (sl_reconstruct)",
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": None,
+            "frac": achieved / HBM_PEAK_GBS if achieved else None,
+            "traffic": recorded_traffic() if args.n == 1024 and args.prec == "f32" else None,
             "bytes_per_node": per_node, "avg_ms": recon_ms,
             "launches": prof["recon_launches"],
         },
