@@ -209,6 +209,75 @@ int sl_profile_read(sl_grid *grid, sl_profile *out);
  * argument. */
 const double *sl_displacement(const sl_grid *grid, const void *workspace, int axis);
 
+/* ------------------------------------------------------------------------
+ * Serving: continuous batching of many independent 2-D problems.
+ *
+ * The caller provides one device arena; its size is the HBM budget.  Each
+ * admitted request receives its own field buffers and lattice workspace from
+ * the arena (or SL_EBUSY when they do not fit or max_requests are active).
+ * Every sl_server_tick advances each active request by one step
+ * (trajectories, then reconstruction and lattice reset, as sl_step +
+ * sl_reconstruct with reconstruct_every = 1) through batched launches on the
+ * server's stream; requests join between ticks and leave when their step
+ * count is reached.  A request's result is bitwise the same as running it
+ * alone through sl_advance.  2-D grids only; all velocity families but
+ * SL_VEL_DEFORM3D.  A server is used from one host thread at a time.
+ * ------------------------------------------------------------------------ */
+typedef struct sl_server sl_server;
+
+typedef struct sl_server_status {
+  int active;              /* requests still stepping */
+  int finished;            /* requests done stepping, not yet fetched */
+  size_t bytes_in_use;     /* arena bytes held by requests */
+  size_t bytes_free;       /* arena bytes available to admissions */
+  int64_t ticks;           /* ticks enqueued */
+  int64_t completed_ticks; /* ticks known to have finished on the device */
+} sl_server_status;
+
+/* Arena bytes one request with this descriptor occupies (0 if invalid). */
+size_t sl_server_request_bytes(const sl_grid_desc *desc);
+
+/* Create a server over the device arena [arena, arena + arena_bytes)
+ * (256-byte aligned, caller-owned, must outlive the server).  At most
+ * max_requests requests are resident; sl_server_tick blocks the host while
+ * more than max_inflight ticks are queued on `stream`.  Errors: SL_EINVAL,
+ * SL_ENOMEM, SL_EHIP. */
+int sl_server_create(void *arena, size_t arena_bytes, int max_requests,
+                     int max_inflight, void *stream, sl_server **out);
+
+/* Wait for the stream and destroy the server (NULL accepted). */
+int sl_server_destroy(sl_server *server);
+
+/* Admit a request: copy its initial fields (device pointers in the grid's
+ * value precision; the copy is queued on the server's stream, so the sources
+ * must stay valid until that stream reaches it) into the arena and schedule
+ * nsteps steps of dt from t0.  *id identifies it.
+ * Errors: SL_EINVAL (bad descriptor, 3-D grid, reconstruct_every != 1),
+ * SL_EBUSY (no room), SL_EHIP. */
+int sl_server_admit(sl_server *server, const sl_grid_desc *desc,
+                    const void *const *fields_in, double t0, double dt, int nsteps,
+                    int64_t *id);
+
+/* Advance every active request by one step; *active (may be NULL) receives
+ * the number still stepping afterwards.  Errors: SL_EINVAL, SL_EHIP. */
+int sl_server_tick(sl_server *server, int *active);
+
+/* Report up to max_ids requests whose last step has completed on the device
+ * and that were not reported before.  Never blocks. */
+int sl_server_poll(sl_server *server, int64_t *done_ids, int max_ids, int *ndone);
+
+/* Copy a finished request's fields into caller buffers (asynchronous on the
+ * server's stream) and release its arena memory.  SL_ENOTFOUND for an unknown
+ * or unfinished id. */
+int sl_server_fetch(sl_server *server, int64_t id, void *const *fields_out);
+
+/* Wait for the stream; report and clear the device counters accumulated by
+ * all requests since the last call (status as for sl_sync). */
+int sl_server_sync(sl_server *server, sl_stats *stats);
+
+/* Occupancy of the server. */
+int sl_server_info(const sl_server *server, sl_server_status *out);
+
 /* Static text for a status code. */
 const char *sl_strerror(int code);
 

@@ -64,6 +64,12 @@ class SlProfile(C.Structure):
                 "recon_launches": self.recon_launches, "recon_ms": self.recon_ms}
 
 
+class SlServerStatus(C.Structure):
+    _fields_ = [("active", C.c_int), ("finished", C.c_int), ("bytes_in_use", C.c_size_t),
+                ("bytes_free", C.c_size_t), ("ticks", C.c_int64),
+                ("completed_ticks", C.c_int64)]
+
+
 # Every symbol include/sl.h declares, with its ctypes signature.
 _VP = C.c_void_p
 SIGNATURES = {
@@ -81,6 +87,16 @@ SIGNATURES = {
     "sl_displacement": (C.c_void_p, [_VP, _VP, C.c_int]),
     "sl_strerror": (C.c_char_p, [C.c_int]),
     "sl_version": (C.c_int, []),
+    "sl_server_request_bytes": (C.c_size_t, [C.POINTER(SlGridDesc)]),
+    "sl_server_create": (C.c_int, [_VP, C.c_size_t, C.c_int, C.c_int, _VP, C.POINTER(_VP)]),
+    "sl_server_destroy": (C.c_int, [_VP]),
+    "sl_server_admit": (C.c_int, [_VP, C.POINTER(SlGridDesc), C.POINTER(_VP), C.c_double,
+                                  C.c_double, C.c_int, C.POINTER(C.c_int64)]),
+    "sl_server_tick": (C.c_int, [_VP, C.POINTER(C.c_int)]),
+    "sl_server_poll": (C.c_int, [_VP, C.POINTER(C.c_int64), C.c_int, C.POINTER(C.c_int)]),
+    "sl_server_fetch": (C.c_int, [_VP, C.c_int64, C.POINTER(_VP)]),
+    "sl_server_sync": (C.c_int, [_VP, C.POINTER(SlStats)]),
+    "sl_server_info": (C.c_int, [_VP, C.POINTER(SlServerStatus)]),
     "sl_error_detail": (C.c_char_p, []),
 }
 

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 INCLUDE = os.path.join(ROOT, "include")
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsl.so")
-SOURCES = [os.path.join(CSRC, "sl.hip")]
+SOURCES = [os.path.join(CSRC, "sl.hip"), os.path.join(CSRC, "sl_serve.hip")]
 ARCH = "gfx950"
 
 

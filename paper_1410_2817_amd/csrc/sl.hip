@@ -24,103 +24,11 @@
 
 #include "sl.h"
 #include "sl_device.h"
+#include "sl_launch.h"
 #include "sl_recon2d.h"
+#include "sl_traj.h"
 
 namespace sl {
-
-constexpr int kBlock = 256;
-
-template <int D>
-__device__ __forceinline__ void unflatten(const GridArgs& g, int lin, int* idx) {
-  idx[0] = lin % g.n[0];
-  if constexpr (D == 2) {
-    idx[1] = lin / g.n[0];
-  } else {
-    const int q = lin / g.n[0];
-    idx[1] = q % g.n[1];
-    idx[2] = q / g.n[1];
-  }
-}
-
-template <int D>
-__device__ __forceinline__ int flatten(const GridArgs& g, const int* w) {
-  if constexpr (D == 2)
-    return w[0] + g.n[0] * w[1];
-  else
-    return w[0] + g.n[0] * (w[1] + g.n[1] * w[2]);
-}
-
-// ---------------------------------------------------------------------------
-// Trajectories (Sec. 2, eq. "vel").
-
-// Time factors cos(pi t_s / p0) of the periodic families at the stage times,
-// computed on the host (1 for the steady families).
-struct StageTimes {
-  double tf[4];
-};
-
-// Launched on a (ceil(nx/64), ceil(ny/4), nz) grid of 64 x 4 work-items, so
-// node coordinates come without integer division.
-constexpr int kTrajBX = 64, kTrajBY = 4;
-
-template <int D, int VK>
-__global__ __launch_bounds__(kBlock) void traj_kernel(GridArgs g, VelArgs v,
-                                                      double* __restrict__ disp, StageTimes st,
-                                                      double dt, int accumulate,
-                                                      int integrator) {
-  int idx[D];
-  idx[0] = blockIdx.x * kTrajBX + threadIdx.x;
-  idx[1] = blockIdx.y * kTrajBY + threadIdx.y;
-  if constexpr (D == 3) idx[2] = blockIdx.z;
-  if (idx[0] >= g.n[0] || idx[1] >= g.n[1]) return;
-  const int lin = flatten<D>(g, idx);
-  double d[D], x[D];
-#pragma unroll
-  for (int a = 0; a < D; ++a) {
-    d[a] = accumulate ? disp[(size_t)a * g.ntot + lin] : 0.0;
-    x[a] = ((double)idx[a] + d[a]) * g.h[a];
-  }
-  NodeVelocity<VK, D> vel;
-  vel.init(x);
-  if (integrator == SL_RK4) {
-    double k1[D], k2[D], k3[D], k4[D], o[D];
-    vel.eval(v, x, nullptr, st.tf[0], k1);
-#pragma unroll
-    for (int a = 0; a < D; ++a) o[a] = 0.5 * dt * k1[a];
-    vel.eval(v, x, o, st.tf[1], k2);
-#pragma unroll
-    for (int a = 0; a < D; ++a) o[a] = 0.5 * dt * k2[a];
-    vel.eval(v, x, o, st.tf[1], k3);
-#pragma unroll
-    for (int a = 0; a < D; ++a) o[a] = dt * k3[a];
-    vel.eval(v, x, o, st.tf[2], k4);
-#pragma unroll
-    for (int a = 0; a < D; ++a)
-      d[a] += dt * (k1[a] + 2.0 * k2[a] + 2.0 * k3[a] + k4[a]) / 6.0 / g.h[a];
-  } else {
-    // Williamson (1980) 2N-storage RK3: q = A_s q + dt u(x + dx, t + c_s dt),
-    // dx += B_s q with A = (0, -5/9, -153/128), B = (1/3, 15/16, 8/15),
-    // c = (0, 1/3, 3/4).
-    const double A[3] = {0.0, -5.0 / 9.0, -153.0 / 128.0};
-    const double B[3] = {1.0 / 3.0, 15.0 / 16.0, 8.0 / 15.0};
-    double q[D], dx[D], u[D];
-#pragma unroll
-    for (int a = 0; a < D; ++a) q[a] = dx[a] = 0.0;
-#pragma unroll
-    for (int s = 0; s < 3; ++s) {
-      vel.eval(v, x, s == 0 ? nullptr : dx, st.tf[s], u);
-#pragma unroll
-      for (int a = 0; a < D; ++a) {
-        q[a] = A[s] * q[a] + dt * u[a];
-        dx[a] += B[s] * q[a];
-      }
-    }
-#pragma unroll
-    for (int a = 0; a < D; ++a) d[a] += dx[a] / g.h[a];
-  }
-#pragma unroll
-  for (int a = 0; a < D; ++a) disp[(size_t)a * g.ntot + lin] = d[a];
-}
 
 // ---------------------------------------------------------------------------
 // Jump flags (Sec. 2.3): bit f of flags[node] is set when the criterion fires
@@ -295,27 +203,7 @@ __global__ void zero_kernel(unsigned long long* p, int n) {
 // ===========================================================================
 // Host side: descriptors, validation, launches.
 
-struct sl_prof_pair {
-  int kind;  // 0 trajectories, 1 reconstruction
-  hipEvent_t start, stop;
-};
-
-struct sl_grid {
-  sl_grid_desc desc;
-  std::vector<double> modes;
-  sl::GridArgs g;
-  sl::VelArgs v;
-  int64_t ntot;
-  size_t off_stats, off_disp, off_flags, ws_bytes;
-  int steps_since_reset;
-  int64_t steps_launched, reconstructs_launched;
-  // Kernel timing with events attached to the dispatch packets.
-  bool prof_on;
-  std::vector<hipEvent_t> ev_free;
-  std::vector<sl_prof_pair> pending;
-  double prof_ms[2];
-  int64_t prof_n[2];
-};
+#include "sl_grid.h"
 
 namespace {
 
@@ -325,27 +213,6 @@ constexpr size_t kStatsBytes = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 constexpr size_t kMaxPendingPairs = 8192;
-
-// Launch through hipExtLaunchKernel so that timing events (when given) are
-// part of the dispatch packet rather than extra packets on the stream.
-template <typename... KArgs, typename... Args, size_t... I>
-hipError_t launch_impl(void (*kernel)(KArgs...), dim3 grid, dim3 block, uint32_t shmem,
-                       hipStream_t s, hipEvent_t e0, hipEvent_t e1,
-                       std::index_sequence<I...>, Args&&... args) {
-  std::tuple<KArgs...> tup(std::forward<Args>(args)...);
-  void* argv[sizeof...(KArgs) > 0 ? sizeof...(KArgs) : 1] = {
-      static_cast<void*>(&std::get<I>(tup))...};
-  return hipExtLaunchKernel(reinterpret_cast<const void*>(kernel), grid, block, argv, shmem,
-                            s, e0, e1, 0);
-}
-
-template <typename... KArgs, typename... Args>
-hipError_t launch(void (*kernel)(KArgs...), dim3 grid, dim3 block, uint32_t shmem,
-                  hipStream_t s, hipEvent_t e0, hipEvent_t e1, Args&&... args) {
-  static_assert(sizeof...(KArgs) == sizeof...(Args), "kernel argument count");
-  return launch_impl(kernel, grid, block, shmem, s, e0, e1,
-                     std::index_sequence_for<KArgs...>{}, std::forward<Args>(args)...);
-}
 
 void prof_fold(sl_grid* gr) {
   for (const sl_prof_pair& p : gr->pending) {
@@ -455,6 +322,8 @@ int hip_status(hipError_t e) {
 // Launch errors are read back with hipGetLastError(); clear whatever another
 // library left behind first so it is not reported as ours.
 void clear_stale_error() { (void)hipGetLastError(); }
+
+using sl::launch;
 
 template <int D>
 hipError_t launch_traj(sl_grid* gr, double* disp, double t, double dt, int accumulate,

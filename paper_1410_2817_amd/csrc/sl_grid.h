@@ -1,0 +1,33 @@
+// Host-side state of a grid handle (private to the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "sl.h"
+#include "sl_device.h"
+
+struct sl_prof_pair {
+  int kind;  // 0 trajectories, 1 reconstruction
+  hipEvent_t start, stop;
+};
+
+struct sl_grid {
+  sl_grid_desc desc;
+  std::vector<double> modes;
+  sl::GridArgs g;
+  sl::VelArgs v;
+  int64_t ntot;
+  size_t off_stats, off_disp, off_flags, ws_bytes;
+  int steps_since_reset;
+  int64_t steps_launched, reconstructs_launched;
+  // Kernel timing with events attached to the dispatch packets.
+  bool prof_on;
+  std::vector<hipEvent_t> ev_free;
+  std::vector<sl_prof_pair> pending;
+  double prof_ms[2];
+  int64_t prof_n[2];
+};
+

@@ -179,18 +179,19 @@ __device__ __forceinline__ T zsum2d(const T* wx, const T* wy, const Val& val) {
   return acc;
 }
 
-// NF is the number of fields (a compile-time constant so that the per-field
-// loops unroll without exec-mask bookkeeping).
+// One workgroup's tile: the whole reconstruction of tile `tile` of a grid
+// with `tiles_x` tiles per row.  NF is the number of fields (a compile-time
+// constant so that the per-field loops unroll without exec-mask
+// bookkeeping).  `smem` is the workgroup's dynamic LDS (Tile2D::LDS_BYTES).
 template <typename T, int NF>
-__global__ __launch_bounds__(kTileThreads) void recon2d_tiled_kernel(
-    GridArgs g, FieldPtrs fp, const double* __restrict__ gdisp,
-    unsigned long long* __restrict__ stats, int tiles_x, int ntiles) {
+__device__ __forceinline__ void recon2d_tile(const GridArgs& g, const FieldPtrs& fp,
+                                             const double* __restrict__ gdisp,
+                                             unsigned long long* __restrict__ stats, int tile,
+                                             int tiles_x, unsigned char* smem) {
   using C = Tile2D<T, NF>;
-  extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int s_box[4];  // min rx, min ry, max rx, max ry
   __shared__ unsigned s_cnt[ST_COUNT];
 
-  const int tile = xcd_tile(blockIdx.x, ntiles);
   const int tx0 = (tile % tiles_x) * C::TX, ty0 = (tile / tiles_x) * C::TY;
   const int lx = threadIdx.x % C::TX, ly0 = threadIdx.x / C::TX;
   constexpr int ROWS = kTileThreads / C::TX;  // rows covered per pass
@@ -454,6 +455,14 @@ __global__ __launch_bounds__(kTileThreads) void recon2d_tiled_kernel(
   __syncthreads();
   if (threadIdx.x < ST_COUNT && s_cnt[threadIdx.x])
     atomicAdd(stats + threadIdx.x, (unsigned long long)s_cnt[threadIdx.x]);
+}
+
+template <typename T, int NF>
+__global__ __launch_bounds__(kTileThreads) void recon2d_tiled_kernel(
+    GridArgs g, FieldPtrs fp, const double* __restrict__ gdisp,
+    unsigned long long* __restrict__ stats, int tiles_x, int ntiles) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  recon2d_tile<T, NF>(g, fp, gdisp, stats, xcd_tile(blockIdx.x, ntiles), tiles_x, smem);
 }
 
 }  // namespace sl

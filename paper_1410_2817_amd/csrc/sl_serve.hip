@@ -1,0 +1,570 @@
+// Continuous batching of many independent 2-D advection problems on one GPU.
+//
+// The caller hands the server one device arena.  The server keeps a table of
+// request descriptors at its start and sub-allocates each admitted request's
+// two field sets and lattice displacement from the rest (first fit, 256-byte
+// aligned); a request that does not fit is refused with SL_EBUSY, so the
+// arena size is the HBM budget.  Every tick advances each active request by
+// one step of the scheme (trajectories, then reconstruction with the lattice
+// reset) through one batched trajectory launch per velocity family and one
+// batched reconstruction launch per (precision, field count): workgroups find
+// their request from per-tick block offsets passed in the kernel arguments and
+// run exactly the per-tile code of the single-grid kernels, so a request's
+// result does not depend on what it was batched with.  Requests join between
+// ticks as memory frees up and leave when their step count is reached.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <deque>
+#include <map>
+#include <new>
+#include <vector>
+
+#include "sl.h"
+#include "sl_device.h"
+#include "sl_grid.h"
+#include "sl_launch.h"
+#include "sl_recon2d.h"
+#include "sl_traj.h"
+
+namespace sl {
+
+// Device-resident, written once at admission.
+struct ReqStatic {
+  GridArgs g;
+  VelArgs v;
+  FieldPtrs ab;  // in = set A, out = set B; odd ticks swap them
+  double* disp;
+  unsigned long long* stats;
+  int tiles_x, ntiles;    // reconstruction tiles
+  int traj_bx, traj_by;   // trajectory blocks (64 x 4 nodes each)
+  int integrator;
+  int pad;
+};
+
+// Per tick and request, passed in the kernel arguments.
+struct ReqTick {
+  int entry;      // table index
+  int blk_begin;  // first block of this request in the batched launch
+  int parity;     // 0: A -> B, 1: B -> A
+  int pad;
+  double dt;
+  double tf[3];   // stage time factors (periodic velocity families)
+};
+
+constexpr int kServeBatch = 40;  // requests per batched launch (kernel-argument budget)
+
+struct TickArgs {
+  int nreq;
+  int total_blocks;
+  ReqTick r[kServeBatch];
+};
+
+// Request of batched block b (block offsets ascend; the search is uniform).
+__device__ __forceinline__ int find_request(const TickArgs& ta, int b) {
+  int i = 0;
+  while (i + 1 < ta.nreq && ta.r[i + 1].blk_begin <= b) ++i;
+  return i;
+}
+
+template <int VK>
+__global__ __launch_bounds__(kBlock) void traj_batched_kernel(const ReqStatic* __restrict__ table,
+                                                              TickArgs ta) {
+  const int i = find_request(ta, blockIdx.x);
+  const ReqTick& rt = ta.r[i];
+  const ReqStatic& rs = table[rt.entry];
+  const int lb = blockIdx.x - rt.blk_begin;
+  const int bx = lb % rs.traj_bx, by = lb / rs.traj_bx;
+  int idx[2] = {bx * kTrajBX + (int)(threadIdx.x % kTrajBX),
+                by * kTrajBY + (int)(threadIdx.x / kTrajBX)};
+  if (idx[0] >= rs.g.n[0] || idx[1] >= rs.g.n[1]) return;
+  StageTimes st;
+  st.tf[0] = rt.tf[0];
+  st.tf[1] = rt.tf[1];
+  st.tf[2] = rt.tf[2];
+  st.tf[3] = rt.tf[2];
+  traj_node<2, VK>(rs.g, rs.v, rs.disp, st, rt.dt, 0, rs.integrator, idx);
+}
+
+template <typename T, int NF>
+__global__ __launch_bounds__(kTileThreads) void recon2d_batched_kernel(
+    const ReqStatic* __restrict__ table, TickArgs ta) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int logical = xcd_tile(blockIdx.x, ta.total_blocks);
+  const int i = find_request(ta, logical);
+  const ReqTick& rt = ta.r[i];
+  const ReqStatic& rs = table[rt.entry];
+  FieldPtrs fp;
+#pragma unroll
+  for (int f = 0; f < SL_MAX_FIELDS; ++f) {
+    fp.in[f] = rt.parity ? rs.ab.out[f] : rs.ab.in[f];
+    fp.out[f] = rt.parity ? const_cast<void*>(rs.ab.in[f]) : rs.ab.out[f];
+  }
+  recon2d_tile<T, NF>(rs.g, fp, rs.disp, rs.stats, logical - rt.blk_begin, rs.tiles_x, smem);
+}
+
+}  // namespace sl
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Request {
+  int64_t id;
+  int entry;
+  sl_grid* grid;
+  size_t off, bytes;
+  int nsteps, done;
+  double t0, dt;
+  int64_t finish_tick;
+  bool reported;
+  void* a[SL_MAX_FIELDS];
+  void* b[SL_MAX_FIELDS];
+};
+
+}  // namespace
+
+struct sl_server {
+  char* arena;
+  size_t arena_bytes;
+  hipStream_t stream;
+  int max_requests;
+  int max_inflight;
+  sl::ReqStatic* table;                 // device, at the arena start
+  std::vector<sl::ReqStatic> host_table;  // host copies (stable source of the uploads)
+  unsigned long long* stats;            // device counters shared by all requests
+  std::map<size_t, size_t> free_blocks;   // offset -> size
+  std::vector<int> free_entries;
+  std::vector<Request> active;
+  std::vector<Request> finished;
+  int64_t next_id;
+  int64_t tick;
+  std::deque<std::pair<int64_t, hipEvent_t>> tick_events;
+  std::vector<hipEvent_t> ev_pool;
+  int64_t completed_tick;
+  size_t in_use;
+};
+
+namespace {
+
+bool arena_alloc(sl_server* s, size_t bytes, size_t* off) {
+  for (auto it = s->free_blocks.begin(); it != s->free_blocks.end(); ++it) {
+    if (it->second >= bytes) {
+      *off = it->first;
+      const size_t rest = it->second - bytes;
+      const size_t roff = it->first + bytes;
+      s->free_blocks.erase(it);
+      if (rest) s->free_blocks[roff] = rest;
+      s->in_use += bytes;
+      return true;
+    }
+  }
+  return false;
+}
+
+void arena_free(sl_server* s, size_t off, size_t bytes) {
+  auto it = s->free_blocks.emplace(off, bytes).first;
+  // Coalesce with the following block, then with the preceding one.
+  auto nx = std::next(it);
+  if (nx != s->free_blocks.end() && it->first + it->second == nx->first) {
+    it->second += nx->second;
+    s->free_blocks.erase(nx);
+  }
+  if (it != s->free_blocks.begin()) {
+    auto pv = std::prev(it);
+    if (pv->first + pv->second == it->first) {
+      pv->second += it->second;
+      s->free_blocks.erase(it);
+    }
+  }
+  s->in_use -= bytes;
+}
+
+size_t request_bytes(const sl_grid* gr) {
+  const size_t vbytes = gr->desc.value_prec == SL_FP32 ? 4 : 8;
+  const size_t field = align_up(vbytes * (size_t)gr->ntot);
+  return 2 * (size_t)gr->desc.nfields * field + align_up(sl_workspace_bytes(gr));
+}
+
+hipEvent_t take_event(sl_server* s) {
+  if (!s->ev_pool.empty()) {
+    hipEvent_t e = s->ev_pool.back();
+    s->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Mark finished ticks (events that have completed), oldest first.
+void drain_events(sl_server* s, bool wait_all, size_t keep) {
+  while (!s->tick_events.empty()) {
+    hipEvent_t e = s->tick_events.front().second;
+    const bool must_wait = wait_all || s->tick_events.size() > keep;
+    if (must_wait) {
+      if (hipEventSynchronize(e) != hipSuccess) break;
+    } else if (hipEventQuery(e) != hipSuccess) {
+      break;
+    }
+    s->completed_tick = s->tick_events.front().first;
+    s->ev_pool.push_back(e);
+    s->tick_events.pop_front();
+  }
+}
+
+template <typename T>
+hipError_t launch_recon_group(sl_server* s, int nf, const sl::TickArgs& ta) {
+  const dim3 grid(ta.total_blocks), block(sl::kTileThreads);
+#define SL_SERVE_RECON(NF)                                                               \
+  case NF:                                                                               \
+    return sl::launch(sl::recon2d_batched_kernel<T, NF>, grid, block,                   \
+                      (uint32_t)sl::Tile2D<T, NF>::LDS_BYTES, s->stream, nullptr, nullptr, \
+                      (const sl::ReqStatic*)s->table, ta);
+  switch (nf) {
+    SL_SERVE_RECON(1)
+    SL_SERVE_RECON(2)
+    SL_SERVE_RECON(3)
+    SL_SERVE_RECON(4)
+    SL_SERVE_RECON(5)
+    SL_SERVE_RECON(6)
+    SL_SERVE_RECON(7)
+    default:
+      return sl::launch(sl::recon2d_batched_kernel<T, 8>, grid, block,
+                        (uint32_t)sl::Tile2D<T, 8>::LDS_BYTES, s->stream, nullptr, nullptr,
+                        (const sl::ReqStatic*)s->table, ta);
+  }
+#undef SL_SERVE_RECON
+}
+
+hipError_t launch_traj_group(sl_server* s, int vk, const sl::TickArgs& ta) {
+  const dim3 grid(ta.total_blocks), block(sl::kBlock);
+  const sl::ReqStatic* t = s->table;
+  switch (vk) {
+    case SL_VEL_UNIFORM:
+      return sl::launch(sl::traj_batched_kernel<SL_VEL_UNIFORM>, grid, block, 0, s->stream, nullptr, nullptr, t, ta);
+    case SL_VEL_SOLID_BODY:
+      return sl::launch(sl::traj_batched_kernel<SL_VEL_SOLID_BODY>, grid, block, 0, s->stream, nullptr, nullptr, t, ta);
+    case SL_VEL_SWIRL2D:
+      return sl::launch(sl::traj_batched_kernel<SL_VEL_SWIRL2D>, grid, block, 0, s->stream, nullptr, nullptr, t, ta);
+    default:
+      return sl::launch(sl::traj_batched_kernel<SL_VEL_FOURIER>, grid, block, 0, s->stream, nullptr, nullptr, t, ta);
+  }
+}
+
+void stage_times(const Request& r, double tf[3]) {
+  const sl_grid* gr = r.grid;
+  const double t = r.t0 + (double)r.done * r.dt, dt = r.dt;
+  const bool periodic = gr->v.kind == SL_VEL_SWIRL2D;
+  const bool rk4 = gr->desc.integrator == SL_RK4;
+  const double ts[3] = {t, rk4 ? t + 0.5 * dt : t + dt / 3.0, rk4 ? t + dt : t + 0.75 * dt};
+  for (int i = 0; i < 3; ++i) tf[i] = periodic ? cos(M_PI * ts[i] / gr->v.p[0]) : 1.0;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t sl_server_request_bytes(const sl_grid_desc* desc) {
+  sl_grid* gr = nullptr;
+  if (sl_create_grid(desc, &gr) != SL_OK) return 0;
+  const size_t b = request_bytes(gr);
+  sl_destroy_grid(gr);
+  return b;
+}
+
+int sl_server_create(void* arena, size_t arena_bytes, int max_requests, int max_inflight,
+                     void* stream, sl_server** out) {
+  if (!out) return SL_EINVAL;
+  *out = nullptr;
+  if (!arena || ((uintptr_t)arena) % kAlign || max_requests < 1 || max_requests > 4096 ||
+      max_inflight < 1)
+    return SL_EINVAL;
+  const size_t table_bytes = align_up(sizeof(sl::ReqStatic) * (size_t)max_requests);
+  const size_t stats_bytes = align_up(sizeof(unsigned long long) * sl::ST_COUNT);
+  if (arena_bytes < table_bytes + stats_bytes + kAlign) return SL_EINVAL;
+  sl_server* s = new (std::nothrow) sl_server();
+  if (!s) return SL_ENOMEM;
+  s->arena = static_cast<char*>(arena);
+  s->arena_bytes = arena_bytes;
+  s->stream = static_cast<hipStream_t>(stream);
+  s->max_requests = max_requests;
+  s->max_inflight = max_inflight;
+  s->table = reinterpret_cast<sl::ReqStatic*>(s->arena);
+  s->stats = reinterpret_cast<unsigned long long*>(s->arena + table_bytes);
+  s->host_table.resize(max_requests);
+  const size_t heap = table_bytes + stats_bytes;
+  s->free_blocks[heap] = (arena_bytes - heap) / kAlign * kAlign;
+  for (int e = max_requests - 1; e >= 0; --e) s->free_entries.push_back(e);
+  s->next_id = 1;
+  s->tick = 0;
+  s->completed_tick = 0;
+  s->in_use = 0;
+  // Counters start at zero.
+  const int rc =
+      hipMemsetAsync(s->stats, 0, sizeof(unsigned long long) * sl::ST_COUNT, s->stream) ==
+              hipSuccess
+          ? SL_OK
+          : SL_EHIP;
+  if (rc != SL_OK) {
+    delete s;
+    return rc;
+  }
+  *out = s;
+  return SL_OK;
+}
+
+int sl_server_destroy(sl_server* s) {
+  if (!s) return SL_OK;
+  (void)hipStreamSynchronize(s->stream);
+  for (auto& p : s->tick_events) s->ev_pool.push_back(p.second);
+  for (hipEvent_t e : s->ev_pool) (void)hipEventDestroy(e);
+  for (auto& r : s->active) sl_destroy_grid(r.grid);
+  for (auto& r : s->finished) sl_destroy_grid(r.grid);
+  delete s;
+  return SL_OK;
+}
+
+int sl_server_admit(sl_server* s, const sl_grid_desc* desc, const void* const* fields_in,
+                    double t0, double dt, int nsteps, int64_t* id) {
+  if (!s || !desc || !fields_in || !id || nsteps < 1 || !isfinite(t0) || !isfinite(dt))
+    return SL_EINVAL;
+  if (desc->dim != 2 || desc->reconstruct_every != 1) return SL_EINVAL;
+  if (desc->vel.kind == SL_VEL_DEFORM3D) return SL_EINVAL;
+  sl_grid* gr = nullptr;
+  int rc = sl_create_grid(desc, &gr);
+  if (rc != SL_OK) return rc;
+  for (int f = 0; f < desc->nfields; ++f)
+    if (!fields_in[f]) {
+      sl_destroy_grid(gr);
+      return SL_EINVAL;
+    }
+  if (s->free_entries.empty()) {
+    sl_destroy_grid(gr);
+    return SL_EBUSY;
+  }
+  const size_t bytes = request_bytes(gr);
+  size_t off = 0;
+  if (!arena_alloc(s, bytes, &off)) {
+    sl_destroy_grid(gr);
+    return SL_EBUSY;
+  }
+  Request r;
+  memset(&r, 0, sizeof(r));
+  r.id = s->next_id++;
+  r.entry = s->free_entries.back();
+  s->free_entries.pop_back();
+  r.grid = gr;
+  r.off = off;
+  r.bytes = bytes;
+  r.nsteps = nsteps;
+  r.t0 = t0;
+  r.dt = dt;
+  r.finish_tick = -1;
+  const size_t vbytes = desc->value_prec == SL_FP32 ? 4 : 8;
+  const size_t field = align_up(vbytes * (size_t)gr->ntot);
+  char* base = s->arena + off;
+  for (int f = 0; f < desc->nfields; ++f) {
+    r.a[f] = base + (size_t)f * field;
+    r.b[f] = base + (size_t)(desc->nfields + f) * field;
+  }
+  char* ws = base + 2 * (size_t)desc->nfields * field;
+
+  sl::ReqStatic& hs = s->host_table[r.entry];
+  memset(&hs, 0, sizeof(hs));
+  hs.g = gr->g;
+  hs.v = gr->v;
+  for (int f = 0; f < desc->nfields; ++f) {
+    hs.ab.in[f] = r.a[f];
+    hs.ab.out[f] = r.b[f];
+  }
+  hs.disp = reinterpret_cast<double*>(ws + gr->off_disp);
+  hs.stats = s->stats;
+  using C = sl::Tile2D<float, 1>;
+  hs.tiles_x = (gr->g.n[0] + C::TX - 1) / C::TX;
+  hs.ntiles = hs.tiles_x * ((gr->g.n[1] + C::TY - 1) / C::TY);
+  hs.traj_bx = (gr->g.n[0] + sl::kTrajBX - 1) / sl::kTrajBX;
+  hs.traj_by = (gr->g.n[1] + sl::kTrajBY - 1) / sl::kTrajBY;
+  hs.integrator = desc->integrator;
+
+  hipError_t e = hipMemcpyAsync(s->table + r.entry, &hs, sizeof(hs), hipMemcpyHostToDevice,
+                                s->stream);
+  for (int f = 0; f < desc->nfields && e == hipSuccess; ++f)
+    e = hipMemcpyAsync(r.a[f], fields_in[f], vbytes * (size_t)gr->ntot,
+                       hipMemcpyDeviceToDevice, s->stream);
+  if (e != hipSuccess) {
+    arena_free(s, off, bytes);
+    s->free_entries.push_back(r.entry);
+    sl_destroy_grid(gr);
+    return SL_EHIP;
+  }
+  s->active.push_back(r);
+  *id = r.id;
+  return SL_OK;
+}
+
+int sl_server_tick(sl_server* s, int* active) {
+  if (!s) return SL_EINVAL;
+  if (active) *active = (int)s->active.size();
+  if (s->active.empty()) return SL_OK;
+  // Keep at most max_inflight ticks queued on the device.
+  drain_events(s, false, (size_t)s->max_inflight - 1);
+
+  // Trajectories, batched per velocity family.
+  std::vector<int> order(s->active.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+  auto vk_of = [&](int i) { return s->active[i].grid->v.kind; };
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return vk_of(x) < vk_of(y); });
+  hipError_t err = hipSuccess;
+  for (size_t i = 0; i < order.size() && err == hipSuccess;) {
+    const int vk = vk_of(order[i]);
+    sl::TickArgs ta;
+    memset(&ta, 0, sizeof(ta));
+    int blocks = 0;
+    while (i < order.size() && vk_of(order[i]) == vk && ta.nreq < sl::kServeBatch) {
+      const Request& r = s->active[order[i]];
+      const sl::ReqStatic& hs = s->host_table[r.entry];
+      sl::ReqTick& rt = ta.r[ta.nreq++];
+      rt.entry = r.entry;
+      rt.blk_begin = blocks;
+      rt.parity = r.done & 1;
+      rt.dt = r.dt;
+      stage_times(r, rt.tf);
+      blocks += hs.traj_bx * hs.traj_by;
+      ++i;
+    }
+    ta.total_blocks = blocks;
+    err = launch_traj_group(s, vk, ta);
+  }
+  // Reconstructions, batched per (value precision, field count).
+  auto key_of = [&](int i) {
+    const sl_grid* g = s->active[i].grid;
+    return g->desc.value_prec * 16 + g->desc.nfields;
+  };
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return key_of(x) < key_of(y); });
+  for (size_t i = 0; i < order.size() && err == hipSuccess;) {
+    const int key = key_of(order[i]);
+    sl::TickArgs ta;
+    memset(&ta, 0, sizeof(ta));
+    int blocks = 0;
+    while (i < order.size() && key_of(order[i]) == key && ta.nreq < sl::kServeBatch) {
+      const Request& r = s->active[order[i]];
+      const sl::ReqStatic& hs = s->host_table[r.entry];
+      sl::ReqTick& rt = ta.r[ta.nreq++];
+      rt.entry = r.entry;
+      rt.blk_begin = blocks;
+      rt.parity = r.done & 1;
+      rt.dt = r.dt;
+      blocks += hs.ntiles;
+      ++i;
+    }
+    ta.total_blocks = blocks;
+    const int nf = key % 16;
+    err = (key / 16 == SL_FP32) ? launch_recon_group<float>(s, nf, ta)
+                                : launch_recon_group<double>(s, nf, ta);
+  }
+  if (err != hipSuccess) return SL_EHIP;
+  ++s->tick;
+  hipEvent_t ev = take_event(s);
+  if (!ev || hipEventRecord(ev, s->stream) != hipSuccess) return SL_EHIP;
+  s->tick_events.emplace_back(s->tick, ev);
+  // Advance the step counters; move completed requests out of the batch.
+  std::vector<Request> still;
+  still.reserve(s->active.size());
+  for (Request& r : s->active) {
+    ++r.done;
+    if (r.done >= r.nsteps) {
+      r.finish_tick = s->tick;
+      s->finished.push_back(r);
+    } else {
+      still.push_back(r);
+    }
+  }
+  s->active.swap(still);
+  if (active) *active = (int)s->active.size();
+  return SL_OK;
+}
+
+int sl_server_poll(sl_server* s, int64_t* done_ids, int max_ids, int* ndone) {
+  if (!s || !ndone || max_ids < 0 || (max_ids > 0 && !done_ids)) return SL_EINVAL;
+  drain_events(s, false, (size_t)-1);
+  int n = 0;
+  for (Request& r : s->finished) {
+    if (n >= max_ids) break;
+    if (!r.reported && r.finish_tick <= s->completed_tick) {
+      r.reported = true;
+      done_ids[n++] = r.id;
+    }
+  }
+  *ndone = n;
+  return SL_OK;
+}
+
+int sl_server_fetch(sl_server* s, int64_t id, void* const* fields_out) {
+  if (!s || !fields_out) return SL_EINVAL;
+  for (size_t i = 0; i < s->finished.size(); ++i) {
+    Request& r = s->finished[i];
+    if (r.id != id) continue;
+    const int nf = r.grid->desc.nfields;
+    const size_t vbytes = r.grid->desc.value_prec == SL_FP32 ? 4 : 8;
+    void* const* res = (r.nsteps & 1) ? r.b : r.a;
+    for (int f = 0; f < nf; ++f) {
+      if (!fields_out[f]) return SL_EINVAL;
+      if (hipMemcpyAsync(fields_out[f], res[f], vbytes * (size_t)r.grid->ntot,
+                         hipMemcpyDeviceToDevice, s->stream) != hipSuccess)
+        return SL_EHIP;
+    }
+    // Later work on the stream runs after the copy, so the memory can be
+    // handed to the next admission right away.
+    arena_free(s, r.off, r.bytes);
+    s->free_entries.push_back(r.entry);
+    sl_destroy_grid(r.grid);
+    s->finished.erase(s->finished.begin() + (long)i);
+    return SL_OK;
+  }
+  return SL_ENOTFOUND;
+}
+
+int sl_server_sync(sl_server* s, sl_stats* out) {
+  if (!s) return SL_EINVAL;
+  unsigned long long host[sl::ST_COUNT];
+  if (hipMemcpyAsync(host, s->stats, sizeof(host), hipMemcpyDeviceToHost, s->stream) !=
+          hipSuccess ||
+      hipMemsetAsync(s->stats, 0, sizeof(host), s->stream) != hipSuccess ||
+      hipStreamSynchronize(s->stream) != hipSuccess)
+    return SL_EHIP;
+  drain_events(s, true, 0);
+  if (out) {
+    memset(out, 0, sizeof(*out));
+    out->search_fail = (int64_t)host[sl::ST_SEARCH_FAIL];
+    out->newton_fail = (int64_t)host[sl::ST_NEWTON_FAIL];
+    out->nonfinite = (int64_t)host[sl::ST_NONFINITE];
+    out->order_hist[0] = (int64_t)host[sl::ST_ORDER0];
+    out->order_hist[1] = (int64_t)host[sl::ST_ORDER1];
+    out->walked = (int64_t)host[sl::ST_WALKED];
+    out->scanned = (int64_t)host[sl::ST_SCANNED];
+  }
+  if (host[sl::ST_SEARCH_FAIL]) return SL_ESEARCH;
+  if (host[sl::ST_NEWTON_FAIL]) return SL_ENEWTON;
+  if (host[sl::ST_NONFINITE]) return SL_ENONFINITE;
+  return SL_OK;
+}
+
+int sl_server_info(const sl_server* s, sl_server_status* out) {
+  if (!s || !out) return SL_EINVAL;
+  out->active = (int)s->active.size();
+  out->finished = (int)s->finished.size();
+  out->bytes_in_use = s->in_use;
+  out->bytes_free = 0;
+  for (const auto& kv : s->free_blocks) out->bytes_free += kv.second;
+  out->ticks = s->tick;
+  out->completed_ticks = s->completed_tick;
+  return SL_OK;
+}
+
+}  // extern "C"

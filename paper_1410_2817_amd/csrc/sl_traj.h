@@ -1,0 +1,117 @@
+// Trajectory integration of the material lattice (Sec. 2, eqs. "momento" and
+// "vel"): one work-item per lattice node, fourth-order Runge-Kutta or the
+// low-storage third-order scheme of Williamson, FP64 displacement in cell
+// units, structure-of-arrays.
+#pragma once
+
+#include "sl_device.h"
+
+namespace sl {
+
+constexpr int kBlock = 256;
+
+template <int D>
+__device__ __forceinline__ void unflatten(const GridArgs& g, int lin, int* idx) {
+  idx[0] = lin % g.n[0];
+  if constexpr (D == 2) {
+    idx[1] = lin / g.n[0];
+  } else {
+    const int q = lin / g.n[0];
+    idx[1] = q % g.n[1];
+    idx[2] = q / g.n[1];
+  }
+}
+
+template <int D>
+__device__ __forceinline__ int flatten(const GridArgs& g, const int* w) {
+  if constexpr (D == 2)
+    return w[0] + g.n[0] * w[1];
+  else
+    return w[0] + g.n[0] * (w[1] + g.n[1] * w[2]);
+}
+
+// ---------------------------------------------------------------------------
+// Trajectories (Sec. 2, eq. "vel").
+
+// Time factors cos(pi t_s / p0) of the periodic families at the stage times,
+// computed on the host (1 for the steady families).
+struct StageTimes {
+  double tf[4];
+};
+
+// Launched on a (ceil(nx/64), ceil(ny/4), nz) grid of 64 x 4 work-items, so
+// node coordinates come without integer division.
+constexpr int kTrajBX = 64, kTrajBY = 4;
+
+// Trajectory of lattice node idx over one step (or one more step when
+// `accumulate` is set).
+template <int D, int VK>
+__device__ __forceinline__ void traj_node(const GridArgs& g, const VelArgs& v,
+                                          double* __restrict__ disp, const StageTimes& st,
+                                          double dt, int accumulate, int integrator,
+                                          const int* idx) {
+  const int lin = flatten<D>(g, idx);
+  double d[D], x[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    d[a] = accumulate ? disp[(size_t)a * g.ntot + lin] : 0.0;
+    x[a] = ((double)idx[a] + d[a]) * g.h[a];
+  }
+  NodeVelocity<VK, D> vel;
+  vel.init(x);
+  if (integrator == SL_RK4) {
+    double k1[D], k2[D], k3[D], k4[D], o[D];
+    vel.eval(v, x, nullptr, st.tf[0], k1);
+#pragma unroll
+    for (int a = 0; a < D; ++a) o[a] = 0.5 * dt * k1[a];
+    vel.eval(v, x, o, st.tf[1], k2);
+#pragma unroll
+    for (int a = 0; a < D; ++a) o[a] = 0.5 * dt * k2[a];
+    vel.eval(v, x, o, st.tf[1], k3);
+#pragma unroll
+    for (int a = 0; a < D; ++a) o[a] = dt * k3[a];
+    vel.eval(v, x, o, st.tf[2], k4);
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+      d[a] += dt * (k1[a] + 2.0 * k2[a] + 2.0 * k3[a] + k4[a]) / 6.0 / g.h[a];
+  } else {
+    // Williamson (1980) 2N-storage RK3: q = A_s q + dt u(x + dx, t + c_s dt),
+    // dx += B_s q with A = (0, -5/9, -153/128), B = (1/3, 15/16, 8/15),
+    // c = (0, 1/3, 3/4).
+    const double A[3] = {0.0, -5.0 / 9.0, -153.0 / 128.0};
+    const double B[3] = {1.0 / 3.0, 15.0 / 16.0, 8.0 / 15.0};
+    double q[D], dx[D], u[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) q[a] = dx[a] = 0.0;
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+      vel.eval(v, x, s == 0 ? nullptr : dx, st.tf[s], u);
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        q[a] = A[s] * q[a] + dt * u[a];
+        dx[a] += B[s] * q[a];
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < D; ++a) d[a] += dx[a] / g.h[a];
+  }
+#pragma unroll
+  for (int a = 0; a < D; ++a) disp[(size_t)a * g.ntot + lin] = d[a];
+}
+
+
+template <int D, int VK>
+__global__ __launch_bounds__(kBlock) void traj_kernel(GridArgs g, VelArgs v,
+                                                      double* __restrict__ disp, StageTimes st,
+                                                      double dt, int accumulate,
+                                                      int integrator) {
+  int idx[D];
+  idx[0] = blockIdx.x * kTrajBX + threadIdx.x;
+  idx[1] = blockIdx.y * kTrajBY + threadIdx.y;
+  if constexpr (D == 3) idx[2] = blockIdx.z;
+  if (idx[0] >= g.n[0] || idx[1] >= g.n[1]) return;
+  traj_node<D, VK>(g, v, disp, st, dt, accumulate, integrator, idx);
+}
+
+
+}  // namespace sl

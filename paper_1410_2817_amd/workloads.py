@@ -268,23 +268,85 @@ SERVING_SIDES = (128, 256, 512, 1024, 2048)
 
 
 @dataclass
+class Component:
+    kind: str            # "gaussian" or "disk"
+    center: tuple
+    size: float          # sigma or radius
+
+
+@dataclass
 class Request:
+    """One serving request.  Field values are built on demand from the drawn
+    components (numpy for the oracle, torch on the device for the server)."""
     rid: int
     arrival: float        # seconds after the stream starts
-    workload: Workload
+    n: int
+    nsteps: int
+    dt: float
+    modes: np.ndarray
+    fields_spec: list     # per field: list of Component
+
+    @property
+    def shape(self):
+        return (self.n, self.n)
+
+    @property
+    def nfields(self):
+        return len(self.fields_spec)
+
+    @property
+    def nodes(self):
+        return self.n * self.n
+
+    def fields(self):
+        out = []
+        for comps in self.fields_spec:
+            f = np.zeros(self.shape)
+            for c in comps:
+                if c.kind == "gaussian":
+                    f += gaussian(self.shape, c.center, c.size)
+                else:
+                    f += disk(self.shape, c.center, c.size)
+            out.append(f)
+        return out
+
+    def fields_torch(self, device, dtype):
+        """The same fields evaluated with torch on `device`."""
+        import torch
+        x = torch.arange(self.n, device=device, dtype=torch.float64) / self.n
+        X = x[None, :]
+        Y = x[:, None]
+        out = []
+        for comps in self.fields_spec:
+            f = torch.zeros(self.shape, device=device, dtype=torch.float64)
+            for c in comps:
+                r2 = (X - c.center[0]) ** 2 + (Y - c.center[1]) ** 2
+                if c.kind == "gaussian":
+                    f += torch.exp(-r2 / (2.0 * c.size * c.size))
+                else:
+                    f += (r2.sqrt() <= c.size).to(torch.float64)
+            out.append(f.to(dtype).contiguous())
+        return out
+
+    @property
+    def workload(self) -> Workload:
+        vel = Velocity(VEL_FOURIER, [1.0], self.modes)
+        return Workload("req%d_%d" % (self.rid, self.n), self.shape, (1.0, 1.0),
+                        self.fields(), vel, dt=self.dt, nsteps=self.nsteps, order_max=2,
+                        limiter=True, value_prec="f32")
 
 
-def _mixture_field(g: np.random.Generator, shape) -> np.ndarray:
-    """Sum of 1-3 components, each a Gaussian (sigma ~ U[0.02, 0.1]) or a
-    step disc (R ~ U[0.05, 0.2]) at a uniform random centre."""
-    f = np.zeros(shape)
+def _components(g: np.random.Generator) -> list:
+    """1-3 components, each a Gaussian (sigma ~ U[0.02, 0.1]) or a step disc
+    (R ~ U[0.05, 0.2]) at a uniform random centre."""
+    comps = []
     for _ in range(int(g.integers(1, 4))):
         c = tuple(g.uniform(0.2, 0.8, 2))
         if g.uniform() < 0.5:
-            f += gaussian(shape, c, g.uniform(0.02, 0.1))
+            comps.append(Component("gaussian", c, float(g.uniform(0.02, 0.1))))
         else:
-            f += disk(shape, c, g.uniform(0.05, 0.2))
-    return f
+            comps.append(Component("disk", c, float(g.uniform(0.05, 0.2))))
+    return comps
 
 
 def serving_request(g: np.random.Generator, rid: int, arrival: float,
@@ -293,15 +355,10 @@ def serving_request(g: np.random.Generator, rid: int, arrival: float,
     n = int(g.choice(np.asarray(sides)))
     nf = int(g.integers(1, 5))
     nsteps = int(g.integers(steps_range[0], steps_range[1] + 1))
-    shape = (n, n)
-    fields = [_mixture_field(g, shape) for _ in range(nf)]
+    spec = [_components(g) for _ in range(nf)]
     modes = fourier_modes(0, 2, gen=g)
     umax = fourier_speed_max(modes, 2)
-    vel = Velocity(VEL_FOURIER, [1.0], modes)
-    wl = Workload("req%d_%d" % (rid, n), shape, (1.0, 1.0), fields, vel,
-                  dt=cfl / (n * umax), nsteps=nsteps, order_max=2, limiter=True,
-                  value_prec="f32")
-    return Request(rid, arrival, wl)
+    return Request(rid, arrival, n, nsteps, cfl / (n * umax), modes, spec)
 
 
 def serving_stream(seed: int = 0, count: int = 512, rate: float = 100.0,

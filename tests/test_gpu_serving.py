@@ -1,0 +1,147 @@
+"""Serving: requests batched by the server give the same bits as each request
+run alone; admission respects the arena budget; a served request matches the
+oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1410_2817_amd import workloads as W
+from tests.util import l1_rel, oracle_problem
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as T
+    if not T.cuda.is_available():
+        pytest.fail("no GPU visible")
+    return T
+
+
+@pytest.fixture(scope="module")
+def S():
+    from paper_1410_2817_amd import serving
+    return serving
+
+
+def _requests(n=6, seed=3):
+    g = W.rng(seed)
+    return [W.serving_request(g, i, 0.0, sides=(64, 96, 128, 200), steps_range=(3, 9))
+            for i in range(n)]
+
+
+def _alone(torch, req):
+    from paper_1410_2817_amd import binding as B
+    g = B.Grid(req.shape, req.nfields, value_prec="f32", order_max=2, limiter=True,
+               vel_kind=W.VEL_FOURIER, vel_params=[1.0], modes=req.modes)
+    x = req.fields_torch(g.device, torch.float32)
+    out = g.advance(x, 0.0, req.dt, req.nsteps)
+    rc, _ = g.sync()
+    assert rc == 0
+    return [f.cpu().numpy() for f in out]
+
+
+def test_mix_equals_alone_bitwise(torch, S):
+    reqs = _requests()
+    say("alone")
+    alone = {r.rid: _alone(torch, r) for r in reqs}
+    say("mix")
+    srv = S.Server(256 << 20, max_requests=8, max_inflight=2)
+    dev = srv.device
+    ids, got = {}, {}
+    # Staggered admissions: three now, the rest after two ticks.
+    for r in reqs[:3]:
+        (desc, _), f = S.request_desc(r), r.fields_torch(dev, torch.float32)
+        ids[srv.admit(desc, f, r.dt, r.nsteps)] = r
+    srv.tick()
+    srv.tick()
+    for r in reqs[3:]:
+        (desc, _), f = S.request_desc(r), r.fields_torch(dev, torch.float32)
+        ids[srv.admit(desc, f, r.dt, r.nsteps)] = r
+    while len(got) < len(reqs):
+        srv.tick()
+        for sid in srv.poll():
+            r = ids[sid]
+            out = [torch.empty(r.shape, dtype=torch.float32, device=dev) for _ in range(r.nfields)]
+            srv.fetch(sid, out)
+            torch.cuda.synchronize()
+            got[r.rid] = [o.cpu().numpy() for o in out]
+    rc, st = srv.sync()
+    assert rc == 0 and st["search_fail"] == 0
+    for r in reqs:
+        for a, b in zip(got[r.rid], alone[r.rid]):
+            assert np.array_equal(a, b), r.rid
+    srv.close()
+
+
+def test_admission_respects_budget(torch, S):
+    reqs = _requests(3, seed=5)
+    desc0, _ = S.request_desc(reqs[0])
+    need = S.Server.request_bytes(desc0)
+    # Room for the descriptor table of two requests, the counters and exactly
+    # one request of this size (plus less than 12 KiB of slack).
+    srv = S.Server(16384 + 256 + need, max_requests=2, max_inflight=1)
+    dev = srv.device
+    f0 = reqs[0].fields_torch(dev, torch.float32)
+    a = srv.admit(desc0, f0, reqs[0].dt, reqs[0].nsteps)
+    assert a is not None
+    big = max(reqs[1:], key=lambda q: q.nodes)
+    (desc1, _), f1 = S.request_desc(big), big.fields_torch(dev, torch.float32)
+    assert S.Server.request_bytes(desc1) > 12 * 1024
+    assert srv.admit(desc1, f1, big.dt, big.nsteps) is None  # no room: SL_EBUSY
+    done = []
+    while not done:
+        srv.tick()
+        done = srv.poll()
+    out = [torch.empty(reqs[0].shape, dtype=torch.float32, device=dev)
+           for _ in range(reqs[0].nfields)]
+    srv.fetch(done[0], out)
+    # Memory came back: a request of the same size fits again.
+    assert srv.admit(desc0, f0, reqs[0].dt, reqs[0].nsteps) is not None
+    info = srv.info()
+    assert info["bytes_in_use"] == need and info["active"] == 1
+    srv.close()
+    # The slot limit binds too.
+    srv = S.Server(64 << 20, max_requests=1)
+    assert srv.admit(desc0, f0, reqs[0].dt, reqs[0].nsteps) is not None
+    assert srv.admit(desc0, f0, reqs[0].dt, reqs[0].nsteps) is None
+    srv.close()
+
+
+def test_served_request_matches_oracle(torch, S, orc):
+    req = W.serving_request(W.rng(11), 0, 0.0, sides=(96,), steps_range=(4, 4))
+    srv = S.Server(64 << 20, max_requests=2)
+    dev = srv.device
+    (desc, _), f = S.request_desc(req), req.fields_torch(dev, torch.float32)
+    stored = [x.double().cpu().numpy() for x in f]
+    sid = srv.admit(desc, f, req.dt, req.nsteps)
+    got = None
+    while got is None:
+        srv.tick()
+        for d in srv.poll():
+            out = [torch.empty(req.shape, dtype=torch.float32, device=dev) for _ in range(req.nfields)]
+            srv.fetch(d, out)
+            got = [o.double().cpu().numpy() for o in out]
+    wl = req.workload
+    wl.fields = stored
+    rc, want, _ = orc.run(oracle_problem(orc, wl), 0.0, wl.dt, wl.nsteps, stored)
+    assert rc == 0
+    for a, b in zip(got, want):
+        assert l1_rel(a, b) <= 1e-5
+    srv.close()
+
+
+def test_stream_driver_completes(torch, S):
+    reqs = W.serving_stream(seed=2, count=24, rate=400.0, sides=(64, 128, 256),
+                            steps_range=(5, 12))
+    rep = S.run_stream(reqs, 64 << 20, max_requests=16)
+    say(rep)
+    assert rep["status"] == 0 and rep["requests"] == 24
+    assert rep["latency_p99_ms"] >= rep["latency_p50_ms"] > 0
