@@ -108,6 +108,10 @@ def parse():
     ap.add_argument("--n", type=int, default=1024, help="grid side")
     ap.add_argument("--prec", default="f32", choices=["f32", "f64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="skip the serving (continuous batching) measurement")
+    ap.add_argument("--serving-requests", type=int, default=512)
+    ap.add_argument("--serving-budget-gib", type=float, default=8.0)
     ap.add_argument("--no-events", action="store_true",
                     help="time without per-launch kernel events")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
@@ -231,9 +235,35 @@ def main():
         "kernels": {"trajectories_avg_ms": traj_ms, "reconstruction_avg_ms": recon_ms},
         "accuracy": acc,
     }
+    if not args.no_serving:
+        out["serving"] = run_serving(args.serving_requests, args.serving_budget_gib)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = run_cpu_baseline(wl, stored, args.cpu_seconds)
     print(json.dumps(out), flush=True)
+
+
+def run_serving(count: int, budget_gib: float):
+    """Serving mix: `count` seeded requests (2-D periodic grids with sides in
+    {128, ..., 2048}, 1-4 fields, 10-50 steps of a 16-mode Fourier flow, FP32
+    values / FP64 positions) through the continuous-batching server with an
+    HBM budget of `budget_gib`.  First all requests arrive at once (capacity),
+    then with Poisson arrivals at 0.7 x that capacity (latency)."""
+    from paper_1410_2817_amd import serving as S
+    from paper_1410_2817_amd import workloads as W
+    budget = int(budget_gib * (1 << 30))
+    burst = W.serving_stream(seed=0, count=count, rate=1e9)
+    for r in burst:
+        r.arrival = 0.0
+    cap = S.run_stream(burst, budget, max_requests=256)
+    rate = 0.7 * count / cap["makespan_s"]
+    rep = S.run_stream(W.serving_stream(seed=0, count=count, rate=rate), budget,
+                       max_requests=256)
+    keep = ("latency_p50_ms", "latency_p99_ms", "latency_mean_ms", "queue_wait_p50_ms",
+            "queue_wait_p99_ms", "node_updates_per_s", "makespan_s", "ticks", "status")
+    return {"requests": count, "budget_gib": budget_gib,
+            "capacity_node_updates_per_s": cap["node_updates_per_s"],
+            "capacity_requests_per_s": count / cap["makespan_s"],
+            "poisson_rate_per_s": rate, **{k: rep[k] for k in keep}}
 
 
 def run_cpu_baseline(wl, stored, seconds):
