@@ -4,11 +4,14 @@
 //   traj_kernel   one work-item per lattice node integrates its trajectory
 //                 (RK4 or Williamson's low-storage RK3) and stores the FP64
 //                 displacement in cell units, structure-of-arrays;
-//   flags_kernel  jump flags of Sec. 2.3, one bit per field per lattice node;
-//   recon_kernel  one work-item per mesh node: host-element walk + Newton on
-//                 the multilinear element map (eq. "mapping1"), order
-//                 selection from the flags, cardinal Z-spline weights
-//                 (Appendix) and the tensor-product gather-sum (eq. "multiZ").
+//   reconstruction, one work-item per mesh node: host-element walk + Newton
+//                 on the multilinear element map (eq. "mapping1"), order
+//                 selection from the jump flags of Sec. 2.3, cardinal
+//                 Z-spline weights (Appendix) and the tensor-product
+//                 gather-sum (eq. "multiZ").  2-D grids use the LDS-tiled
+//                 kernel of sl_recon2d.h; 3-D grids compute the flags here
+//                 (flags_kernel), reduce them to per-cell order words and run
+//                 the kernel of sl_recon3d.h.
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
@@ -26,6 +29,7 @@
 #include "sl_device.h"
 #include "sl_launch.h"
 #include "sl_recon2d.h"
+#include "sl_recon3d.h"
 #include "sl_traj.h"
 
 namespace sl {
@@ -61,136 +65,6 @@ __global__ __launch_bounds__(kBlock) void flags_kernel(GridArgs g, FieldPtrs fp,
     bits |= (fl ? 1u : 0u) << f;
   }
   flags[lin] = (uint8_t)bits;
-}
-
-// ---------------------------------------------------------------------------
-// Reconstruction (Sec. 2.1-2.3).
-
-// Displacement of the lattice node with unwrapped index v, from global memory.
-template <int D>
-struct GlobalDisp {
-  const double* __restrict__ disp;
-  GridArgs g;
-  __device__ __forceinline__ void operator()(const int* v, double* d) const {
-    int w[D];
-#pragma unroll
-    for (int a = 0; a < D; ++a) w[a] = wrap_index(v[a], g.n[a]);
-    const int lin = flatten<D>(g, w);
-#pragma unroll
-    for (int a = 0; a < D; ++a) d[a] = disp[(size_t)a * g.ntot + lin];
-  }
-};
-
-template <int D, typename T>
-__global__ __launch_bounds__(kBlock) void recon_kernel(GridArgs g, FieldPtrs fp,
-                                                       const double* __restrict__ disp,
-                                                       const uint8_t* __restrict__ flags,
-                                                       unsigned long long* __restrict__ stats) {
-  const int lin = blockIdx.x * kBlock + threadIdx.x;
-  if (lin >= g.ntot) return;
-  int tgt[D];
-  unflatten<D>(g, lin, tgt);
-  int r[D];
-  double xi[D], d0[D];
-  int walked = 0;
-  const GlobalDisp<D> gd{disp, g};
-  gd(tgt, d0);
-  const int loc = locate<D>(g, gd, tgt, d0, r, xi, walked);
-  wave_count(stats + ST_SEARCH_FAIL, loc == LOC_SEARCH_FAIL);
-  wave_count(stats + ST_NEWTON_FAIL, loc == LOC_NEWTON_FAIL);
-  wave_count(stats + ST_WALKED, walked != 0);
-  wave_count(stats + ST_SCANNED, walked == 2);
-  if (loc != LOC_OK) {
-    for (int f = 0; f < g.nfields; ++f) static_cast<T*>(fp.out[f])[lin] = T(NAN);
-    return;
-  }
-  // Wrapped stencil indices, slot s <-> node r - 2 + s.
-  int ix[D][6];
-#pragma unroll
-  for (int a = 0; a < D; ++a) {
-    int w = wrap_index(r[a] - 2, g.n[a]);
-#pragma unroll
-    for (int s = 0; s < 6; ++s) {
-      ix[a][s] = w;
-      w = (w + 1 == g.n[a]) ? 0 : w + 1;
-    }
-  }
-  const int sy = g.n[0], sz = g.n[0] * g.n[1];
-  // Flags in the quintic (6^D) and cubic (4^D) stencils.
-  unsigned or6 = 0, or4 = 0;
-  if (g.limiter && g.order_max > 0) {
-    if constexpr (D == 2) {
-#pragma unroll
-      for (int ky = 0; ky < 6; ++ky)
-#pragma unroll
-        for (int kx = 0; kx < 6; ++kx) {
-          const unsigned fb = flags[ix[0][kx] + sy * ix[1][ky]];
-          or6 |= fb;
-          if (kx >= 1 && kx <= 4 && ky >= 1 && ky <= 4) or4 |= fb;
-        }
-    } else {
-      for (int kz = 0; kz < 6; ++kz)
-#pragma unroll
-        for (int ky = 0; ky < 6; ++ky)
-#pragma unroll
-          for (int kx = 0; kx < 6; ++kx) {
-            const unsigned fb = flags[ix[0][kx] + sy * ix[1][ky] + sz * ix[2][kz]];
-            or6 |= fb;
-            if (kx >= 1 && kx <= 4 && ky >= 1 && ky <= 4 && kz >= 1 && kz <= 4) or4 |= fb;
-          }
-    }
-  }
-  T t[D];
-#pragma unroll
-  for (int a = 0; a < D; ++a) t[a] = (T)xi[a];
-  T w[D][6];
-  int wm = -1;
-  int cnt0 = 0, cnt1 = 0, bad = 0;
-  for (int f = 0; f < g.nfields; ++f) {
-    int m = g.order_max;
-    if (m == 2 && ((or6 >> f) & 1u)) m = 1;
-    if (m == 1 && ((or4 >> f) & 1u)) m = 0;
-    cnt0 += m == 0;
-    cnt1 += m == 1;
-    if (m != wm) {
-#pragma unroll
-      for (int a = 0; a < D; ++a) zspline_weights<T>(m, t[a], w[a]);
-      wm = m;
-    }
-    const T* __restrict__ h = static_cast<const T*>(fp.in[f]);
-    T acc = T(0);
-    if constexpr (D == 2) {
-#pragma unroll
-      for (int ky = 0; ky < 6; ++ky) {
-        const T* row = h + (size_t)sy * ix[1][ky];
-        T s = T(0);
-#pragma unroll
-        for (int kx = 0; kx < 6; ++kx) s = fma(row[ix[0][kx]], w[0][kx], s);
-        acc = fma(s, w[1][ky], acc);
-      }
-    } else {
-      for (int kz = 0; kz < 6; ++kz) {
-        T pl = T(0);
-#pragma unroll
-        for (int ky = 0; ky < 6; ++ky) {
-          const T* row = h + (size_t)sz * ix[2][kz] + (size_t)sy * ix[1][ky];
-          T s = T(0);
-#pragma unroll
-          for (int kx = 0; kx < 6; ++kx) s = fma(row[ix[0][kx]], w[0][kx], s);
-          pl = fma(s, w[1][ky], pl);
-        }
-        acc = fma(pl, w[2][kz], acc);
-      }
-    }
-    bad += !isfinite(acc);
-    static_cast<T*>(fp.out[f])[lin] = acc;
-  }
-  // Per-field order counts: lanes contribute their counts one field at a time.
-  for (int f = 0; f < g.nfields; ++f) {
-    wave_count(stats + ST_ORDER0, f < cnt0);
-    wave_count(stats + ST_ORDER1, f < cnt1);
-    wave_count(stats + ST_NONFINITE, f < bad);
-  }
 }
 
 __global__ void zero_kernel(unsigned long long* p, int n) {
@@ -386,16 +260,56 @@ hipError_t launch_recon(sl_grid* gr, const sl::FieldPtrs& fp, char* ws, hipStrea
     }
 #undef SL_RECON2D
   } else {
-    const dim3 blocks((unsigned)((gr->ntot + sl::kBlock - 1) / sl::kBlock)), threads(sl::kBlock);
-    uint8_t* flags = reinterpret_cast<uint8_t*>(ws + gr->off_flags);
-    if (gr->g.limiter && gr->g.order_max > 0) {
-      const hipError_t e = launch(sl::flags_kernel<D, T>, blocks, threads, 0, s, e0, nullptr,
-                                  gr->g, fp, flags);
+    using C = sl::Tile3D;
+    const bool lim = gr->g.limiter && gr->g.order_max > 0;
+    const uint16_t* ord = nullptr;
+    if (lim) {
+      uint8_t* flags = reinterpret_cast<uint8_t*>(ws + gr->off_flags);
+      uint16_t* wa = reinterpret_cast<uint16_t*>(ws + gr->off_ord);
+      uint16_t* wb = wa + gr->ntot;
+      const dim3 fb((unsigned)((gr->ntot + sl::kBlock - 1) / sl::kBlock)), ft(sl::kBlock);
+      hipError_t e = launch(sl::flags_kernel<D, T>, fb, ft, 0, s, e0, nullptr, gr->g, fp, flags);
+      const dim3 wbk((unsigned)((gr->g.n[0] + 63) / 64), (unsigned)((gr->g.n[1] + 3) / 4),
+                     (unsigned)gr->g.n[2]);
+      const dim3 wt(64, 4);
+      if (e == hipSuccess)
+        e = launch(sl::window_or_kernel<0>, wbk, wt, 0, s, nullptr, nullptr, gr->g,
+                   (const uint8_t*)flags, (const uint16_t*)nullptr, wa);
+      if (e == hipSuccess)
+        e = launch(sl::window_or_kernel<1>, wbk, wt, 0, s, nullptr, nullptr, gr->g,
+                   (const uint8_t*)nullptr, (const uint16_t*)wa, wb);
+      if (e == hipSuccess)
+        e = launch(sl::window_or_kernel<2>, wbk, wt, 0, s, nullptr, nullptr, gr->g,
+                   (const uint8_t*)nullptr, (const uint16_t*)wb, wa);
       if (e != hipSuccess) return e;
       e0 = nullptr;
+      ord = wa;
     }
-    return launch(sl::recon_kernel<D, T>, blocks, threads, 0, s, e0, e1, gr->g, fp,
-                  (const double*)disp, (const uint8_t*)flags, stats);
+    const int tiles_x = (gr->g.n[0] + C::TX - 1) / C::TX;
+    const int tiles_y = (gr->g.n[1] + C::TY - 1) / C::TY;
+    const int tiles_z = (gr->g.n[2] + C::TZ - 1) / C::TZ;
+    const int ntiles = tiles_x * tiles_y * tiles_z;
+    // Buffer offsets are signed 32-bit byte offsets within one field.
+    const int buf_ok = (size_t)gr->ntot * sizeof(T) <= (size_t)INT32_MAX;
+    const int dbuf_ok = (size_t)gr->ntot * sizeof(double) <= (size_t)INT32_MAX;
+    const dim3 grid(ntiles), block(sl::kTileThreads);
+#define SL_RECON3D(NF)                                                                       \
+  case NF:                                                                                   \
+    return launch(sl::recon3d_kernel<T, NF>, grid, block, 0, s, e0, e1, gr->g, fp, disp, ord, \
+                  stats, tiles_x, tiles_y, ntiles, buf_ok, dbuf_ok);
+    switch (gr->g.nfields) {
+      SL_RECON3D(1)
+      SL_RECON3D(2)
+      SL_RECON3D(3)
+      SL_RECON3D(4)
+      SL_RECON3D(5)
+      SL_RECON3D(6)
+      SL_RECON3D(7)
+      default:
+        return launch(sl::recon3d_kernel<T, 8>, grid, block, 0, s, e0, e1, gr->g, fp, disp, ord,
+                      stats, tiles_x, tiles_y, ntiles, buf_ok, dbuf_ok);
+    }
+#undef SL_RECON3D
   }
 }
 
@@ -490,7 +404,9 @@ int sl_create_grid(const sl_grid_desc* desc, sl_grid** out) {
   gr->off_stats = 0;
   gr->off_disp = align_up(kStatsBytes);
   gr->off_flags = align_up(gr->off_disp + sizeof(double) * (size_t)D * (size_t)gr->ntot);
-  gr->ws_bytes = align_up(gr->off_flags + (size_t)gr->ntot);
+  // 3-D grids also hold two 16-bit window words per node (ping-pong).
+  gr->off_ord = align_up(gr->off_flags + (size_t)gr->ntot);
+  gr->ws_bytes = D == 3 ? align_up(gr->off_ord + 4 * (size_t)gr->ntot) : gr->off_ord;
   gr->steps_since_reset = 0;
   *out = gr;
   return SL_OK;

@@ -279,17 +279,37 @@ __device__ __forceinline__ void zspline_weights(int m, T t, T* w) {
 // about vertex r gives the finite series of eq. "mapping1":
 //   F(xi) = V0 + sum_a A_a xi_a + sum_{a<b} B_ab xi_a xi_b (+ C xi_0 xi_1 xi_2).
 // Newton's method solves F = 0 starting from the root of the linear part.
-// Returns 1 if Newton converged (xi = solution), 0 if only the linear root is
-// available (xi = that), -1 if the linear part is singular.
+// solve() returns 1 if Newton converged (xi = solution), 0 if only the linear
+// root is available (xi = that), -1 if the linear part is singular.
+//
+// Reciprocals are the hardware estimate refined by one Newton-Raphson step
+// (exact for powers of two; the next Newton iteration absorbs any residual).
+// The first kFastNewton iterations run unconditionally; more run while any
+// lane of the wave has not converged, up to newton_max_iter in all.  A lane
+// has converged once one of its steps is within newton_tol; later iterations
+// only move it by rounding.  A singular Jacobian or a non-finite iterate
+// leaves NaNs, which report non-convergence.
 
 template <int D>
 struct Element;
 
-// Newton iterations run unconditionally by the fast path.  In a cell whose
-// element is close to a parallelogram (the common case) Newton from the
-// linear root converges in about three; further iterations only add
-// rounding-level corrections.
+// In a cell whose element is close to a parallelogram (the common case)
+// Newton from the linear root converges in about three iterations.
 constexpr int kFastNewton = 3;
+
+__device__ __forceinline__ double rcp_refined(double d) {
+  const double r = __builtin_amdgcn_rcp(d);
+  return fma(r, fma(-d, r, 1.0), r);
+}
+
+// Runs `iterate` (which updates `conv`) as described above.
+template <class Iter>
+__device__ __forceinline__ void newton_loop(const GridArgs& g, bool& conv, const Iter& iterate) {
+#pragma unroll
+  for (int it = 0; it < kFastNewton; ++it)
+    if (it < g.newton_max_iter) iterate();
+  for (int it = kFastNewton; it < g.newton_max_iter && __ballot(!conv) != 0ull; ++it) iterate();
+}
 
 template <>
 struct Element<2> {
@@ -305,41 +325,34 @@ struct Element<2> {
   }
 
   __device__ __forceinline__ int solve(const GridArgs& g, double* xi) const {
-    double det = a[0] * b[1] - b[0] * a[1];
+    const double det = a[0] * b[1] - b[0] * a[1];
     if (!(det != 0.0) || !isfinite(det)) return -1;
-    double inv = 1.0 / det;
+    const double inv = rcp_refined(det);
     const double xl = (-v0[0] * b[1] + b[0] * v0[1]) * inv;
     const double yl = (-a[0] * v0[1] + v0[0] * a[1]) * inv;
     double x = xl, y = yl;
-    for (int it = 0; it < g.newton_max_iter; ++it) {
+    bool conv = false;
+    newton_loop(g, conv, [&]() {
       const double f0 = v0[0] + a[0] * x + b[0] * y + c[0] * (x * y);
       const double f1 = v0[1] + a[1] * x + b[1] * y + c[1] * (x * y);
       const double j00 = a[0] + c[0] * y, j01 = b[0] + c[0] * x;
       const double j10 = a[1] + c[1] * y, j11 = b[1] + c[1] * x;
-      const double dj = j00 * j11 - j01 * j10;
-      if (!(dj != 0.0) || !isfinite(dj)) break;
-      const double ij = 1.0 / dj;
+      const double ij = rcp_refined(j00 * j11 - j01 * j10);
       const double dx = (f0 * j11 - j01 * f1) * ij;
       const double dy = (j00 * f1 - f0 * j10) * ij;
       x -= dx;
       y -= dy;
-      const double mx = fmax(fabs(dx), fabs(dy));
-      if (!isfinite(mx)) break;
-      if (mx <= g.newton_tol) {
-        xi[0] = x;
-        xi[1] = y;
-        return 1;
-      }
+      conv = conv || fmax(fabs(dx), fabs(dy)) <= g.newton_tol;
+    });
+    if (conv && isfinite(x) && isfinite(y)) {
+      xi[0] = x;
+      xi[1] = y;
+      return 1;
     }
     xi[0] = xl;
     xi[1] = yl;
     return 0;
   }
-
-  // kFastNewton iterations without early exit, then more while any lane of
-  // the wave is unconverged; true if one of them moved by at most the
-  // tolerance (then xi is the converged root).
-  __device__ __forceinline__ bool solve_fixed(const GridArgs& g, double* xi) const;
 };
 
 template <>
@@ -360,32 +373,32 @@ struct Element<3> {
     }
   }
 
-  // Solve M d = f for the 3x3 matrix with columns c0, c1, c2 (Cramer).
-  __device__ __forceinline__ static bool solve3(const double* c0, const double* c1,
-                                                const double* c2, const double* f,
-                                                double* d) {
-    const double x12[3] = {c1[1] * c2[2] - c1[2] * c2[1], c1[2] * c2[0] - c1[0] * c2[2],
-                           c1[0] * c2[1] - c1[1] * c2[0]};
-    const double det = c0[0] * x12[0] + c0[1] * x12[1] + c0[2] * x12[2];
-    if (!(det != 0.0) || !isfinite(det)) return false;
-    const double x20[3] = {c2[1] * c0[2] - c2[2] * c0[1], c2[2] * c0[0] - c2[0] * c0[2],
-                           c2[0] * c0[1] - c2[1] * c0[0]};
-    const double x01[3] = {c0[1] * c1[2] - c0[2] * c1[1], c0[2] * c1[0] - c0[0] * c1[2],
-                           c0[0] * c1[1] - c0[1] * c1[0]};
-    const double inv = 1.0 / det;
-    d[0] = (f[0] * x12[0] + f[1] * x12[1] + f[2] * x12[2]) * inv;
-    d[1] = (f[0] * x20[0] + f[1] * x20[1] + f[2] * x20[2]) * inv;
-    d[2] = (f[0] * x01[0] + f[1] * x01[1] + f[2] * x01[2]) * inv;
-    return true;
+  __device__ __forceinline__ static void cross(const double* p, const double* q, double* o) {
+    o[0] = p[1] * q[2] - p[2] * q[1];
+    o[1] = p[2] * q[0] - p[0] * q[2];
+    o[2] = p[0] * q[1] - p[1] * q[0];
   }
 
+  __device__ __forceinline__ static double dot(const double* p, const double* q) {
+    return p[0] * q[0] + p[1] * q[1] + p[2] * q[2];
+  }
+
+  // Linear systems by Cramer's rule: M d = f for M with columns (c0, c1, c2)
+  // is d_k = f . (c_{k+1} x c_{k+2}) / det.
   __device__ __forceinline__ int solve(const GridArgs& g, double* xi) const {
-    const double mv0[3] = {-v0[0], -v0[1], -v0[2]};
-    double xl[3];
-    if (!solve3(a, b, c, mv0, xl)) return -1;
-    double x = xl[0], y = xl[1], z = xl[2];
-    for (int it = 0; it < g.newton_max_iter; ++it) {
+    double x12[3], x20[3], x01[3];
+    cross(b, c, x12);
+    cross(c, a, x20);
+    cross(a, b, x01);
+    const double det = dot(a, x12);
+    if (!(det != 0.0) || !isfinite(det)) return -1;
+    const double inv = rcp_refined(det);
+    const double xl = -dot(v0, x12) * inv, yl = -dot(v0, x20) * inv, zl = -dot(v0, x01) * inv;
+    double x = xl, y = yl, z = zl;
+    bool conv = false;
+    newton_loop(g, conv, [&]() {
       double f[3], j0[3], j1[3], j2[3];
+#pragma unroll
       for (int i = 0; i < 3; ++i) {
         f[i] = v0[i] + a[i] * x + b[i] * y + c[i] * z + ab[i] * (x * y) + ac[i] * (x * z) +
                bc[i] * (y * z) + abc[i] * (x * y * z);
@@ -393,71 +406,44 @@ struct Element<3> {
         j1[i] = b[i] + ab[i] * x + bc[i] * z + abc[i] * (x * z);
         j2[i] = c[i] + ac[i] * x + bc[i] * y + abc[i] * (x * y);
       }
-      double dl[3];
-      if (!solve3(j0, j1, j2, f, dl)) break;
-      x -= dl[0];
-      y -= dl[1];
-      z -= dl[2];
-      const double mx = fmax(fabs(dl[0]), fmax(fabs(dl[1]), fabs(dl[2])));
-      if (!isfinite(mx)) break;
-      if (mx <= g.newton_tol) {
-        xi[0] = x;
-        xi[1] = y;
-        xi[2] = z;
-        return 1;
-      }
+      double k12[3], k20[3], k01[3];
+      cross(j1, j2, k12);
+      cross(j2, j0, k20);
+      cross(j0, j1, k01);
+      const double ij = rcp_refined(dot(j0, k12));
+      const double dx = dot(f, k12) * ij, dy = dot(f, k20) * ij, dz = dot(f, k01) * ij;
+      x -= dx;
+      y -= dy;
+      z -= dz;
+      conv = conv || fmax(fabs(dx), fmax(fabs(dy), fabs(dz))) <= g.newton_tol;
+    });
+    if (conv && isfinite(x) && isfinite(y) && isfinite(z)) {
+      xi[0] = x;
+      xi[1] = y;
+      xi[2] = z;
+      return 1;
     }
-    xi[0] = xl[0];
-    xi[1] = xl[1];
-    xi[2] = xl[2];
+    xi[0] = xl;
+    xi[1] = yl;
+    xi[2] = zl;
     return 0;
   }
 };
 
-// Reciprocal for the fixed-iteration Newton path: the hardware estimate
-// refined by one Newton-Raphson step (exact for powers of two; any residual
-// error is absorbed by the next Newton iteration).  A zero argument yields a
-// NaN, which fails the acceptance test.
-__device__ __forceinline__ double rcp_refined(double d) {
-  const double r = __builtin_amdgcn_rcp(d);
-  return fma(r, fma(-d, r, 1.0), r);
-}
-
-__device__ __forceinline__ bool Element<2>::solve_fixed(const GridArgs& g, double* xi) const {
-  const double det = a[0] * b[1] - b[0] * a[1];
-  const double inv = rcp_refined(det);
-  double x = (-v0[0] * b[1] + b[0] * v0[1]) * inv;
-  double y = (-a[0] * v0[1] + v0[0] * a[1]) * inv;
-  bool conv = false;
-  auto iterate = [&]() {
-    const double f0 = v0[0] + a[0] * x + b[0] * y + c[0] * (x * y);
-    const double f1 = v0[1] + a[1] * x + b[1] * y + c[1] * (x * y);
-    const double j00 = a[0] + c[0] * y, j01 = b[0] + c[0] * x;
-    const double j10 = a[1] + c[1] * y, j11 = b[1] + c[1] * x;
-    const double ij = rcp_refined(j00 * j11 - j01 * j10);
-    const double dx = (f0 * j11 - j01 * f1) * ij;
-    const double dy = (j00 * f1 - f0 * j10) * ij;
-    x -= dx;
-    y -= dy;
-    conv = conv || fmax(fabs(dx), fabs(dy)) <= g.newton_tol;
-  };
-#pragma unroll
-  for (int it = 0; it < kFastNewton; ++it) iterate();
-  // Continue while any lane of the wave has not converged (a wave-uniform
-  // loop; lanes that have converged only pick up rounding-level steps).
-  for (int it = kFastNewton; it < g.newton_max_iter && __ballot(!conv) != 0ull; ++it)
-    iterate();
-  xi[0] = x;
-  xi[1] = y;
-  // A singular or non-finite system leaves NaNs, which fail the cube test.
-  return conv && det != 0.0 && isfinite(x) && isfinite(y);
-}
-
 // Result codes of locate().
 enum { LOC_OK = 0, LOC_SEARCH_FAIL = 1, LOC_NEWTON_FAIL = 2 };
 
+template <int D>
+__device__ __forceinline__ bool in_cube(const GridArgs& g, const double* xi) {
+  bool ok = true;
+#pragma unroll
+  for (int a = 0; a < D; ++a) ok = ok && (xi[a] >= -g.eps) && (xi[a] <= 1.0 + g.eps);
+  return ok;
+}
+
 // Element with lower vertex r for target mesh node tgt; `disp(v, d)` returns
 // the displacement (cells) of the lattice node with unwrapped index v.
+// Returns Element::solve's code.
 template <int D, class DispFn>
 __device__ __forceinline__ int element_solve(const GridArgs& g, const DispFn& disp,
                                              const int* tgt, const int* r, double* xi) {
@@ -477,60 +463,31 @@ __device__ __forceinline__ int element_solve(const GridArgs& g, const DispFn& di
   return el.solve(g, xi);
 }
 
-template <int D>
-__device__ __forceinline__ bool in_cube(const GridArgs& g, const double* xi);
-
-// Start-cell attempt with kFastNewton unconditional Newton iterations (no
-// data-dependent branches).  True when Newton converged (some iteration's
-// step was within tolerance) to a point of the unit cube: the same acceptance
-// test locate() applies to its first cell.
-template <int D, class DispFn>
-__device__ __forceinline__ bool element_solve_fast(const GridArgs& g, const DispFn& disp,
-                                                   const int* tgt, const int* r, double* xi) {
-  double V[1 << D][D];
-#pragma unroll
-  for (int e = 0; e < (1 << D); ++e) {
-    int v[D];
-#pragma unroll
-    for (int a = 0; a < D; ++a) v[a] = r[a] + ((e >> a) & 1);
-    double d[D];
-    disp(v, d);
-#pragma unroll
-    for (int a = 0; a < D; ++a) V[e][a] = (double)(v[a] - tgt[a]) + d[a];
-  }
-  Element<D> el;
-  el.set(V);
-  return el.solve_fixed(g, xi) && in_cube<D>(g, xi);
-}
-
-template <int D>
-__device__ __forceinline__ bool in_cube(const GridArgs& g, const double* xi) {
-  bool ok = true;
-#pragma unroll
-  for (int a = 0; a < D; ++a) ok = ok && (xi[a] >= -g.eps) && (xi[a] <= 1.0 + g.eps);
-  return ok;
-}
-
-// Host-element search (Sec. 2.2): start in the cell below tgt - d(tgt), move
-// one cell per axis toward the side an out-of-range local coordinate points
-// to.  A cell is accepted only when Newton converges inside its unit cube;
-// when Newton does not converge the linear root points the way.  If the walk
-// stalls (linear root inside, Newton not converging) or does not settle within
-// walk_max moves, the cells of the box of half-width scan_radius around the
-// start cell are tried in order, x fastest.  `walked` reports 0 (start cell),
-// 1 (walked), 2 (fallback scan).
-// d0 is the displacement of the lattice node with the target's own index.
-template <int D, class DispFn>
-__device__ __forceinline__ int locate(const GridArgs& g, const DispFn& disp, const int* tgt,
-                                      const double* d0, int* r, double* xi, int& walked) {
+// Host-element search (Sec. 2.2) after the first attempt: rc0 / x0 are the
+// solve result in the start cell r (the cell below tgt - d(tgt)).  The search
+// moves one cell per axis toward the side an out-of-range local coordinate
+// points to.  A cell is accepted only when Newton converges inside its unit
+// cube; when Newton does not converge the linear root points the way.  If
+// the walk stalls (linear root inside, Newton not converging) or does not
+// settle within walk_max moves, the cells of the box of half-width
+// scan_radius around the start cell are tried in order, x fastest.
+// `solve(r, x)` solves in cell r (Element::solve's code).  On return r is the
+// host cell; `walked` reports 0 (start cell), 1 (walked), 2 (fallback scan).
+template <int D, class SolveFn>
+__device__ __forceinline__ int locate_from(const GridArgs& g, const SolveFn& solve, int rc0,
+                                           const double* x0, int* r, double* xi, int& walked) {
   int start[D];
+  double x[D];
 #pragma unroll
-  for (int a = 0; a < D; ++a) start[a] = r[a] = (int)floor((double)tgt[a] - d0[a]);
+  for (int a = 0; a < D; ++a) {
+    start[a] = r[a];
+    x[a] = x0[a];
+  }
   walked = 0;
   bool newton_trouble = false;
+  int rc = rc0;
   for (int walk = 0; walk < g.walk_max; ++walk) {
-    double x[D];
-    const int rc = element_solve<D>(g, disp, tgt, r, x);
+    if (walk > 0) rc = solve(r, x);
     if (rc < 0) break;
     if (in_cube<D>(g, x)) {
       if (rc == 1) {
@@ -555,8 +512,7 @@ __device__ __forceinline__ int locate(const GridArgs& g, const DispFn& disp, con
       r[a] = start[a] - W + qq % span;
       qq /= span;
     }
-    double x[D];
-    const int rc = element_solve<D>(g, disp, tgt, r, x);
+    rc = solve(r, x);
     if (rc >= 0 && in_cube<D>(g, x)) {
       if (rc == 1) {
 #pragma unroll

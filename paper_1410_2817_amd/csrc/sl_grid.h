@@ -20,7 +20,7 @@ struct sl_grid {
   sl::GridArgs g;
   sl::VelArgs v;
   int64_t ntot;
-  size_t off_stats, off_disp, off_flags, ws_bytes;
+  size_t off_stats, off_disp, off_flags, off_ord, ws_bytes;
   int steps_since_reset;
   int64_t steps_launched, reconstructs_launched;
   // Kernel timing with events attached to the dispatch packets.

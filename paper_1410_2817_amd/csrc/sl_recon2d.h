@@ -355,8 +355,13 @@ __device__ __forceinline__ void recon2d_tile(const GridArgs& g, const FieldPtrs&
     double xi[2];
     int walked = 0;
     int loc = LOC_OK;
-    if (!element_solve_fast<2>(g, acc, tgt, r, xi)) {
-      loc = locate<2>(g, acc, tgt, d0[k], r, xi, walked);
+    const auto solve = [&](const int* rr, double* x) {
+      return element_solve<2>(g, acc, tgt, rr, x);
+    };
+    const int rc0 = solve(r, xi);
+    if (rc0 != 1 || !in_cube<2>(g, xi)) {
+      const double x0[2] = {xi[0], xi[1]};
+      loc = locate_from<2>(g, solve, rc0, x0, r, xi, walked);
     }
     walked_any += walked != 0;
     scanned_any += walked == 2;
@@ -412,6 +417,8 @@ __device__ __forceinline__ void recon2d_tile(const GridArgs& g, const FieldPtrs&
       static_cast<T*>(fp.out[f])[lin] = v;
     };
     if (__ballot(low) == 0ull) {
+      c0 += g.order_max == 0 ? nf : 0;
+      c1 += g.order_max == 1 ? nf : 0;
 #pragma unroll
       for (int f = 0; f < nf; ++f) field_value(f, w2x, w2y);
     } else {

@@ -141,6 +141,10 @@ def _step_cases():
     yield "fourier3d_f32", W.fourier3d_three_fields(20, value_prec="f32"), 0.0
     yield "deform3d_f64", W.deform3d_slotted_sphere(24), 0.5
     yield "deform3d_f32", W.deform3d_slotted_sphere(24, value_prec="f32"), 0.5
+    # Several full tiles (interior waves take the buffer-load gather) plus a
+    # ragged edge tile in every axis.
+    yield "fourier3d_f32_50", W.fourier3d_three_fields(50, value_prec="f32"), 0.0
+    yield "deform3d_f64_42", W.deform3d_slotted_sphere(42), 1.0
 
 
 @pytest.mark.parametrize("name,wl,t0", list(_step_cases()))
@@ -315,3 +319,31 @@ def test_full_size_swirl_sampled(B, torch, orc):
         err = np.abs(got - vals[:, f]).max()
         say("  field", f, "max abs err", err)
         assert err <= 1e-5 * max(1.0, np.abs(vals[:, f]).max())
+
+
+@pytest.mark.parametrize("which", ["fourier256_f32", "deform512_f64"])
+def test_full_size_3d_sampled(B, torch, orc, which):
+    """The 3-D workloads at full size (256^3 three fields FP32, 512^3 one
+    field FP64): one GPU step, checked at sampled nodes (random ones and
+    nodes next to the slotted sphere's surface) that the oracle evaluates one
+    by one."""
+    if which == "fourier256_f32":
+        wl, t0 = W.fourier3d_three_fields(256, value_prec="f32"), 0.0
+    else:
+        wl, t0 = W.deform3d_slotted_sphere(512), 0.7
+    say("full size", which)
+    out, st, rc, _ = gpu_run(B, torch, wl, nsteps=1, t0=t0)
+    assert rc == 0 and st["search_fail"] == 0 and st["newton_fail"] == 0
+    g = np.random.Generator(np.random.PCG64(11))
+    n = wl.nodes
+    edge = np.nonzero(np.abs(np.diff(wl.fields[0].ravel(), append=0.0)) > 0)[0]
+    sample = np.unique(np.concatenate([g.integers(0, n, 2000), g.choice(edge, 1000)]))
+    rc2, vals, ost = orc.step_sampled(oracle_problem(orc, wl), t0, wl.dt,
+                                      stored_values(wl), sample)
+    assert rc2 == 0
+    rel = 1e-5 if wl.value_prec == "f32" else 1e-12
+    for f in range(wl.nfields):
+        got = out[f].ravel()[sample]
+        err = np.abs(got - vals[:, f]).max()
+        say("  field", f, "max abs err", err)
+        assert err <= rel * max(1.0, np.abs(vals[:, f]).max())
