@@ -112,6 +112,8 @@ def parse():
                     help="skip the serving (continuous batching) measurement")
     ap.add_argument("--serving-requests", type=int, default=512)
     ap.add_argument("--serving-budget-gib", type=float, default=8.0)
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the other configurations (SBR 64^2, swirl 4096^2, 3-D)")
     ap.add_argument("--no-events", action="store_true",
                     help="time without per-launch kernel events")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
@@ -235,11 +237,142 @@ def main():
         "kernels": {"trajectories_avg_ms": traj_ms, "reconstruction_avg_ms": recon_ms},
         "accuracy": acc,
     }
+    if not args.no_configs and args.n == 1024 and args.prec == "f32":
+        out["precision_forms"] = precision_forms(wl, stored, value, final)
+        out["configs"] = other_configs()
     if not args.no_serving:
         out["serving"] = run_serving(args.serving_requests, args.serving_budget_gib)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = run_cpu_baseline(wl, stored, args.cpu_seconds)
+        cpu, ofields = run_cpu_baseline(wl, stored, args.cpu_seconds)
+        out["cpu_baseline"] = cpu
+        out["accuracy"]["vs_oracle"] = gpu_vs_oracle(wl, stored, cpu["steps"], ofields)
     print(json.dumps(out), flush=True)
+
+
+def run_gpu(wl, nsteps, prec=None, t0=0.0, profile=True, warmup=2):
+    """nsteps GPU steps of workload wl from its stored initial values (after
+    `warmup` untimed steps); returns (fields, seconds, profile, stats)."""
+    import torch
+    from paper_1410_2817_amd import binding as B
+    prec = prec or wl.value_prec
+    dt_np = np.float32 if prec == "f32" else np.float64
+    g = B.Grid.from_workload(wl, value_prec=prec)
+    init = [np.asarray(f, dt_np) for f in wl.fields]
+    if warmup:
+        g.advance(g.new_fields(init), t0, wl.dt, warmup)
+        torch.cuda.synchronize()
+    x = g.new_fields(init)
+    g.profile(profile)
+    g.profile_read()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    out = g.advance(x, t0, wl.dt, nsteps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t1
+    prof = g.profile_read()
+    g.profile(False)
+    rc, st = g.sync()
+    if rc != 0:
+        raise B.SlError(rc, wl.name)
+    return out, el, prof, st
+
+
+def _l1(a, b):
+    return float(np.abs(a - b).sum() / max(np.abs(b).sum(), 1e-300))
+
+
+def precision_forms(wl, stored, value_f32, final_f32):
+    """The same swirl workload in plain FP64 next to the FP32-value split form:
+    throughput and L1 error against the exact solution (the initial state,
+    after a whole period), so the two are compared at their L1 error."""
+    out64, el, prof, _ = run_gpu(wl, int(round(wl.velocity.params[0] / wl.dt)), prec="f64")
+    # Each form's exact solution is its own initial state.
+    l1_64 = [_l1(f.double().cpu().numpy(), np.asarray(e, np.float64))
+             for f, e in zip(out64, wl.fields)]
+    l1_32 = [_l1(f.double().cpu().numpy(), np.asarray(e, np.float64))
+             for f, e in zip(final_f32, stored)]
+    nsteps = int(round(wl.velocity.params[0] / wl.dt))
+    return {"workload": "swirl2d_1024x1024_3fields, one period (%d steps)" % nsteps,
+            "f32_split": {"node_updates_per_s": value_f32, "l1_rel_vs_exact": l1_32},
+            "f64_plain": {"node_updates_per_s": wl.nodes * nsteps / el,
+                          "reconstruction_avg_ms": prof["recon_ms"] / max(prof["recon_launches"], 1),
+                          "l1_rel_vs_exact": l1_64},
+            "split_over_plain": value_f32 / (wl.nodes * nsteps / el)}
+
+
+def other_configs():
+    """The remaining single-GPU configurations: SBR 64^2 FP64 (one revolution,
+    L1 against the exact solution and the oracle), the swirl at 4096^2 (the
+    HBM-roofline size), the 3-D Fourier flow at 256^3 (FP32 split, 50 steps)
+    and the 3-D deformation at 512^3 (plain FP64 and FP32 split, 60 steps)."""
+    import oracle
+    from paper_1410_2817_amd import workloads as W
+    res = {}
+
+    # SBR 64^2: one revolution (100 steps).
+    wl = W.solid_body_gaussian(64, 100)
+    out, el, prof, st = run_gpu(wl, 100)
+    got = out[0].double().cpu().numpy()
+    exact = np.asarray(wl.fields[0], np.float64)
+    prob = _oracle_problem(oracle, wl)
+    rc, ofs, _ = oracle.run(prob, 0.0, wl.dt, 100, [exact])
+    res["sbr64_f64"] = {"node_updates_per_s": wl.nodes * 100 / el, "ms_per_step": el * 1e3 / 100,
+                        "l1_rel_vs_exact": _l1(got, exact), "l1_rel_vs_oracle": _l1(got, ofs[0]),
+                        "linf_vs_oracle": float(np.abs(got - ofs[0]).max())}
+
+    # Swirl 4096^2: reconstruction at the size whose working set exceeds the
+    # 256 MB last-level cache.
+    wl = W.swirl_three_fields(4096, value_prec="f32")
+    n4 = 40
+    out, el, prof, st = run_gpu(wl, n4)
+    rms = prof["recon_ms"] / max(prof["recon_launches"], 1)
+    per_node = recon_bytes_per_node(2, wl.nfields, 4)
+    ach = per_node * wl.nodes / (rms * 1e-3) / 1e9
+    res["swirl4096_f32"] = {"node_updates_per_s": wl.nodes * n4 / el, "ms_per_step": el * 1e3 / n4,
+                            "steps": n4, "reconstruction_avg_ms": rms,
+                            "trajectories_avg_ms": prof["traj_ms"] / max(prof["traj_launches"], 1),
+                            "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
+                                         "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                                         "bytes_per_node": per_node}}
+    del out
+
+    # 3-D configurations.
+    cases = [("fourier3d_256_f32", W.fourier3d_three_fields(256, value_prec="f32"), 50, "f32"),
+             ("deform3d_512_f64", W.deform3d_slotted_sphere(512), 60, "f64"),
+             ("deform3d_512_f32", W.deform3d_slotted_sphere(512), 60, "f32")]
+    keep = {}
+    for name, wl, nsteps, prec in cases:
+        out, el, prof, st = run_gpu(wl, nsteps, prec=prec)
+        rms = prof["recon_ms"] / max(prof["recon_launches"], 1)
+        vb = 4 if prec == "f32" else 8
+        per_node = recon_bytes_per_node(3, wl.nfields, vb)
+        ach = per_node * wl.nodes / (rms * 1e-3) / 1e9
+        res[name] = {"node_updates_per_s": wl.nodes * nsteps / el, "ms_per_step": el * 1e3 / nsteps,
+                     "steps": nsteps, "reconstruction_avg_ms": rms,
+                     "trajectories_avg_ms": prof["traj_ms"] / max(prof["traj_launches"], 1),
+                     "hbm_achieved_gbs": ach, "hbm_frac": ach / HBM_PEAK_GBS,
+                     "order_hist": st["order_hist"], "walked": st["walked"]}
+        if name.startswith("deform3d"):
+            keep[prec] = out[0].double().cpu().numpy()
+        del out
+    # Split form against plain FP64 after the same 60 steps.
+    res["deform3d_512_f32"]["l1_rel_vs_f64_plain"] = _l1(keep["f32"], keep["f64"])
+    return res
+
+
+def _oracle_problem(oracle, wl):
+    return oracle.Problem(wl.shape, wl.nfields, wl.length, order_max=wl.order_max,
+                          limiter=wl.limiter, theta=wl.theta, integrator=wl.integrator,
+                          vel_kind=wl.velocity.kind, vp=wl.velocity.padded_params(),
+                          modes=wl.velocity.modes)
+
+
+def gpu_vs_oracle(wl, stored, steps, ofields):
+    """GPU result after the oracle sample's steps against the oracle's."""
+    out, _, _, _ = run_gpu(wl, steps, profile=False, warmup=0)
+    got = [f.double().cpu().numpy() for f in out]
+    return {"steps": steps, "l1_rel": [_l1(g, o) for g, o in zip(got, ofields)],
+            "linf": [float(np.abs(g - o).max()) for g, o in zip(got, ofields)]}
 
 
 def run_serving(count: int, budget_gib: float):
@@ -270,10 +403,7 @@ def run_cpu_baseline(wl, stored, seconds):
     """Time the FP64 oracle (unchanged) on the host over the first steps of the
     same workload; stop once `seconds` of wall time are spent."""
     import oracle
-    prob = oracle.Problem(wl.shape, wl.nfields, wl.length, order_max=wl.order_max,
-                          limiter=wl.limiter, theta=wl.theta, integrator=wl.integrator,
-                          vel_kind=wl.velocity.kind, vp=wl.velocity.padded_params(),
-                          modes=wl.velocity.modes)
+    prob = _oracle_problem(oracle, wl)
     fields = [np.asarray(s, np.float64) for s in stored]
     steps, spent = 0, 0.0
     while spent < seconds:
@@ -284,9 +414,9 @@ def run_cpu_baseline(wl, stored, seconds):
         if rc != 0:
             break
     return {"value": wl.nodes * steps / spent, "unit": "node-updates/s",
-            "cores": oracle.threads(), "kind": "oracle",
+            "cores": oracle.threads(), "kind": "oracle", "steps": steps,
             "sample": "first %d step(s) of the same %dx%d workload, %.1f s wall" % (
-                steps, wl.shape[1], wl.shape[0], spent)}
+                steps, wl.shape[1], wl.shape[0], spent)}, fields
 
 
 if __name__ == "__main__":
