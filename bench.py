@@ -115,7 +115,9 @@ def parse():
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the other configurations (SBR 64^2, swirl 4096^2, 3-D)")
     ap.add_argument("--no-events", action="store_true",
-                    help="time without per-launch kernel events")
+                    help="time without kernel events")
+    ap.add_argument("--event-period", type=int, default=8,
+                    help="attach timing events to every N-th launch of each kernel kind")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="wall-clock budget of the oracle sample")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -177,7 +179,7 @@ def main():
     # launch carries HIP timing events in its dispatch packet.
     for a_, b_ in zip(bufs[0], f0):
         a_.copy_(b_)
-    grid.profile(not args.no_events)
+    grid.profile(0 if args.no_events else args.event_period)
     grid.profile_read()
     torch.cuda.synchronize()
     t_start = time.perf_counter()
@@ -191,6 +193,7 @@ def main():
         raise B.SlError(rc, "timed run")
     recon_ms = prof["recon_ms"] / max(prof["recon_launches"], 1)
     traj_ms = prof["traj_ms"] / max(prof["traj_launches"], 1)
+    orders_ms = prof["orders_ms"] / max(prof["orders_launches"], 1)
 
     value = nodes * args.steps / elapsed
     vb = 4 if args.prec == "f32" else 8
@@ -234,7 +237,8 @@ def main():
             "bytes_per_node": per_node, "avg_ms": recon_ms,
             "launches": prof["recon_launches"],
         },
-        "kernels": {"trajectories_avg_ms": traj_ms, "reconstruction_avg_ms": recon_ms},
+        "kernels": {"trajectories_avg_ms": traj_ms, "reconstruction_avg_ms": recon_ms,
+                    "order_words_avg_ms": orders_ms, "event_period": args.event_period},
         "accuracy": acc,
     }
     if not args.no_configs and args.n == 1024 and args.prec == "f32":
@@ -249,7 +253,7 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def run_gpu(wl, nsteps, prec=None, t0=0.0, profile=True, warmup=2):
+def run_gpu(wl, nsteps, prec=None, t0=0.0, profile=4, warmup=2):
     """nsteps GPU steps of workload wl from its stored initial values (after
     `warmup` untimed steps); returns (fields, seconds, profile, stats)."""
     import torch
@@ -270,7 +274,7 @@ def run_gpu(wl, nsteps, prec=None, t0=0.0, profile=True, warmup=2):
     torch.cuda.synchronize()
     el = time.perf_counter() - t1
     prof = g.profile_read()
-    g.profile(False)
+    g.profile(0)
     rc, st = g.sync()
     if rc != 0:
         raise B.SlError(rc, wl.name)
@@ -331,6 +335,7 @@ def other_configs():
     res["swirl4096_f32"] = {"node_updates_per_s": wl.nodes * n4 / el, "ms_per_step": el * 1e3 / n4,
                             "steps": n4, "reconstruction_avg_ms": rms,
                             "trajectories_avg_ms": prof["traj_ms"] / max(prof["traj_launches"], 1),
+                            "order_words_avg_ms": prof["orders_ms"] / max(prof["orders_launches"], 1),
                             "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
                                          "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
                                          "bytes_per_node": per_node}}
@@ -350,6 +355,7 @@ def other_configs():
         res[name] = {"node_updates_per_s": wl.nodes * nsteps / el, "ms_per_step": el * 1e3 / nsteps,
                      "steps": nsteps, "reconstruction_avg_ms": rms,
                      "trajectories_avg_ms": prof["traj_ms"] / max(prof["traj_launches"], 1),
+                     "order_words_avg_ms": prof["orders_ms"] / max(prof["orders_launches"], 1),
                      "hbm_achieved_gbs": ach, "hbm_frac": ach / HBM_PEAK_GBS,
                      "order_hist": st["order_hist"], "walked": st["walked"]}
         if name.startswith("deform3d"):
@@ -369,7 +375,7 @@ def _oracle_problem(oracle, wl):
 
 def gpu_vs_oracle(wl, stored, steps, ofields):
     """GPU result after the oracle sample's steps against the oracle's."""
-    out, _, _, _ = run_gpu(wl, steps, profile=False, warmup=0)
+    out, _, _, _ = run_gpu(wl, steps, profile=0, warmup=0)
     got = [f.double().cpu().numpy() for f in out]
     return {"steps": steps, "l1_rel": [_l1(g, o) for g, o in zip(got, ofields)],
             "linf": [float(np.abs(g - o).max()) for g, o in zip(got, ofields)]}

@@ -188,17 +188,23 @@ int sl_advance(sl_grid *grid, void *workspace, void *const *fields_a,
                void *const *fields_b, double t0, double dt, int nsteps,
                void *stream, int *result_in_b);
 
-/* Kernel timing: when enabled, every trajectory and reconstruction launch of
- * the grid carries HIP events in its dispatch packet. */
+/* Kernel timing: when enabled, the timed launches of the grid carry HIP
+ * events in their dispatch packets.  Kinds: trajectories (sl_step), the
+ * reconstruction kernel, and the limiter order-word kernels that precede it
+ * in sl_reconstruct (none when the limiter is off). */
 typedef struct sl_profile {
   int64_t traj_launches;
-  double traj_ms;          /* summed kernel time of the trajectory launches */
+  double traj_ms;          /* summed kernel time of the timed trajectory launches */
   int64_t recon_launches;
-  double recon_ms;         /* summed kernel time of the reconstruction launches */
+  double recon_ms;         /* summed kernel time of the timed reconstruction launches */
+  int64_t orders_launches;
+  double orders_ms;        /* first order-word kernel start to last one's end, summed */
 } sl_profile;
 
-/* Switch event timing on (1) or off (0) for later launches. */
-int sl_profile_enable(sl_grid *grid, int on);
+/* Time every `period`-th launch of each kind from now on (1: every launch;
+ * 0 or less: off).  Events add a few microseconds between kernels, so a
+ * period above 1 keeps a long run close to its untimed speed. */
+int sl_profile_enable(sl_grid *grid, int period);
 
 /* Wait for the timed launches, report their totals and clear them. */
 int sl_profile_read(sl_grid *grid, sl_profile *out);

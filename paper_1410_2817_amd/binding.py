@@ -57,11 +57,11 @@ class SlStats(C.Structure):
 
 class SlProfile(C.Structure):
     _fields_ = [("traj_launches", C.c_int64), ("traj_ms", C.c_double),
-                ("recon_launches", C.c_int64), ("recon_ms", C.c_double)]
+                ("recon_launches", C.c_int64), ("recon_ms", C.c_double),
+                ("orders_launches", C.c_int64), ("orders_ms", C.c_double)]
 
     def as_dict(self) -> dict:
-        return {"traj_launches": self.traj_launches, "traj_ms": self.traj_ms,
-                "recon_launches": self.recon_launches, "recon_ms": self.recon_ms}
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class SlServerStatus(C.Structure):
@@ -276,8 +276,10 @@ class Grid:
         nbytes = 8 * dim * self.nodes
         return self.workspace[off:off + nbytes].view(torch.float64).view(dim, *self.shape)
 
-    def profile(self, on: bool = True):
-        check(load().sl_profile_enable(self._h, int(bool(on))), "sl_profile_enable")
+    def profile(self, period=1):
+        """Time every `period`-th launch of each kind (True: every launch;
+        False or 0: off)."""
+        check(load().sl_profile_enable(self._h, int(period)), "sl_profile_enable")
 
     def profile_read(self) -> dict:
         p = SlProfile()

@@ -17,6 +17,7 @@
 
 #include <math.h>
 #include <stdint.h>
+#include <stdlib.h>
 #include <stdio.h>
 #include <string.h>
 
@@ -28,44 +29,12 @@
 #include "sl.h"
 #include "sl_device.h"
 #include "sl_launch.h"
+#include "sl_orders.h"
 #include "sl_recon2d.h"
 #include "sl_recon3d.h"
 #include "sl_traj.h"
 
 namespace sl {
-
-// ---------------------------------------------------------------------------
-// Jump flags (Sec. 2.3): bit f of flags[node] is set when the criterion fires
-// for field f along any axis.
-
-template <int D, typename T>
-__global__ __launch_bounds__(kBlock) void flags_kernel(GridArgs g, FieldPtrs fp,
-                                                       uint8_t* __restrict__ flags) {
-  const int lin = blockIdx.x * kBlock + threadIdx.x;
-  if (lin >= g.ntot) return;
-  int idx[D];
-  unflatten<D>(g, lin, idx);
-  int nb[D][2];
-  const int stride[3] = {1, g.n[0], g.n[0] * g.n[1]};
-#pragma unroll
-  for (int a = 0; a < D; ++a) {
-    const int up = idx[a] + 1 == g.n[a] ? -(g.n[a] - 1) : 1;
-    const int dn = idx[a] == 0 ? (g.n[a] - 1) : -1;
-    nb[a][0] = lin + dn * stride[a];
-    nb[a][1] = lin + up * stride[a];
-  }
-  unsigned bits = 0;
-  for (int f = 0; f < g.nfields; ++f) {
-    const T* __restrict__ h = static_cast<const T*>(fp.in[f]);
-    const double hc = (double)h[lin];
-    bool fl = false;
-#pragma unroll
-    for (int a = 0; a < D; ++a)
-      fl = fl || jump_flag((double)h[nb[a][0]], hc, (double)h[nb[a][1]], g.theta);
-    bits |= (fl ? 1u : 0u) << f;
-  }
-  flags[lin] = (uint8_t)bits;
-}
 
 __global__ void zero_kernel(unsigned long long* p, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -118,9 +87,11 @@ struct ProfSlot {
   hipEvent_t start = nullptr, stop = nullptr;
 };
 
-ProfSlot prof_begin(sl_grid* gr) {
+// Every prof_period-th launch of each kind is timed (none when it is 0).
+ProfSlot prof_begin(sl_grid* gr, int kind) {
   ProfSlot ps;
-  if (!gr->prof_on) return ps;
+  if (gr->prof_period <= 0) return ps;
+  if (gr->prof_count[kind]++ % gr->prof_period != 0) return ps;
   if (gr->pending.size() >= kMaxPendingPairs) prof_fold(gr);
   ps.start = prof_event(gr);
   ps.stop = prof_event(gr);
@@ -141,6 +112,9 @@ void prof_end(sl_grid* gr, const ProfSlot& ps, int kind, hipError_t launched) {
     gr->ev_free.push_back(ps.stop);
   }
 }
+
+// 2-D grids from this many nodes up take the separate order-word pass.
+constexpr int64_t kWordsMinNodes = int64_t(1) << 22;
 
 int check_desc(const sl_grid_desc* d) {
   if (!d) return SL_EINVAL;
@@ -228,9 +202,61 @@ hipError_t launch_traj(sl_grid* gr, double* disp, double t, double dt, int accum
   }
 }
 
+// Limiter order words of the fields `fp.in` (none when the limiter is off):
+// flag bytes, then one window pass per axis.  *ord receives the word array
+// (in the workspace); e0 / e1 are recorded by the first / last launch.
 template <int D, typename T>
-hipError_t launch_recon(sl_grid* gr, const sl::FieldPtrs& fp, char* ws, hipStream_t s,
-                        hipEvent_t e0, hipEvent_t e1) {
+hipError_t launch_order_words(sl_grid* gr, const sl::FieldPtrs& fp, char* ws, hipStream_t s,
+                              hipEvent_t e0, hipEvent_t e1, const uint16_t** ord) {
+  *ord = nullptr;
+  if (!(gr->g.limiter && gr->g.order_max > 0) || !gr->limiter_words) return hipSuccess;
+  uint8_t* flags = reinterpret_cast<uint8_t*>(ws + gr->off_flags);
+  uint16_t* wa = reinterpret_cast<uint16_t*>(ws + gr->off_ord);
+  uint16_t* wb = wa + gr->ntot;
+  const dim3 wt(64, 4);
+  // Quad kernels when rows are a multiple of 4 nodes and the fields are
+  // 16-byte aligned.
+  bool quad = gr->g.n[0] % 4 == 0;
+  for (int f = 0; f < gr->g.nfields; ++f) quad = quad && ((uintptr_t)fp.in[f] % 16) == 0;
+  hipError_t e;
+  if (quad) {
+    const dim3 qb((unsigned)((gr->g.n[0] / 4 + 63) / 64), (unsigned)((gr->g.n[1] + 3) / 4),
+                  (unsigned)gr->g.n[2]);
+    auto* f4 = reinterpret_cast<uint32_t*>(flags);
+    auto* qa = reinterpret_cast<unsigned long long*>(wa);
+    auto* qb2 = reinterpret_cast<unsigned long long*>(wb);
+    e = launch(sl::flags_quad_kernel<D, T>, qb, wt, 0, s, e0, nullptr, gr->g, fp, f4);
+    if (e == hipSuccess)
+      e = launch(sl::window_x_quad_kernel, qb, wt, 0, s, nullptr, nullptr, gr->g,
+                 (const uint32_t*)f4, qa);
+    if (e == hipSuccess)
+      e = launch(sl::window_yz_quad_kernel<1>, qb, wt, 0, s, nullptr, D == 2 ? e1 : nullptr,
+                 gr->g, (const unsigned long long*)qa, qb2);
+    if (e == hipSuccess && D == 3)
+      e = launch(sl::window_yz_quad_kernel<2>, qb, wt, 0, s, nullptr, e1, gr->g,
+                 (const unsigned long long*)qb2, qa);
+  } else {
+    const dim3 fb((unsigned)((gr->ntot + sl::kBlock - 1) / sl::kBlock)), ft(sl::kBlock);
+    e = launch(sl::flags_kernel<D, T>, fb, ft, 0, s, e0, nullptr, gr->g, fp, flags);
+    const dim3 wbk((unsigned)((gr->g.n[0] + 63) / 64), (unsigned)((gr->g.n[1] + 3) / 4),
+                   (unsigned)gr->g.n[2]);
+    if (e == hipSuccess)
+      e = launch(sl::window_or_kernel<0>, wbk, wt, 0, s, nullptr, nullptr, gr->g,
+                 (const uint8_t*)flags, (const uint16_t*)nullptr, wa);
+    if (e == hipSuccess)
+      e = launch(sl::window_or_kernel<1>, wbk, wt, 0, s, nullptr, D == 2 ? e1 : nullptr, gr->g,
+                 (const uint8_t*)nullptr, (const uint16_t*)wa, wb);
+    if (e == hipSuccess && D == 3)
+      e = launch(sl::window_or_kernel<2>, wbk, wt, 0, s, nullptr, e1, gr->g,
+                 (const uint8_t*)nullptr, (const uint16_t*)wb, wa);
+  }
+  *ord = D == 3 ? wa : wb;
+  return e;
+}
+
+template <int D, typename T>
+hipError_t launch_recon(sl_grid* gr, const sl::FieldPtrs& fp, char* ws, const uint16_t* ord,
+                        hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   const double* disp = reinterpret_cast<const double*>(ws + gr->off_disp);
   auto* stats = reinterpret_cast<unsigned long long*>(ws + gr->off_stats);
   if constexpr (D == 2) {
@@ -244,7 +270,7 @@ hipError_t launch_recon(sl_grid* gr, const sl::FieldPtrs& fp, char* ws, hipStrea
   case NF:                                                                                \
     return launch(sl::recon2d_tiled_kernel<T, NF>, grid, block,                          \
                   (uint32_t)sl::Tile2D<T, NF>::LDS_BYTES, s, e0, e1, gr->g, fp, disp, \
-                  stats, tiles_x, ntiles);
+                  ord, stats, tiles_x, ntiles);
     switch (gr->g.nfields) {
       SL_RECON2D(1)
       SL_RECON2D(2)
@@ -256,35 +282,11 @@ hipError_t launch_recon(sl_grid* gr, const sl::FieldPtrs& fp, char* ws, hipStrea
       default:
         return launch(sl::recon2d_tiled_kernel<T, 8>, grid, block,
                       (uint32_t)sl::Tile2D<T, 8>::LDS_BYTES, s, e0, e1, gr->g, fp, disp,
-                      stats, tiles_x, ntiles);
+                      ord, stats, tiles_x, ntiles);
     }
 #undef SL_RECON2D
   } else {
     using C = sl::Tile3D;
-    const bool lim = gr->g.limiter && gr->g.order_max > 0;
-    const uint16_t* ord = nullptr;
-    if (lim) {
-      uint8_t* flags = reinterpret_cast<uint8_t*>(ws + gr->off_flags);
-      uint16_t* wa = reinterpret_cast<uint16_t*>(ws + gr->off_ord);
-      uint16_t* wb = wa + gr->ntot;
-      const dim3 fb((unsigned)((gr->ntot + sl::kBlock - 1) / sl::kBlock)), ft(sl::kBlock);
-      hipError_t e = launch(sl::flags_kernel<D, T>, fb, ft, 0, s, e0, nullptr, gr->g, fp, flags);
-      const dim3 wbk((unsigned)((gr->g.n[0] + 63) / 64), (unsigned)((gr->g.n[1] + 3) / 4),
-                     (unsigned)gr->g.n[2]);
-      const dim3 wt(64, 4);
-      if (e == hipSuccess)
-        e = launch(sl::window_or_kernel<0>, wbk, wt, 0, s, nullptr, nullptr, gr->g,
-                   (const uint8_t*)flags, (const uint16_t*)nullptr, wa);
-      if (e == hipSuccess)
-        e = launch(sl::window_or_kernel<1>, wbk, wt, 0, s, nullptr, nullptr, gr->g,
-                   (const uint8_t*)nullptr, (const uint16_t*)wa, wb);
-      if (e == hipSuccess)
-        e = launch(sl::window_or_kernel<2>, wbk, wt, 0, s, nullptr, nullptr, gr->g,
-                   (const uint8_t*)nullptr, (const uint16_t*)wb, wa);
-      if (e != hipSuccess) return e;
-      e0 = nullptr;
-      ord = wa;
-    }
     const int tiles_x = (gr->g.n[0] + C::TX - 1) / C::TX;
     const int tiles_y = (gr->g.n[1] + C::TY - 1) / C::TY;
     const int tiles_z = (gr->g.n[2] + C::TZ - 1) / C::TZ;
@@ -404,9 +406,17 @@ int sl_create_grid(const sl_grid_desc* desc, sl_grid** out) {
   gr->off_stats = 0;
   gr->off_disp = align_up(kStatsBytes);
   gr->off_flags = align_up(gr->off_disp + sizeof(double) * (size_t)D * (size_t)gr->ntot);
-  // 3-D grids also hold two 16-bit window words per node (ping-pong).
+  // Two 16-bit limiter window words per node (ping-pong).
   gr->off_ord = align_up(gr->off_flags + (size_t)gr->ntot);
-  gr->ws_bytes = D == 3 ? align_up(gr->off_ord + 4 * (size_t)gr->ntot) : gr->off_ord;
+  gr->ws_bytes = align_up(gr->off_ord + 4 * (size_t)gr->ntot);
+  // 2-D grids evaluate the limiter flags inside the reconstruction tiles
+  // (the values are staged there anyway) unless the grid is large, where a
+  // separate order-word pass costs less than the tiles' redundant flag work.
+  // SL_LIMITER_WORDS=0/1 in the environment forces the choice in 2-D.
+  {
+    const char* ev = getenv("SL_LIMITER_WORDS");
+    gr->limiter_words = D == 3 || (ev && *ev ? atoi(ev) != 0 : gr->ntot >= kWordsMinNodes);
+  }
   gr->steps_since_reset = 0;
   *out = gr;
   return SL_OK;
@@ -433,7 +443,7 @@ int sl_step(sl_grid* gr, void* workspace, double t, double dt, void* stream) {
   double* disp = reinterpret_cast<double*>(static_cast<char*>(workspace) + gr->off_disp);
   const int acc = gr->steps_since_reset > 0;
   clear_stale_error();
-  const ProfSlot ps = prof_begin(gr);
+  const ProfSlot ps = prof_begin(gr, 0);
   const hipError_t e = gr->desc.dim == 2
                            ? launch_traj<2>(gr, disp, t, dt, acc, s, ps.start, ps.stop)
                            : launch_traj<3>(gr, disp, t, dt, acc, s, ps.start, ps.stop);
@@ -466,15 +476,26 @@ int sl_reconstruct(sl_grid* gr, void* workspace, const void* const* fields_in,
   char* ws = static_cast<char*>(workspace);
   const bool f32 = gr->desc.value_prec == SL_FP32;
   clear_stale_error();
-  const ProfSlot ps = prof_begin(gr);
+  const ProfSlot po = prof_begin(gr, 2);
+  const uint16_t* ord = nullptr;
   hipError_t e;
   if (gr->desc.dim == 2)
-    e = f32 ? launch_recon<2, float>(gr, fp, ws, s, ps.start, ps.stop)
-            : launch_recon<2, double>(gr, fp, ws, s, ps.start, ps.stop);
+    e = f32 ? launch_order_words<2, float>(gr, fp, ws, s, po.start, po.stop, &ord)
+            : launch_order_words<2, double>(gr, fp, ws, s, po.start, po.stop, &ord);
   else
-    e = f32 ? launch_recon<3, float>(gr, fp, ws, s, ps.start, ps.stop)
-            : launch_recon<3, double>(gr, fp, ws, s, ps.start, ps.stop);
-  prof_end(gr, ps, 1, e);
+    e = f32 ? launch_order_words<3, float>(gr, fp, ws, s, po.start, po.stop, &ord)
+            : launch_order_words<3, double>(gr, fp, ws, s, po.start, po.stop, &ord);
+  prof_end(gr, po, 2, ord ? e : hipErrorInvalidValue);  // no launch: drop the pair
+  if (e == hipSuccess) {
+    const ProfSlot ps = prof_begin(gr, 1);
+    if (gr->desc.dim == 2)
+      e = f32 ? launch_recon<2, float>(gr, fp, ws, ord, s, ps.start, ps.stop)
+              : launch_recon<2, double>(gr, fp, ws, ord, s, ps.start, ps.stop);
+    else
+      e = f32 ? launch_recon<3, float>(gr, fp, ws, ord, s, ps.start, ps.stop)
+              : launch_recon<3, double>(gr, fp, ws, ord, s, ps.start, ps.stop);
+    prof_end(gr, ps, 1, e);
+  }
   const int rc = hip_status(e);
   if (rc == SL_OK) {
     gr->steps_since_reset = 0;
@@ -546,9 +567,10 @@ int sl_advance(sl_grid* gr, void* workspace, void* const* fields_a, void* const*
   return SL_OK;
 }
 
-int sl_profile_enable(sl_grid* gr, int on) {
+int sl_profile_enable(sl_grid* gr, int period) {
   if (!gr) return SL_EINVAL;
-  gr->prof_on = on != 0;
+  gr->prof_period = period > 0 ? period : 0;
+  gr->prof_count[0] = gr->prof_count[1] = gr->prof_count[2] = 0;
   return SL_OK;
 }
 
@@ -560,9 +582,11 @@ int sl_profile_read(sl_grid* gr, sl_profile* out) {
     out->traj_ms = gr->prof_ms[0];
     out->recon_launches = gr->prof_n[1];
     out->recon_ms = gr->prof_ms[1];
+    out->orders_launches = gr->prof_n[2];
+    out->orders_ms = gr->prof_ms[2];
   }
-  gr->prof_n[0] = gr->prof_n[1] = 0;
-  gr->prof_ms[0] = gr->prof_ms[1] = 0.0;
+  gr->prof_n[0] = gr->prof_n[1] = gr->prof_n[2] = 0;
+  gr->prof_ms[0] = gr->prof_ms[1] = gr->prof_ms[2] = 0.0;
   return SL_OK;
 }
 

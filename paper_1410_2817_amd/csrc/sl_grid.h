@@ -10,7 +10,7 @@
 #include "sl_device.h"
 
 struct sl_prof_pair {
-  int kind;  // 0 trajectories, 1 reconstruction
+  int kind;  // 0 trajectories, 1 reconstruction, 2 limiter order words
   hipEvent_t start, stop;
 };
 
@@ -21,13 +21,16 @@ struct sl_grid {
   sl::VelArgs v;
   int64_t ntot;
   size_t off_stats, off_disp, off_flags, off_ord, ws_bytes;
+  bool limiter_words;  // limiter order words from a separate pass
   int steps_since_reset;
   int64_t steps_launched, reconstructs_launched;
-  // Kernel timing with events attached to the dispatch packets.
-  bool prof_on;
+  // Kernel timing with events attached to the dispatch packets of every
+  // prof_period-th launch of each kind (0: off).
+  int prof_period;
+  int64_t prof_count[3];
   std::vector<hipEvent_t> ev_free;
   std::vector<sl_prof_pair> pending;
-  double prof_ms[2];
-  int64_t prof_n[2];
+  double prof_ms[3];
+  int64_t prof_n[3];
 };
 

@@ -1,0 +1,177 @@
+// Limiter order words (Sec. 2.3) for gfx950.
+//
+// The limiter's order choice for a mesh node depends only on its host cell r:
+// the quintic stencil reads the jump flags of the nodes r-2..r+3 per axis and
+// the cubic one those of r-1..r+2.  Both ORs are separable, so short passes
+// (one per axis) turn the per-node flag bytes (bit f set when the criterion
+// fires for field f along any axis) into one 16-bit word per cell: low byte
+// the quintic window, high byte the cubic window, bit f for field f.  The
+// reconstruction then reads one word per node.
+#pragma once
+
+#include "sl_device.h"
+#include "sl_traj.h"
+
+namespace sl {
+
+// Jump flags (Sec. 2.3): bit f of flags[node] is set when the criterion fires
+// for field f along any axis.
+
+template <int D, typename T>
+__global__ __launch_bounds__(kBlock) void flags_kernel(GridArgs g, FieldPtrs fp,
+                                                       uint8_t* __restrict__ flags) {
+  const int lin = blockIdx.x * kBlock + threadIdx.x;
+  if (lin >= g.ntot) return;
+  int idx[D];
+  unflatten<D>(g, lin, idx);
+  int nb[D][2];
+  const int stride[3] = {1, g.n[0], g.n[0] * g.n[1]};
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    const int up = idx[a] + 1 == g.n[a] ? -(g.n[a] - 1) : 1;
+    const int dn = idx[a] == 0 ? (g.n[a] - 1) : -1;
+    nb[a][0] = lin + dn * stride[a];
+    nb[a][1] = lin + up * stride[a];
+  }
+  unsigned bits = 0;
+  for (int f = 0; f < g.nfields; ++f) {
+    const T* __restrict__ h = static_cast<const T*>(fp.in[f]);
+    const double hc = (double)h[lin];
+    bool fl = false;
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+      fl = fl || jump_flag((double)h[nb[a][0]], hc, (double)h[nb[a][1]], g.theta);
+    bits |= (fl ? 1u : 0u) << f;
+  }
+  flags[lin] = (uint8_t)bits;
+}
+
+// Separable window OR of the jump flags along AXIS.  AXIS 0 reads the flag
+// bytes and writes both windows; the y and z passes OR the words' low bytes
+// over slots -2..3 and their high bytes over slots -1..2.
+template <int AXIS>
+__global__ __launch_bounds__(256) void window_or_kernel(GridArgs g,
+                                                        const uint8_t* __restrict__ flags,
+                                                        const uint16_t* __restrict__ win,
+                                                        uint16_t* __restrict__ out) {
+  const int x = blockIdx.x * 64 + threadIdx.x, y = blockIdx.y * 4 + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= g.n[0] || y >= g.n[1]) return;
+  const int idx[3] = {x, y, z};
+  const int lin = x + g.n[0] * (y + g.n[1] * z);
+  const int n = g.n[AXIS];
+  const int stride = AXIS == 0 ? 1 : (AXIS == 1 ? g.n[0] : g.n[0] * g.n[1]);
+  const int base = lin - idx[AXIS] * stride;
+  int j = idx[AXIS] - 2;
+  j = j < 0 ? j + n : j;  // n >= 6
+  unsigned lo = 0, hi = 0;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const unsigned v = AXIS == 0 ? (unsigned)flags[base + j] * 0x101u
+                                 : (unsigned)win[base + j * stride];
+    lo |= v & 0xffu;
+    if (k >= 1 && k <= 4) hi |= v & 0xff00u;
+    j = j + 1 == n ? 0 : j + 1;
+  }
+  out[lin] = (uint16_t)(lo | hi);
+}
+
+// The same passes four x-nodes per work-item, for rows whose length is a
+// multiple of 4 (and 16-byte aligned fields): flag bytes and window words
+// move as 32- and 64-bit words.  Grids: (ceil(n0/4/64), ceil(n1/4), n2) of
+// 64 x 4 (n2 = 1 in 2-D).
+template <int D, typename T>
+__global__ __launch_bounds__(256) void flags_quad_kernel(GridArgs g, FieldPtrs fp,
+                                                         uint32_t* __restrict__ flags4) {
+  using V4 = T __attribute__((ext_vector_type(4)));
+  const int nq = g.n[0] / 4;
+  const int q = blockIdx.x * 64 + threadIdx.x, y = blockIdx.y * 4 + threadIdx.y;
+  const int z = blockIdx.z;
+  if (q >= nq || y >= g.n[1]) return;
+  const int n0 = g.n[0], n1 = g.n[1], n2 = g.n[2];
+  const int x = 4 * q;
+  const int ym = y == 0 ? n1 - 1 : y - 1, yp = y + 1 == n1 ? 0 : y + 1;
+  const int zm = z == 0 ? n2 - 1 : z - 1, zp = z + 1 == n2 ? 0 : z + 1;
+  const int row = n0 * (y + n1 * z);
+  const int rym = n0 * (ym + n1 * z), ryp = n0 * (yp + n1 * z);
+  const int rzm = n0 * (y + n1 * zm), rzp = n0 * (y + n1 * zp);
+  const int xm = x == 0 ? n0 - 1 : x - 1, xp = x + 4 == n0 ? 0 : x + 4;
+  unsigned bits = 0;
+  for (int f = 0; f < g.nfields; ++f) {
+    const T* __restrict__ h = static_cast<const T*>(fp.in[f]);
+    const V4 c = *reinterpret_cast<const V4*>(h + row + x);
+    const V4 vym = *reinterpret_cast<const V4*>(h + rym + x);
+    const V4 vyp = *reinterpret_cast<const V4*>(h + ryp + x);
+    const V4 vzm = D == 3 ? *reinterpret_cast<const V4*>(h + rzm + x) : c;
+    const V4 vzp = D == 3 ? *reinterpret_cast<const V4*>(h + rzp + x) : c;
+    const double l = (double)h[row + xm], r = (double)h[row + xp];
+    const double cc[4] = {(double)c.x, (double)c.y, (double)c.z, (double)c.w};
+    const double am[4] = {(double)vym.x, (double)vym.y, (double)vym.z, (double)vym.w};
+    const double ap[4] = {(double)vyp.x, (double)vyp.y, (double)vyp.z, (double)vyp.w};
+    const double bm[4] = {(double)vzm.x, (double)vzm.y, (double)vzm.z, (double)vzm.w};
+    const double bp[4] = {(double)vzp.x, (double)vzp.y, (double)vzp.z, (double)vzp.w};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const double hm = j == 0 ? l : cc[j - 1], hp = j == 3 ? r : cc[j + 1];
+      const bool fl = jump_flag(hm, cc[j], hp, g.theta) ||
+                      jump_flag(am[j], cc[j], ap[j], g.theta) ||
+                      (D == 3 && jump_flag(bm[j], cc[j], bp[j], g.theta));
+      bits |= (fl ? 1u : 0u) << (8 * j + f);
+    }
+  }
+  flags4[(row + x) / 4] = bits;
+}
+
+__global__ __launch_bounds__(256) void window_x_quad_kernel(GridArgs g,
+                                                            const uint32_t* __restrict__ flags4,
+                                                            unsigned long long* __restrict__ out4) {
+  const int nq = g.n[0] / 4;
+  const int q = blockIdx.x * 64 + threadIdx.x, y = blockIdx.y * 4 + threadIdx.y;
+  const int z = blockIdx.z;
+  if (q >= nq || y >= g.n[1]) return;
+  const int rowq = nq * (y + g.n[1] * z);
+  // Bytes of the nodes x-4 .. x+7 (x = 4q); nq >= 2 since n0 >= 6.
+  const unsigned w[3] = {flags4[rowq + (q == 0 ? nq - 1 : q - 1)], flags4[rowq + q],
+                         flags4[rowq + (q + 1 == nq ? 0 : q + 1)]};
+  unsigned b[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) b[k] = (w[k / 4] >> (8 * (k % 4))) & 0xffu;
+  unsigned long long o = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    // Node x + j: quintic window b[j+2 .. j+7], cubic window b[j+3 .. j+6].
+    unsigned lo = 0, hi = 0;
+#pragma unroll
+    for (int k = 2; k <= 7; ++k) lo |= b[j + k];
+#pragma unroll
+    for (int k = 3; k <= 6; ++k) hi |= b[j + k];
+    o |= (unsigned long long)(lo | (hi << 8)) << (16 * j);
+  }
+  out4[rowq + q] = o;
+}
+
+template <int AXIS>
+__global__ __launch_bounds__(256) void window_yz_quad_kernel(
+    GridArgs g, const unsigned long long* __restrict__ in4, unsigned long long* __restrict__ out4) {
+  const int nq = g.n[0] / 4;
+  const int q = blockIdx.x * 64 + threadIdx.x, y = blockIdx.y * 4 + threadIdx.y;
+  const int z = blockIdx.z;
+  if (q >= nq || y >= g.n[1]) return;
+  const int lin = q + nq * (y + g.n[1] * z);
+  const int idx = AXIS == 1 ? y : z, n = g.n[AXIS];
+  const int stride = AXIS == 1 ? nq : nq * g.n[1];
+  const int base = lin - idx * stride;
+  int j = idx - 2;
+  j = j < 0 ? j + n : j;  // n >= 6
+  unsigned long long lo = 0, hi = 0;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const unsigned long long v = in4[base + j * stride];
+    lo |= v & 0x00ff00ff00ff00ffull;
+    if (k >= 1 && k <= 4) hi |= v & 0xff00ff00ff00ff00ull;
+    j = j + 1 == n ? 0 : j + 1;
+  }
+  out4[lin] = lo | hi;
+}
+
+}  // namespace sl

@@ -166,15 +166,26 @@ __device__ __forceinline__ void stencil_global(const GridArgs& g, const FieldPtr
 // Separable Z-spline sum over the 6x6 stencil; val(kx, ky) returns the value
 // of node (r - 2 + kx, r - 2 + ky).  The same operation order is used on the
 // LDS and the global path.
+// Rows go two at a time in a rolled loop; the y weights are shifted down each
+// pass so that only constant register indices occur (a rolled loop indexing
+// wy[ky] would select among all six per row).
 template <typename T, class Val>
 __device__ __forceinline__ T zsum2d(const T* wx, const T* wy, const Val& val) {
   T acc = T(0);
-#pragma unroll 2
-  for (int ky = 0; ky < 6; ++ky) {
-    T s = T(0);
+  T w0 = wy[0], w1 = wy[1], w2 = wy[2], w3 = wy[3], w4 = wy[4], w5 = wy[5];
+#pragma unroll 1
+  for (int ky = 0; ky < 6; ky += 2) {
+    T s0 = T(0), s1 = T(0);
 #pragma unroll
-    for (int kx = 0; kx < 6; ++kx) s = fma(val(kx, ky), wx[kx], s);
-    acc = fma(s, wy[ky], acc);
+    for (int kx = 0; kx < 6; ++kx) s0 = fma(val(kx, ky), wx[kx], s0);
+#pragma unroll
+    for (int kx = 0; kx < 6; ++kx) s1 = fma(val(kx, ky + 1), wx[kx], s1);
+    acc = fma(s0, w0, acc);
+    acc = fma(s1, w1, acc);
+    w0 = w2;
+    w1 = w3;
+    w2 = w4;
+    w3 = w5;
   }
   return acc;
 }
@@ -183,9 +194,14 @@ __device__ __forceinline__ T zsum2d(const T* wx, const T* wy, const Val& val) {
 // with `tiles_x` tiles per row.  NF is the number of fields (a compile-time
 // constant so that the per-field loops unroll without exec-mask
 // bookkeeping).  `smem` is the workgroup's dynamic LDS (Tile2D::LDS_BYTES).
+//
+// `ord`, when not null, holds the limiter order words of every cell (see
+// sl_orders.h); the tile then skips its own flag pass and reads one word per
+// node.  Otherwise the flags of the staged box are evaluated here.
 template <typename T, int NF>
 __device__ __forceinline__ void recon2d_tile(const GridArgs& g, const FieldPtrs& fp,
                                              const double* __restrict__ gdisp,
+                                             const uint16_t* __restrict__ ord,
                                              unsigned long long* __restrict__ stats, int tile,
                                              int tiles_x, unsigned char* smem) {
   using C = Tile2D<T, NF>;
@@ -310,7 +326,7 @@ __device__ __forceinline__ void recon2d_tile(const GridArgs& g, const FieldPtrs&
     // two box rows at a time (lanes 0-31 the first, 32-63 the second, lane =
     // x), evaluates the criterion in FP64 and packs the flags of each field
     // into row words with one ballot.
-    if (g.limiter && g.order_max > 0) {
+    if (g.limiter && g.order_max > 0 && ord == nullptr) {
       const int lane = __lane_id(), wave = threadIdx.x / 64;
       const int bx = lane & 31;
       for (int by2 = 2 * wave; by2 < BY; by2 += 2 * (kTileThreads / 64)) {
@@ -377,7 +393,14 @@ __device__ __forceinline__ void recon2d_tile(const GridArgs& g, const FieldPtrs&
     const bool lim = g.limiter && g.order_max > 0;
     unsigned or6 = 0, or4 = 0;
     int ix[6], iy[6];
-    if (inbox) {
+    if (ord != nullptr) {
+      if (!inbox) stencil_global<T>(g, fp, r, false, ix, iy, or6, or4);
+      if (lim) {
+        const unsigned o = ord[wrap_near(r[0], g.n[0]) + g.n[0] * wrap_near(r[1], g.n[1])];
+        or6 = o & 0xffu;
+        or4 = o >> 8;
+      }
+    } else if (inbox) {
       if (lim) {
 #pragma unroll
         for (int f = 0; f < nf; ++f) {
@@ -467,9 +490,10 @@ __device__ __forceinline__ void recon2d_tile(const GridArgs& g, const FieldPtrs&
 template <typename T, int NF>
 __global__ __launch_bounds__(kTileThreads) void recon2d_tiled_kernel(
     GridArgs g, FieldPtrs fp, const double* __restrict__ gdisp,
-    unsigned long long* __restrict__ stats, int tiles_x, int ntiles) {
+    const uint16_t* __restrict__ ord, unsigned long long* __restrict__ stats, int tiles_x,
+    int ntiles) {
   extern __shared__ __align__(16) unsigned char smem[];
-  recon2d_tile<T, NF>(g, fp, gdisp, stats, xcd_tile(blockIdx.x, ntiles), tiles_x, smem);
+  recon2d_tile<T, NF>(g, fp, gdisp, ord, stats, xcd_tile(blockIdx.x, ntiles), tiles_x, smem);
 }
 
 }  // namespace sl

@@ -19,39 +19,10 @@
 // index tables.  Both paths sum in the same order.
 #pragma once
 
+#include "sl_orders.h"
 #include "sl_recon2d.h"
 
 namespace sl {
-
-// Separable window OR of the jump flags along AXIS.  AXIS 0 reads the flag
-// bytes and writes both windows; the y and z passes OR the words' low bytes
-// over slots -2..3 and their high bytes over slots -1..2.
-template <int AXIS>
-__global__ __launch_bounds__(256) void window_or_kernel(GridArgs g,
-                                                        const uint8_t* __restrict__ flags,
-                                                        const uint16_t* __restrict__ win,
-                                                        uint16_t* __restrict__ out) {
-  const int x = blockIdx.x * 64 + threadIdx.x, y = blockIdx.y * 4 + threadIdx.y;
-  const int z = blockIdx.z;
-  if (x >= g.n[0] || y >= g.n[1]) return;
-  const int idx[3] = {x, y, z};
-  const int lin = x + g.n[0] * (y + g.n[1] * z);
-  const int n = g.n[AXIS];
-  const int stride = AXIS == 0 ? 1 : (AXIS == 1 ? g.n[0] : g.n[0] * g.n[1]);
-  const int base = lin - idx[AXIS] * stride;
-  int j = idx[AXIS] - 2;
-  j = j < 0 ? j + n : j;  // n >= 6
-  unsigned lo = 0, hi = 0;
-#pragma unroll
-  for (int k = 0; k < 6; ++k) {
-    const unsigned v = AXIS == 0 ? (unsigned)flags[base + j] * 0x101u
-                                 : (unsigned)win[base + j * stride];
-    lo |= v & 0xffu;
-    if (k >= 1 && k <= 4) hi |= v & 0xff00u;
-    j = j + 1 == n ? 0 : j + 1;
-  }
-  out[lin] = (uint16_t)(lo | hi);
-}
 
 // Lattice displacement through the caches.
 struct NearDisp3D {
@@ -182,7 +153,7 @@ __device__ __forceinline__ int cell_solve3d(const GridArgs& g, const double* __r
 // non-zero when one field's bytes fit the 31-bit buffer offsets, `dbuf_ok`
 // when one displacement component's do.
 template <typename T, int NF>
-__global__ __launch_bounds__(kTileThreads) void recon3d_kernel(
+__global__ __launch_bounds__(kTileThreads, 4) void recon3d_kernel(
     GridArgs g, FieldPtrs fp, const double* __restrict__ gdisp,
     const uint16_t* __restrict__ ord, unsigned long long* __restrict__ stats, int tiles_x,
     int tiles_y, int ntiles, int buf_ok, int dbuf_ok) {

@@ -104,7 +104,8 @@ __global__ __launch_bounds__(kTileThreads) void recon2d_batched_kernel(
     fp.in[f] = rt.parity ? rs.ab.out[f] : rs.ab.in[f];
     fp.out[f] = rt.parity ? const_cast<void*>(rs.ab.in[f]) : rs.ab.out[f];
   }
-  recon2d_tile<T, NF>(rs.g, fp, rs.disp, rs.stats, logical - rt.blk_begin, rs.tiles_x, smem);
+  recon2d_tile<T, NF>(rs.g, fp, rs.disp, nullptr, rs.stats, logical - rt.blk_begin, rs.tiles_x,
+                      smem);
 }
 
 }  // namespace sl
@@ -188,7 +189,9 @@ void arena_free(sl_server* s, size_t off, size_t bytes) {
 size_t request_bytes(const sl_grid* gr) {
   const size_t vbytes = gr->desc.value_prec == SL_FP32 ? 4 : 8;
   const size_t field = align_up(vbytes * (size_t)gr->ntot);
-  return 2 * (size_t)gr->desc.nfields * field + align_up(sl_workspace_bytes(gr));
+  // The batched reconstruction evaluates the limiter flags in LDS, so the
+  // request needs the workspace only up to the order-word arrays.
+  return 2 * (size_t)gr->desc.nfields * field + align_up(gr->off_ord);
 }
 
 hipEvent_t take_event(sl_server* s) {

@@ -347,3 +347,25 @@ def test_full_size_3d_sampled(B, torch, orc, which):
         err = np.abs(got - vals[:, f]).max()
         say("  field", f, "max abs err", err)
         assert err <= rel * max(1.0, np.abs(vals[:, f]).max())
+
+
+@pytest.mark.parametrize("name,wl", [
+    ("swirl96_f32", W.swirl_three_fields(96, value_prec="f32")),
+    ("swirl96_f64", W.swirl_three_fields(96, value_prec="f64")),
+    ("swirl70_f64", W.swirl_three_fields(70, value_prec="f64")),
+])
+def test_2d_limiter_paths_agree_bitwise(B, torch, name, wl, monkeypatch):
+    """2-D grids take the limiter flags either inside the reconstruction
+    tiles or from the separate order-word pass (quad kernels when rows are a
+    multiple of 4, scalar ones otherwise); both give the same orders, so the
+    results are bitwise equal."""
+    outs = []
+    for words in ("0", "1"):
+        monkeypatch.setenv("SL_LIMITER_WORDS", words)
+        out, st, rc, _ = gpu_run(B, torch, wl, nsteps=3, t0=1.1)
+        assert rc == 0
+        outs.append((out, st["order_hist"]))
+    (a, ha), (b, hb) = outs
+    assert ha == hb
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
