@@ -173,16 +173,20 @@ void clear_stale_error() { (void)hipGetLastError(); }
 
 using sl::launch;
 
+// Time factors of the stages of a step over [t, t + dt].
+sl::StageTimes stage_times(const sl_grid* gr, double t, double dt) {
+  sl::StageTimes st;
+  const bool periodic = gr->v.kind == SL_VEL_SWIRL2D || gr->v.kind == SL_VEL_DEFORM3D;
+  const double ts[4] = {t, gr->desc.integrator == SL_RK4 ? t + 0.5 * dt : t + dt / 3.0,
+                        gr->desc.integrator == SL_RK4 ? t + dt : t + 0.75 * dt, t + dt};
+  for (int i = 0; i < 4; ++i) st.tf[i] = periodic ? cos(M_PI * ts[i] / gr->v.p[0]) : 1.0;
+  return st;
+}
+
 template <int D>
 hipError_t launch_traj(sl_grid* gr, double* disp, double t, double dt, int accumulate,
                        hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-  sl::StageTimes st;
-  {
-    const bool periodic = gr->v.kind == SL_VEL_SWIRL2D || gr->v.kind == SL_VEL_DEFORM3D;
-    const double ts[4] = {t, gr->desc.integrator == SL_RK4 ? t + 0.5 * dt : t + dt / 3.0,
-                          gr->desc.integrator == SL_RK4 ? t + dt : t + 0.75 * dt, t + dt};
-    for (int i = 0; i < 4; ++i) st.tf[i] = periodic ? cos(M_PI * ts[i] / gr->v.p[0]) : 1.0;
-  }
+  const sl::StageTimes st = stage_times(gr, t, dt);
   const dim3 blocks((unsigned)((gr->g.n[0] + sl::kTrajBX - 1) / sl::kTrajBX),
                     (unsigned)((gr->g.n[1] + sl::kTrajBY - 1) / sl::kTrajBY),
                     (unsigned)gr->g.n[2]);
@@ -255,9 +259,9 @@ hipError_t launch_order_words(sl_grid* gr, const sl::FieldPtrs& fp, char* ws, hi
 }
 
 template <int D, typename T>
-hipError_t launch_recon(sl_grid* gr, const sl::FieldPtrs& fp, char* ws, const uint16_t* ord,
-                        hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-  const double* disp = reinterpret_cast<const double*>(ws + gr->off_disp);
+hipError_t launch_recon(sl_grid* gr, const sl::FieldPtrs& fp, char* ws, const double* disp,
+                        const uint16_t* ord, const sl::NextTraj& nt, hipStream_t s,
+                        hipEvent_t e0, hipEvent_t e1) {
   auto* stats = reinterpret_cast<unsigned long long*>(ws + gr->off_stats);
   if constexpr (D == 2) {
     // Tile shape does not depend on the field count.
@@ -270,7 +274,7 @@ hipError_t launch_recon(sl_grid* gr, const sl::FieldPtrs& fp, char* ws, const ui
   case NF:                                                                                \
     return launch(sl::recon2d_tiled_kernel<T, NF>, grid, block,                          \
                   (uint32_t)sl::Tile2D<T, NF>::LDS_BYTES, s, e0, e1, gr->g, fp, disp, \
-                  ord, stats, tiles_x, ntiles);
+                  ord, stats, tiles_x, ntiles, nt, gr->v);
     switch (gr->g.nfields) {
       SL_RECON2D(1)
       SL_RECON2D(2)
@@ -282,7 +286,7 @@ hipError_t launch_recon(sl_grid* gr, const sl::FieldPtrs& fp, char* ws, const ui
       default:
         return launch(sl::recon2d_tiled_kernel<T, 8>, grid, block,
                       (uint32_t)sl::Tile2D<T, 8>::LDS_BYTES, s, e0, e1, gr->g, fp, disp,
-                      ord, stats, tiles_x, ntiles);
+                      ord, stats, tiles_x, ntiles, nt, gr->v);
     }
 #undef SL_RECON2D
   } else {
@@ -408,7 +412,10 @@ int sl_create_grid(const sl_grid_desc* desc, sl_grid** out) {
   gr->off_flags = align_up(gr->off_disp + sizeof(double) * (size_t)D * (size_t)gr->ntot);
   // Two 16-bit limiter window words per node (ping-pong).
   gr->off_ord = align_up(gr->off_flags + (size_t)gr->ntot);
-  gr->ws_bytes = align_up(gr->off_ord + 4 * (size_t)gr->ntot);
+  // Second displacement buffer: sl_advance integrates the next step's
+  // trajectories there while the current step reconstructs.
+  gr->off_disp2 = align_up(gr->off_ord + 4 * (size_t)gr->ntot);
+  gr->ws_bytes = align_up(gr->off_disp2 + sizeof(double) * (size_t)D * (size_t)gr->ntot);
   // 2-D grids evaluate the limiter flags inside the reconstruction tiles
   // (the values are staged there anyway) unless the grid is large, where a
   // separate order-word pass costs less than the tiles' redundant flag work.
@@ -456,26 +463,31 @@ int sl_step(sl_grid* gr, void* workspace, double t, double dt, void* stream) {
   return rc;
 }
 
-int sl_reconstruct(sl_grid* gr, void* workspace, const void* const* fields_in,
-                   void* const* fields_out, void* stream) {
-  if (!gr || !workspace || !fields_in || !fields_out) return SL_EINVAL;
-  if (((uintptr_t)workspace) % kAlign) return SL_EINVAL;
-  if (gr->steps_since_reset < 1) return SL_ESTATE;
-  sl::FieldPtrs fp;
-  memset(&fp, 0, sizeof(fp));
+}  // extern "C"
+
+namespace {
+
+// Field pointer block for in -> out after the checks of sl_reconstruct.
+int field_ptrs(const sl_grid* gr, const void* const* in, void* const* out, sl::FieldPtrs* fp) {
+  if (!in || !out) return SL_EINVAL;
+  memset(fp, 0, sizeof(*fp));
   const int nf = gr->desc.nfields;
   for (int f = 0; f < nf; ++f) {
-    if (!fields_in[f] || !fields_out[f]) return SL_EINVAL;
-    fp.in[f] = fields_in[f];
-    fp.out[f] = fields_out[f];
+    if (!in[f] || !out[f]) return SL_EINVAL;
+    fp->in[f] = in[f];
+    fp->out[f] = out[f];
   }
   for (int f = 0; f < nf; ++f)
     for (int q = 0; q < nf; ++q)
-      if (fp.out[f] == fp.in[q]) return SL_EINVAL;
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  char* ws = static_cast<char*>(workspace);
+      if (fp->out[f] == fp->in[q]) return SL_EINVAL;
+  return SL_OK;
+}
+
+// Order words (if any) and the reconstruction from displacement `disp`; the
+// reconstruction kernel also integrates the trajectories `nt` asks for.
+hipError_t reconstruct_launches(sl_grid* gr, char* ws, const sl::FieldPtrs& fp,
+                                const double* disp, const sl::NextTraj& nt, hipStream_t s) {
   const bool f32 = gr->desc.value_prec == SL_FP32;
-  clear_stale_error();
   const ProfSlot po = prof_begin(gr, 2);
   const uint16_t* ord = nullptr;
   hipError_t e;
@@ -486,16 +498,35 @@ int sl_reconstruct(sl_grid* gr, void* workspace, const void* const* fields_in,
     e = f32 ? launch_order_words<3, float>(gr, fp, ws, s, po.start, po.stop, &ord)
             : launch_order_words<3, double>(gr, fp, ws, s, po.start, po.stop, &ord);
   prof_end(gr, po, 2, ord ? e : hipErrorInvalidValue);  // no launch: drop the pair
-  if (e == hipSuccess) {
-    const ProfSlot ps = prof_begin(gr, 1);
-    if (gr->desc.dim == 2)
-      e = f32 ? launch_recon<2, float>(gr, fp, ws, ord, s, ps.start, ps.stop)
-              : launch_recon<2, double>(gr, fp, ws, ord, s, ps.start, ps.stop);
-    else
-      e = f32 ? launch_recon<3, float>(gr, fp, ws, ord, s, ps.start, ps.stop)
-              : launch_recon<3, double>(gr, fp, ws, ord, s, ps.start, ps.stop);
-    prof_end(gr, ps, 1, e);
-  }
+  if (e != hipSuccess) return e;
+  const ProfSlot ps = prof_begin(gr, 1);
+  if (gr->desc.dim == 2)
+    e = f32 ? launch_recon<2, float>(gr, fp, ws, disp, ord, nt, s, ps.start, ps.stop)
+            : launch_recon<2, double>(gr, fp, ws, disp, ord, nt, s, ps.start, ps.stop);
+  else
+    e = f32 ? launch_recon<3, float>(gr, fp, ws, disp, ord, nt, s, ps.start, ps.stop)
+            : launch_recon<3, double>(gr, fp, ws, disp, ord, nt, s, ps.start, ps.stop);
+  prof_end(gr, ps, 1, e);
+  return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sl_reconstruct(sl_grid* gr, void* workspace, const void* const* fields_in,
+                   void* const* fields_out, void* stream) {
+  if (!gr || !workspace || !fields_in || !fields_out) return SL_EINVAL;
+  if (((uintptr_t)workspace) % kAlign) return SL_EINVAL;
+  if (gr->steps_since_reset < 1) return SL_ESTATE;
+  sl::FieldPtrs fp;
+  const int prc = field_ptrs(gr, fields_in, fields_out, &fp);
+  if (prc != SL_OK) return prc;
+  char* ws = static_cast<char*>(workspace);
+  clear_stale_error();
+  const hipError_t e = reconstruct_launches(gr, ws, fp,
+                                            reinterpret_cast<const double*>(ws + gr->off_disp),
+                                            sl::NextTraj{}, static_cast<hipStream_t>(stream));
   const int rc = hip_status(e);
   if (rc == SL_OK) {
     gr->steps_since_reset = 0;
@@ -548,6 +579,41 @@ int sl_advance(sl_grid* gr, void* workspace, void* const* fields_a, void* const*
   const int K = gr->desc.reconstruct_every;
   if (nsteps % K) return SL_EINVAL;
   if (gr->steps_since_reset != 0) return SL_ESTATE;
+  if (K == 1 && nsteps > 0 && gr->desc.dim == 2) {
+    // Each reconstruction also integrates the next step's trajectories into
+    // the other displacement buffer, so a step is one reconstruction launch
+    // (plus the limiter order words) after the first step's trajectories.
+    // (3-D steps are long enough that the separate launch costs nothing.)
+    if (!workspace || ((uintptr_t)workspace) % kAlign) return SL_EINVAL;
+    sl::FieldPtrs ab, ba;
+    int rc = field_ptrs(gr, (const void* const*)fields_a, fields_b, &ab);
+    if (rc == SL_OK) rc = field_ptrs(gr, (const void* const*)fields_b, fields_a, &ba);
+    if (rc != SL_OK) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char* ws = static_cast<char*>(workspace);
+    double* dbuf[2] = {reinterpret_cast<double*>(ws + gr->off_disp),
+                       reinterpret_cast<double*>(ws + gr->off_disp2)};
+    clear_stale_error();
+    const ProfSlot ps = prof_begin(gr, 0);
+    hipError_t e = gr->desc.dim == 2
+                       ? launch_traj<2>(gr, dbuf[0], t0, dt, 0, s, ps.start, ps.stop)
+                       : launch_traj<3>(gr, dbuf[0], t0, dt, 0, s, ps.start, ps.stop);
+    prof_end(gr, ps, 0, e);
+    for (int k = 0; k < nsteps && e == hipSuccess; ++k) {
+      gr->steps_launched++;
+      sl::NextTraj nt{};
+      if (k + 1 < nsteps) {
+        nt.disp = dbuf[(k + 1) & 1];
+        nt.st = stage_times(gr, t0 + (double)(k + 1) * dt, dt);
+        nt.dt = dt;
+        nt.integrator = gr->desc.integrator;
+      }
+      e = reconstruct_launches(gr, ws, (k & 1) ? ba : ab, dbuf[k & 1], nt, s);
+      if (e == hipSuccess) gr->reconstructs_launched++;
+    }
+    if (e == hipSuccess && result_in_b) *result_in_b = nsteps & 1;
+    return hip_status(e);
+  }
   void* const* cur = fields_a;
   void* const* nxt = fields_b;
   int in_b = 0;

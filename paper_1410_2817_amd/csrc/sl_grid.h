@@ -20,7 +20,7 @@ struct sl_grid {
   sl::GridArgs g;
   sl::VelArgs v;
   int64_t ntot;
-  size_t off_stats, off_disp, off_flags, off_ord, ws_bytes;
+  size_t off_stats, off_disp, off_flags, off_ord, off_disp2, ws_bytes;
   bool limiter_words;  // limiter order words from a separate pass
   int steps_since_reset;
   int64_t steps_launched, reconstructs_launched;

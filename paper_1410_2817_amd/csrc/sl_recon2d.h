@@ -21,6 +21,7 @@
 #include <type_traits>
 
 #include "sl_device.h"
+#include "sl_traj.h"
 
 namespace sl {
 
@@ -198,12 +199,16 @@ __device__ __forceinline__ T zsum2d(const T* wx, const T* wy, const Val& val) {
 // `ord`, when not null, holds the limiter order words of every cell (see
 // sl_orders.h); the tile then skips its own flag pass and reads one word per
 // node.  Otherwise the flags of the staged box are evaluated here.
-template <typename T, int NF>
+//
+// `nt` / `v` (VelT = VelArgs): the tile then also integrates the next step's
+// trajectories of its own nodes (see NextTraj); VelT = NoVel compiles that out.
+template <typename T, int NF, class VelT>
 __device__ __forceinline__ void recon2d_tile(const GridArgs& g, const FieldPtrs& fp,
                                              const double* __restrict__ gdisp,
                                              const uint16_t* __restrict__ ord,
                                              unsigned long long* __restrict__ stats, int tile,
-                                             int tiles_x, unsigned char* smem) {
+                                             int tiles_x, unsigned char* smem,
+                                             const NextTraj& nt, const VelT& v) {
   using C = Tile2D<T, NF>;
   __shared__ int s_box[4];  // min rx, min ry, max rx, max ry
   __shared__ unsigned s_cnt[ST_COUNT];
@@ -212,6 +217,18 @@ __device__ __forceinline__ void recon2d_tile(const GridArgs& g, const FieldPtrs&
   const int lx = threadIdx.x % C::TX, ly0 = threadIdx.x / C::TX;
   constexpr int ROWS = kTileThreads / C::TX;  // rows covered per pass
 
+  // The next step's trajectories of the tile's own nodes (NextTraj); they
+  // touch nothing the reconstruction below reads.
+  if constexpr (std::is_same<VelT, VelArgs>::value) {
+    if (nt.disp) {
+#pragma unroll 1
+      for (int k = 0; k < C::NPT; ++k) {
+        const int idx[2] = {tx0 + lx, ty0 + ly0 + ROWS * k};
+        if (idx[0] < g.n[0] && idx[1] < g.n[1])
+          traj_any<2>(g, v, nt.disp, nt.st, nt.dt, nt.integrator, idx);
+      }
+    }
+  }
   if (threadIdx.x == 0) {
     s_box[0] = s_box[1] = INT_MAX;
     s_box[2] = s_box[3] = INT_MIN;
@@ -488,12 +505,14 @@ __device__ __forceinline__ void recon2d_tile(const GridArgs& g, const FieldPtrs&
 }
 
 template <typename T, int NF>
-__global__ __launch_bounds__(kTileThreads) void recon2d_tiled_kernel(
+__global__ __launch_bounds__(kTileThreads, sizeof(T) == 4 ? (NF <= 4 ? 6 : 5) : (NF <= 4 ? 4 : 3))
+void recon2d_tiled_kernel(
     GridArgs g, FieldPtrs fp, const double* __restrict__ gdisp,
     const uint16_t* __restrict__ ord, unsigned long long* __restrict__ stats, int tiles_x,
-    int ntiles) {
+    int ntiles, NextTraj nt, VelArgs v) {
   extern __shared__ __align__(16) unsigned char smem[];
-  recon2d_tile<T, NF>(g, fp, gdisp, ord, stats, xcd_tile(blockIdx.x, ntiles), tiles_x, smem);
+  recon2d_tile<T, NF>(g, fp, gdisp, ord, stats, xcd_tile(blockIdx.x, ntiles), tiles_x, smem, nt,
+                      v);
 }
 
 }  // namespace sl

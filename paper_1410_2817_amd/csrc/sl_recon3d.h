@@ -105,6 +105,10 @@ struct Box3D {
   static constexpr int BZ = Tile3D::TZ + 8;
   static constexpr int NB = BX * BY * BZ;
   static constexpr bool STAGE = SL_STAGE3D && NF * (int)sizeof(T) * NB <= 48 * 1024;
+  // Waves per SIMD the register budget targets: four workgroups per CU when
+  // their boxes fit 160 KB of LDS, three otherwise.
+  static constexpr int WAVES =
+      STAGE && NF * (int)sizeof(T) * NB <= 40 * 1024 ? 4 : 3;
 };
 
 // Element solve in cell r for the search.  When no active lane's cell
@@ -153,7 +157,7 @@ __device__ __forceinline__ int cell_solve3d(const GridArgs& g, const double* __r
 // non-zero when one field's bytes fit the 31-bit buffer offsets, `dbuf_ok`
 // when one displacement component's do.
 template <typename T, int NF>
-__global__ __launch_bounds__(kTileThreads, 4) void recon3d_kernel(
+__global__ __launch_bounds__(kTileThreads, (Box3D<T, NF>::WAVES)) void recon3d_kernel(
     GridArgs g, FieldPtrs fp, const double* __restrict__ gdisp,
     const uint16_t* __restrict__ ord, unsigned long long* __restrict__ stats, int tiles_x,
     int tiles_y, int ntiles, int buf_ok, int dbuf_ok) {

@@ -105,7 +105,7 @@ __global__ __launch_bounds__(kTileThreads) void recon2d_batched_kernel(
     fp.out[f] = rt.parity ? const_cast<void*>(rs.ab.in[f]) : rs.ab.out[f];
   }
   recon2d_tile<T, NF>(rs.g, fp, rs.disp, nullptr, rs.stats, logical - rt.blk_begin, rs.tiles_x,
-                      smem);
+                      smem, NextTraj{}, NoVel{});
 }
 
 }  // namespace sl

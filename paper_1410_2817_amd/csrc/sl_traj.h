@@ -100,6 +100,45 @@ __device__ __forceinline__ void traj_node(const GridArgs& g, const VelArgs& v,
 }
 
 
+// Trajectory of lattice node idx from its mesh node (a fresh lattice) for
+// the grid's velocity family, chosen at run time (a wave-uniform switch).
+template <int D>
+__device__ __forceinline__ void traj_any(const GridArgs& g, const VelArgs& v,
+                                         double* __restrict__ disp, const StageTimes& st,
+                                         double dt, int integrator, const int* idx) {
+  switch (v.kind) {
+    case SL_VEL_UNIFORM:
+      traj_node<D, SL_VEL_UNIFORM>(g, v, disp, st, dt, 0, integrator, idx);
+      break;
+    case SL_VEL_SOLID_BODY:
+      traj_node<D, SL_VEL_SOLID_BODY>(g, v, disp, st, dt, 0, integrator, idx);
+      break;
+    case SL_VEL_SWIRL2D:
+      traj_node<D, SL_VEL_SWIRL2D>(g, v, disp, st, dt, 0, integrator, idx);
+      break;
+    case SL_VEL_DEFORM3D:
+      traj_node<D, SL_VEL_DEFORM3D>(g, v, disp, st, dt, 0, integrator, idx);
+      break;
+    default:
+      traj_node<D, SL_VEL_FOURIER>(g, v, disp, st, dt, 0, integrator, idx);
+      break;
+  }
+}
+
+// The next step's trajectories, computed by a reconstruction kernel for its
+// own tile's lattice nodes: they start on the mesh (the lattice is reset each
+// step) and so do not depend on the fields being reconstructed.  `disp` null:
+// nothing to do.
+struct NextTraj {
+  double* disp;
+  StageTimes st;
+  double dt;
+  int integrator;
+};
+
+// Stand-in for the velocity argument of kernels that never integrate.
+struct NoVel {};
+
 template <int D, int VK>
 __global__ __launch_bounds__(kBlock) void traj_kernel(GridArgs g, VelArgs v,
                                                       double* __restrict__ disp, StageTimes st,
