@@ -197,7 +197,10 @@ def main():
 
     value = nodes * args.steps / elapsed
     vb = 4 if args.prec == "f32" else 8
-    per_node = recon_bytes_per_node(2, wl.nfields, vb)
+    # In a 2-D run each reconstruction launch also integrates the next step's
+    # trajectories (all launches but the last), so it writes their
+    # displacements too.
+    per_node = recon_bytes_per_node(2, wl.nfields, vb) + traj_bytes_per_node(2)
     achieved = per_node * nodes / (recon_ms * 1e-3) / 1e9 if recon_ms > 0 else None
 
     # Accuracy: after a whole period the exact solution is the initial state.
@@ -230,7 +233,7 @@ def main():
             "dt": wl.dt, "t_end": args.steps * wl.dt,
         },
         "roofline": {
-            "kernel": "reconstruction (sl_reconstruct)",
+            "kernel": "reconstruction + next step's trajectories (recon2d_tiled_kernel)",
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS if achieved else None,
             "traffic": recorded_traffic() if args.n == 1024 and args.prec == "f32" else None,
@@ -330,7 +333,7 @@ def other_configs():
     n4 = 40
     out, el, prof, st = run_gpu(wl, n4)
     rms = prof["recon_ms"] / max(prof["recon_launches"], 1)
-    per_node = recon_bytes_per_node(2, wl.nfields, 4)
+    per_node = recon_bytes_per_node(2, wl.nfields, 4) + traj_bytes_per_node(2)
     ach = per_node * wl.nodes / (rms * 1e-3) / 1e9
     res["swirl4096_f32"] = {"node_updates_per_s": wl.nodes * n4 / el, "ms_per_step": el * 1e3 / n4,
                             "steps": n4, "reconstruction_avg_ms": rms,

@@ -54,6 +54,15 @@ struct Tile2D {
   static constexpr int LDS_BYTES = (RAW + 255) / 256 * 256 < CAP ? (RAW + 255) / 256 * 256 : CAP;
 };
 
+// Waves per SIMD the register budget of the 2-D reconstruction kernels
+// targets, per (precision, field count): the most that compile without
+// spills (the LDS boxes allow more).
+template <typename T, int NF>
+constexpr int tile2d_waves() {
+  if (sizeof(T) == 4) return (NF >= 2 && NF <= 4) ? 6 : (NF <= 5 ? 5 : 4);
+  return (NF == 1 || NF == 3 || NF == 4) ? 4 : 3;
+}
+
 __device__ __forceinline__ int xcd_tile(int b, int nblocks) {
   const int xcd = b % kNumXcd, local = b / kNumXcd;
   const int q = nblocks / kNumXcd, rem = nblocks % kNumXcd;
@@ -115,13 +124,14 @@ __device__ __forceinline__ NearDisp2D make_disp_accessor(std::false_type, const 
 
 // Jump-flag bits (all fields) of the lattice node at wrapped (x, y), from
 // global memory.
-template <typename T>
+template <typename T, int NF>
 __device__ __forceinline__ unsigned global_flag_bits(const GridArgs& g, const FieldPtrs& fp,
                                                      int x, int y) {
   const int xm = x == 0 ? g.n[0] - 1 : x - 1, xp = x + 1 == g.n[0] ? 0 : x + 1;
   const int ym = y == 0 ? g.n[1] - 1 : y - 1, yp = y + 1 == g.n[1] ? 0 : y + 1;
   unsigned bits = 0;
-  for (int f = 0; f < g.nfields; ++f) {
+#pragma unroll
+  for (int f = 0; f < NF; ++f) {
     const T* __restrict__ h = static_cast<const T*>(fp.in[f]);
     const double hc = (double)h[x + g.n[0] * y];
     const bool fl = jump_flag((double)h[xm + g.n[0] * y], hc, (double)h[xp + g.n[0] * y], g.theta) ||
@@ -141,7 +151,7 @@ __device__ __forceinline__ int pick_order(int order_max, unsigned or6, unsigned 
 
 // Wrapped stencil indices and flag masks through global memory, for nodes
 // whose stencil is not in the staged box.
-template <typename T>
+template <typename T, int NF>
 __device__ __forceinline__ void stencil_global(const GridArgs& g, const FieldPtrs& fp,
                                                          const int* r, bool lim, int* ix,
                                                          int* iy, unsigned& or6,
@@ -157,7 +167,7 @@ __device__ __forceinline__ void stencil_global(const GridArgs& g, const FieldPtr
   if (lim) {
     for (int ky = 0; ky < 6; ++ky)
       for (int kx = 0; kx < 6; ++kx) {
-        const unsigned fb = global_flag_bits<T>(g, fp, ix[kx], iy[ky]);
+        const unsigned fb = global_flag_bits<T, NF>(g, fp, ix[kx], iy[ky]);
         or6 |= fb;
         if (kx >= 1 && kx <= 4 && ky >= 1 && ky <= 4) or4 |= fb;
       }
@@ -411,7 +421,7 @@ __device__ __forceinline__ void recon2d_tile(const GridArgs& g, const FieldPtrs&
     unsigned or6 = 0, or4 = 0;
     int ix[6], iy[6];
     if (ord != nullptr) {
-      if (!inbox) stencil_global<T>(g, fp, r, false, ix, iy, or6, or4);
+      if (!inbox) stencil_global<T, NF>(g, fp, r, false, ix, iy, or6, or4);
       if (lim) {
         const unsigned o = ord[wrap_near(r[0], g.n[0]) + g.n[0] * wrap_near(r[1], g.n[1])];
         or6 = o & 0xffu;
@@ -434,7 +444,7 @@ __device__ __forceinline__ void recon2d_tile(const GridArgs& g, const FieldPtrs&
         }
       }
     } else {
-      stencil_global<T>(g, fp, r, lim, ix, iy, or6, or4);
+      stencil_global<T, NF>(g, fp, r, lim, ix, iy, or6, or4);
     }
     // Weights of the top order; the lower orders and the per-field select
     // only run when some lane of the wave needs them (a wave-uniform branch).
@@ -505,7 +515,7 @@ __device__ __forceinline__ void recon2d_tile(const GridArgs& g, const FieldPtrs&
 }
 
 template <typename T, int NF>
-__global__ __launch_bounds__(kTileThreads, sizeof(T) == 4 ? (NF <= 4 ? 6 : 5) : (NF <= 4 ? 4 : 3))
+__global__ __launch_bounds__(kTileThreads, (tile2d_waves<T, NF>()))
 void recon2d_tiled_kernel(
     GridArgs g, FieldPtrs fp, const double* __restrict__ gdisp,
     const uint16_t* __restrict__ ord, unsigned long long* __restrict__ stats, int tiles_x,

@@ -6,8 +6,10 @@
 // aligned); a request that does not fit is refused with SL_EBUSY, so the
 // arena size is the HBM budget.  Every tick advances each active request by
 // one step of the scheme (trajectories, then reconstruction with the lattice
-// reset) through one batched trajectory launch per velocity family and one
-// batched reconstruction launch per (precision, field count): workgroups find
+// reset) through batched reconstruction launches, one per (precision, field
+// count), that also integrate each request's next-step trajectories into its
+// other displacement buffer; only a request's first step needs a batched
+// trajectory launch (one per velocity family).  Workgroups find
 // their request from per-tick block offsets passed in the kernel arguments and
 // run exactly the per-tile code of the single-grid kernels, so a request's
 // result does not depend on what it was batched with.  Requests join between
@@ -37,8 +39,9 @@ namespace sl {
 struct ReqStatic {
   GridArgs g;
   VelArgs v;
-  FieldPtrs ab;  // in = set A, out = set B; odd ticks swap them
-  double* disp;
+  FieldPtrs ab;  // in = set A, out = set B; odd steps swap them
+  double* disp;   // displacement of even steps
+  double* disp2;  // displacement of odd steps
   unsigned long long* stats;
   int tiles_x, ntiles;    // reconstruction tiles
   int traj_bx, traj_by;   // trajectory blocks (64 x 4 nodes each)
@@ -50,10 +53,11 @@ struct ReqStatic {
 struct ReqTick {
   int entry;      // table index
   int blk_begin;  // first block of this request in the batched launch
-  int parity;     // 0: A -> B, 1: B -> A
-  int pad;
+  int parity;     // step parity: 0: A -> B from disp, 1: B -> A from disp2
+  int next;       // reconstruction: also integrate the next step
   double dt;
-  double tf[3];   // stage time factors (periodic velocity families)
+  double tf[3];   // stage time factors (periodic velocity families) of the
+                  // step the trajectories are for
 };
 
 constexpr int kServeBatch = 40;  // requests per batched launch (kernel-argument budget)
@@ -91,7 +95,8 @@ __global__ __launch_bounds__(kBlock) void traj_batched_kernel(const ReqStatic* _
 }
 
 template <typename T, int NF>
-__global__ __launch_bounds__(kTileThreads) void recon2d_batched_kernel(
+__global__ __launch_bounds__(kTileThreads, (tile2d_waves<T, NF>()))
+void recon2d_batched_kernel(
     const ReqStatic* __restrict__ table, TickArgs ta) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int logical = xcd_tile(blockIdx.x, ta.total_blocks);
@@ -104,8 +109,18 @@ __global__ __launch_bounds__(kTileThreads) void recon2d_batched_kernel(
     fp.in[f] = rt.parity ? rs.ab.out[f] : rs.ab.in[f];
     fp.out[f] = rt.parity ? const_cast<void*>(rs.ab.in[f]) : rs.ab.out[f];
   }
-  recon2d_tile<T, NF>(rs.g, fp, rs.disp, nullptr, rs.stats, logical - rt.blk_begin, rs.tiles_x,
-                      smem, NextTraj{}, NoVel{});
+  NextTraj nt{};
+  if (rt.next) {
+    nt.disp = rt.parity ? rs.disp : rs.disp2;
+    nt.st.tf[0] = rt.tf[0];
+    nt.st.tf[1] = rt.tf[1];
+    nt.st.tf[2] = rt.tf[2];
+    nt.st.tf[3] = rt.tf[2];
+    nt.dt = rt.dt;
+    nt.integrator = rs.integrator;
+  }
+  recon2d_tile<T, NF>(rs.g, fp, rt.parity ? rs.disp2 : rs.disp, nullptr, rs.stats,
+                      logical - rt.blk_begin, rs.tiles_x, smem, nt, rs.v);
 }
 
 }  // namespace sl
@@ -190,8 +205,10 @@ size_t request_bytes(const sl_grid* gr) {
   const size_t vbytes = gr->desc.value_prec == SL_FP32 ? 4 : 8;
   const size_t field = align_up(vbytes * (size_t)gr->ntot);
   // The batched reconstruction evaluates the limiter flags in LDS, so the
-  // request needs the workspace only up to the order-word arrays.
-  return 2 * (size_t)gr->desc.nfields * field + align_up(gr->off_ord);
+  // request needs the workspace only up to the order-word arrays, plus the
+  // second displacement buffer.
+  return 2 * (size_t)gr->desc.nfields * field + align_up(gr->off_ord) +
+         align_up(sizeof(double) * 2 * (size_t)gr->ntot);
 }
 
 hipEvent_t take_event(sl_server* s) {
@@ -260,9 +277,10 @@ hipError_t launch_traj_group(sl_server* s, int vk, const sl::TickArgs& ta) {
   }
 }
 
-void stage_times(const Request& r, double tf[3]) {
+// Stage time factors of step `k` of request r.
+void stage_times(const Request& r, int k, double tf[3]) {
   const sl_grid* gr = r.grid;
-  const double t = r.t0 + (double)r.done * r.dt, dt = r.dt;
+  const double t = r.t0 + (double)k * r.dt, dt = r.dt;
   const bool periodic = gr->v.kind == SL_VEL_SWIRL2D;
   const bool rk4 = gr->desc.integrator == SL_RK4;
   const double ts[3] = {t, rk4 ? t + 0.5 * dt : t + dt / 3.0, rk4 ? t + dt : t + 0.75 * dt};
@@ -387,6 +405,7 @@ int sl_server_admit(sl_server* s, const sl_grid_desc* desc, const void* const* f
     hs.ab.out[f] = r.b[f];
   }
   hs.disp = reinterpret_cast<double*>(ws + gr->off_disp);
+  hs.disp2 = reinterpret_cast<double*>(ws + align_up(gr->off_ord));
   hs.stats = s->stats;
   using C = sl::Tile2D<float, 1>;
   hs.tiles_x = (gr->g.n[0] + C::TX - 1) / C::TX;
@@ -418,9 +437,11 @@ int sl_server_tick(sl_server* s, int* active) {
   // Keep at most max_inflight ticks queued on the device.
   drain_events(s, false, (size_t)s->max_inflight - 1);
 
-  // Trajectories, batched per velocity family.
-  std::vector<int> order(s->active.size());
-  for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+  // First-step trajectories of newly admitted requests, batched per velocity
+  // family (later steps' come from the previous tick's reconstruction).
+  std::vector<int> order;
+  for (size_t i = 0; i < s->active.size(); ++i)
+    if (s->active[i].done == 0) order.push_back((int)i);
   auto vk_of = [&](int i) { return s->active[i].grid->v.kind; };
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return vk_of(x) < vk_of(y); });
   hipError_t err = hipSuccess;
@@ -435,9 +456,9 @@ int sl_server_tick(sl_server* s, int* active) {
       sl::ReqTick& rt = ta.r[ta.nreq++];
       rt.entry = r.entry;
       rt.blk_begin = blocks;
-      rt.parity = r.done & 1;
+      rt.parity = 0;
       rt.dt = r.dt;
-      stage_times(r, rt.tf);
+      stage_times(r, 0, rt.tf);
       blocks += hs.traj_bx * hs.traj_by;
       ++i;
     }
@@ -445,6 +466,8 @@ int sl_server_tick(sl_server* s, int* active) {
     err = launch_traj_group(s, vk, ta);
   }
   // Reconstructions, batched per (value precision, field count).
+  order.resize(s->active.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
   auto key_of = [&](int i) {
     const sl_grid* g = s->active[i].grid;
     return g->desc.value_prec * 16 + g->desc.nfields;
@@ -462,7 +485,9 @@ int sl_server_tick(sl_server* s, int* active) {
       rt.entry = r.entry;
       rt.blk_begin = blocks;
       rt.parity = r.done & 1;
+      rt.next = r.done + 1 < r.nsteps;
       rt.dt = r.dt;
+      if (rt.next) stage_times(r, r.done + 1, rt.tf);
       blocks += hs.ntiles;
       ++i;
     }
