@@ -4,10 +4,14 @@ Workload: the 2-D reversing swirl (period T = 5, max speed 1) on a 1024 x 1024
 periodic grid carrying three fields (slotted disc, cosine bell, Gaussian), FP32
 values with FP64 positions, Z2 with the jump limiter on, dt = 4h (CFL 4), so a
 full period is 1280 steps.  A step is one pass of the whole hot path: the
-lattice trajectories (sl_step) and the reconstruction of all three fields
-(sl_reconstruct).  Inputs are resident in HBM before timing starts.
+lattice trajectories and the reconstruction of all three fields, run by
+sl_advance (in 2-D each reconstruction launch also integrates the next step's
+trajectories).  Inputs are resident in HBM before timing starts.
 
-Prints one JSON line (metric, value, ms_per_step, roofline, cpu_baseline, ...).
+Prints one JSON line (metric, value, ms_per_step, roofline, cpu_baseline, ...);
+with the defaults it also reports the plain-FP64 form, the other single-GPU
+configurations and the serving mix.  --workload fourier3d / deform3d make a
+3-D flow the measured workload instead (used for the 3-D kernel profiles).
 """
 from __future__ import annotations
 
@@ -103,9 +107,14 @@ def traj_bytes_per_node(dim: int) -> int:
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1280)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--n", type=int, default=1024, help="grid side")
+    ap.add_argument("--workload", default="swirl", choices=["swirl", "fourier3d", "deform3d"],
+                    help="swirl: the 2-D reversing swirl (default); fourier3d / deform3d: the "
+                         "3-D Fourier-mode and deformational flows (for profiling runs)")
+    ap.add_argument("--n", type=int, default=None,
+                    help="grid side (default 1024 swirl, 256 fourier3d, 512 deform3d)")
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default 1280 swirl = one period, 50 fourier3d, 60 deform3d)")
     ap.add_argument("--prec", default="f32", choices=["f32", "f64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true",
@@ -160,7 +169,20 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
-    wl = W.swirl_three_fields(args.n, value_prec=args.prec)
+    dim = 2 if args.workload == "swirl" else 3
+    if args.workload == "swirl":
+        args.n = args.n or 1024
+        wl = W.swirl_three_fields(args.n, value_prec=args.prec)
+        args.steps = args.steps or 1280
+    elif args.workload == "fourier3d":
+        args.n = args.n or 256
+        wl = W.fourier3d_three_fields(args.n, value_prec=args.prec)
+        args.steps = args.steps or 50
+    else:
+        args.n = args.n or 512
+        wl = W.deform3d_slotted_sphere(args.n, value_prec=args.prec)
+        args.steps = args.steps or 60
+    headline = args.workload == "swirl" and args.n == 1024 and args.prec == "f32"
     grid = B.Grid.from_workload(wl, device=dev)
     stored = [np.asarray(f, np.float32 if args.prec == "f32" else np.float64) for f in wl.fields]
     f0 = grid.new_fields(stored)
@@ -200,12 +222,12 @@ def main():
     # In a 2-D run each reconstruction launch also integrates the next step's
     # trajectories (all launches but the last), so it writes their
     # displacements too.
-    per_node = recon_bytes_per_node(2, wl.nfields, vb) + traj_bytes_per_node(2)
+    per_node = recon_bytes_per_node(dim, wl.nfields, vb) + (traj_bytes_per_node(2) if dim == 2 else 0)
     achieved = per_node * nodes / (recon_ms * 1e-3) / 1e9 if recon_ms > 0 else None
 
     # Accuracy: after a whole period the exact solution is the initial state.
     acc = {}
-    if args.steps * wl.dt >= wl.velocity.params[0] - 1e-9 and \
+    if args.workload == "swirl" and args.steps * wl.dt >= wl.velocity.params[0] - 1e-9 and \
             abs(args.steps * wl.dt - round(args.steps * wl.dt / wl.velocity.params[0]) * wl.velocity.params[0]) < 1e-9:
         got = [f.double().cpu().numpy() for f in final]
         acc["l1_rel_vs_exact_after_period"] = [
@@ -228,15 +250,17 @@ def main():
         "dtype": "f32+f64" if args.prec == "f32" else "f64",
         "data": "synthetic",
         "config": {
-            "workload": "swirl2d_%dx%d_3fields_%s_cfl4_limiter_z2" % (args.n, args.n, args.prec),
+            "workload": wl.name if not headline else
+                        "swirl2d_%dx%d_3fields_%s_cfl4_limiter_z2" % (args.n, args.n, args.prec),
             "nodes": nodes, "nfields": wl.nfields, "values": args.prec, "positions": "f64",
             "dt": wl.dt, "t_end": args.steps * wl.dt,
         },
         "roofline": {
-            "kernel": "reconstruction + next step's trajectories (recon2d_tiled_kernel)",
+            "kernel": ("reconstruction + next step's trajectories (recon2d_tiled_kernel)"
+                       if dim == 2 else "reconstruction (recon3d_kernel)"),
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS if achieved else None,
-            "traffic": recorded_traffic() if args.n == 1024 and args.prec == "f32" else None,
+            "traffic": recorded_traffic() if headline else None,
             "bytes_per_node": per_node, "avg_ms": recon_ms,
             "launches": prof["recon_launches"],
         },
@@ -244,10 +268,10 @@ def main():
                     "order_words_avg_ms": orders_ms, "event_period": args.event_period},
         "accuracy": acc,
     }
-    if not args.no_configs and args.n == 1024 and args.prec == "f32":
+    if not args.no_configs and headline:
         out["precision_forms"] = precision_forms(wl, stored, value, final)
         out["configs"] = other_configs()
-    if not args.no_serving:
+    if not args.no_serving and headline:
         out["serving"] = run_serving(args.serving_requests, args.serving_budget_gib)
     if not args.no_cpu_baseline:
         cpu, ofields = run_cpu_baseline(wl, stored, args.cpu_seconds)
