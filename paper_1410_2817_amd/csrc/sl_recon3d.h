@@ -103,12 +103,18 @@ struct Box3D {
   static constexpr int BX = Tile3D::TX + 8;
   static constexpr int BY = Tile3D::TY + 8;
   static constexpr int BZ = Tile3D::TZ + 8;
-  static constexpr int NB = BX * BY * BZ;
-  static constexpr bool STAGE = SL_STAGE3D && NF * (int)sizeof(T) * NB <= 48 * 1024;
+  static constexpr int bytes(int px) { return NF * (int)sizeof(T) * px * BY * BZ; }
+  // LDS row pitch: a wave's 8 x 8 lanes read 8 consecutive x values in each
+  // of 8 rows; a pitch of 24 elements (8 mod 16) puts the rows of each
+  // half-wave on distinct LDS banks for 4- and 8-byte values alike.  Boxes
+  // that would then no longer fit four workgroups per CU keep the unpadded
+  // pitch (occupancy matters more there than the bank conflicts).
+  static constexpr int PX = bytes(BX + 8) <= 40 * 1024 ? BX + 8 : BX;
+  static constexpr int NB = PX * BY * BZ;  // elements per field
+  static constexpr bool STAGE = SL_STAGE3D && bytes(PX) <= 48 * 1024;
   // Waves per SIMD the register budget targets: four workgroups per CU when
   // their boxes fit 160 KB of LDS, three otherwise.
-  static constexpr int WAVES =
-      STAGE && NF * (int)sizeof(T) * NB <= 40 * 1024 ? 4 : 3;
+  static constexpr int WAVES = STAGE && bytes(PX) <= 40 * 1024 ? 4 : 3;
 };
 
 // Element solve in cell r for the search.  When no active lane's cell
@@ -215,7 +221,7 @@ __global__ __launch_bounds__(kTileThreads, (Box3D<T, NF>::WAVES)) void recon3d_k
       const int gl = gxy + sz * gz;
 #pragma unroll
       for (int f = 0; f < nf; ++f)
-        lval[f * X::NB + (int)threadIdx.x + kTileThreads * bz] =
+        lval[f * X::NB + bx + X::PX * by + X::PX * X::BY * bz] =
             static_cast<const T*>(fp.in[f])[gl];
       gz = gz + 1 == g.n[2] ? 0 : gz + 1;
     }
@@ -253,7 +259,7 @@ __global__ __launch_bounds__(kTileThreads, (Box3D<T, NF>::WAVES)) void recon3d_k
         lb[a] = r[a] - 2 - ox[a];
         inbox = inbox && (unsigned)lb[a] <= (unsigned)(B[a] - 6);
       }
-      const int lbase = lb[0] + X::BX * (lb[1] + X::BY * lb[2]);
+      const int lbase = lb[0] + X::PX * (lb[1] + X::BY * lb[2]);
       const bool lim = g.limiter && g.order_max > 0;
       unsigned or6 = 0, or4 = 0;
       if (lim) {
@@ -290,7 +296,7 @@ __global__ __launch_bounds__(kTileThreads, (Box3D<T, NF>::WAVES)) void recon3d_k
         if (inbox) {
           const T* lv = lval + f * X::NB + lbase;
           v = zsum3d<T>(wx, wy, wz, [&](int kx, int ky, int kz) {
-            return lv[kx + X::BX * (ky + X::BY * kz)];
+            return lv[kx + X::PX * (ky + X::BY * kz)];
           });
         } else if (fast) {
           const __amdgpu_buffer_rsrc_t rs = field_rsrc(fp.in[f], fbytes);
