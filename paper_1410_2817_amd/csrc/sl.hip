@@ -302,7 +302,7 @@ hipError_t launch_recon(sl_grid* gr, const sl::FieldPtrs& fp, char* ws, const do
 #define SL_RECON3D(NF)                                                                       \
   case NF:                                                                                   \
     return launch(sl::recon3d_kernel<T, NF>, grid, block, 0, s, e0, e1, gr->g, fp, disp, ord, \
-                  stats, tiles_x, tiles_y, ntiles, buf_ok, dbuf_ok);
+                  stats, tiles_x, tiles_y, ntiles, buf_ok, dbuf_ok, nt, gr->v);
     switch (gr->g.nfields) {
       SL_RECON3D(1)
       SL_RECON3D(2)
@@ -313,7 +313,7 @@ hipError_t launch_recon(sl_grid* gr, const sl::FieldPtrs& fp, char* ws, const do
       SL_RECON3D(7)
       default:
         return launch(sl::recon3d_kernel<T, 8>, grid, block, 0, s, e0, e1, gr->g, fp, disp, ord,
-                      stats, tiles_x, tiles_y, ntiles, buf_ok, dbuf_ok);
+                      stats, tiles_x, tiles_y, ntiles, buf_ok, dbuf_ok, nt, gr->v);
     }
 #undef SL_RECON3D
   }
@@ -579,11 +579,10 @@ int sl_advance(sl_grid* gr, void* workspace, void* const* fields_a, void* const*
   const int K = gr->desc.reconstruct_every;
   if (nsteps % K) return SL_EINVAL;
   if (gr->steps_since_reset != 0) return SL_ESTATE;
-  if (K == 1 && nsteps > 0 && gr->desc.dim == 2) {
+  if (K == 1 && nsteps > 0) {
     // Each reconstruction also integrates the next step's trajectories into
     // the other displacement buffer, so a step is one reconstruction launch
     // (plus the limiter order words) after the first step's trajectories.
-    // (3-D steps are long enough that the separate launch costs nothing.)
     if (!workspace || ((uintptr_t)workspace) % kAlign) return SL_EINVAL;
     sl::FieldPtrs ab, ba;
     int rc = field_ptrs(gr, (const void* const*)fields_a, fields_b, &ab);

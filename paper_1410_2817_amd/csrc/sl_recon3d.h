@@ -161,12 +161,13 @@ __device__ __forceinline__ int cell_solve3d(const GridArgs& g, const double* __r
 
 // `ord` holds the window words (null when the limiter is off); `buf_ok` is
 // non-zero when one field's bytes fit the 31-bit buffer offsets, `dbuf_ok`
-// when one displacement component's do.
+// when one displacement component's do; `nt` / `v`: the next step's
+// trajectories of the tile's nodes (NextTraj).
 template <typename T, int NF>
 __global__ __launch_bounds__(kTileThreads, (Box3D<T, NF>::WAVES)) void recon3d_kernel(
     GridArgs g, FieldPtrs fp, const double* __restrict__ gdisp,
     const uint16_t* __restrict__ ord, unsigned long long* __restrict__ stats, int tiles_x,
-    int tiles_y, int ntiles, int buf_ok, int dbuf_ok) {
+    int tiles_y, int ntiles, int buf_ok, int dbuf_ok, NextTraj nt, VelArgs v) {
   using C = Tile3D;
   using X = Box3D<T, NF>;
   constexpr int nf = NF;
@@ -187,6 +188,10 @@ __global__ __launch_bounds__(kTileThreads, (Box3D<T, NF>::WAVES)) void recon3d_k
   const int sy = g.n[0], sz = g.n[0] * g.n[1];
   const int lin = x + sy * y + sz * z;
   const int tgt[3] = {x, y, z};
+
+  // The next step's trajectory of this work-item's lattice node (NextTraj);
+  // it touches nothing the reconstruction below reads.
+  if (nt.disp && act) traj_any<3>(g, v, nt.disp, nt.st, nt.dt, nt.integrator, tgt);
 
   // 1. Own displacement and start cell.
   double d0[3] = {0.0, 0.0, 0.0};

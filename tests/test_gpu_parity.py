@@ -268,10 +268,15 @@ def test_jump_flags_at_ties_fp32(B, torch, orc, theta):
         assert np.abs(a_ - b_).max() <= 1e-5 * np.abs(b_).max()
 
 
-def test_per_call_path_equals_advance(B, torch):
+@pytest.mark.parametrize("name,wl", [
+    ("swirl96_f32", W.swirl_three_fields(96, value_prec="f32")),
+    ("fourier3d_28_f32", W.fourier3d_three_fields(28, value_prec="f32")),
+    ("deform3d_24_f64", W.deform3d_slotted_sphere(24)),
+])
+def test_per_call_path_equals_advance(B, torch, name, wl):
     """sl_step / sl_reconstruct called one by one give the same bits as
-    sl_advance, and kernel events do not change results."""
-    wl = W.swirl_three_fields(96, value_prec="f32")
+    sl_advance (where each reconstruction also integrates the next step's
+    trajectories), and kernel events do not change results."""
     a, _, _, _ = gpu_run(B, torch, wl, nsteps=4, t0=0.6)
     g = B.Grid.from_workload(wl)
     g.profile(True)
