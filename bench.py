@@ -219,10 +219,10 @@ def main():
 
     value = nodes * args.steps / elapsed
     vb = 4 if args.prec == "f32" else 8
-    # In a 2-D run each reconstruction launch also integrates the next step's
+    # Each reconstruction launch of sl_advance also integrates the next step's
     # trajectories (all launches but the last), so it writes their
     # displacements too.
-    per_node = recon_bytes_per_node(dim, wl.nfields, vb) + (traj_bytes_per_node(2) if dim == 2 else 0)
+    per_node = recon_bytes_per_node(dim, wl.nfields, vb) + traj_bytes_per_node(dim)
     achieved = per_node * nodes / (recon_ms * 1e-3) / 1e9 if recon_ms > 0 else None
 
     # Accuracy: after a whole period the exact solution is the initial state.
@@ -256,8 +256,8 @@ def main():
             "dt": wl.dt, "t_end": args.steps * wl.dt,
         },
         "roofline": {
-            "kernel": ("reconstruction + next step's trajectories (recon2d_tiled_kernel)"
-                       if dim == 2 else "reconstruction (recon3d_kernel)"),
+            "kernel": "reconstruction + next step's trajectories (%s)" % (
+                "recon2d_tiled_kernel" if dim == 2 else "recon3d_kernel"),
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS if achieved else None,
             "traffic": recorded_traffic() if headline else None,
@@ -377,7 +377,7 @@ def other_configs():
         out, el, prof, st = run_gpu(wl, nsteps, prec=prec)
         rms = prof["recon_ms"] / max(prof["recon_launches"], 1)
         vb = 4 if prec == "f32" else 8
-        per_node = recon_bytes_per_node(3, wl.nfields, vb)
+        per_node = recon_bytes_per_node(3, wl.nfields, vb) + traj_bytes_per_node(3)
         ach = per_node * wl.nodes / (rms * 1e-3) / 1e9
         res[name] = {"node_updates_per_s": wl.nodes * nsteps / el, "ms_per_step": el * 1e3 / nsteps,
                      "steps": nsteps, "reconstruction_avg_ms": rms,
