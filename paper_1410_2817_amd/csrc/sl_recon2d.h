@@ -472,17 +472,25 @@ __device__ __forceinline__ void recon2d_tile(const GridArgs& g, const FieldPtrs&
 #pragma unroll
       for (int f = 0; f < nf; ++f) field_value(f, w2x, w2y);
     } else {
-      T w1x[6], w1y[6], w0x[6], w0y[6];
-      zspline_weights<T>(g.order_max > 1 ? 1 : 0, tx, w1x);
-      zspline_weights<T>(g.order_max > 1 ? 1 : 0, ty, w1y);
-      zspline_weights<T>(0, tx, w0x);
-      zspline_weights<T>(0, ty, w0y);
+      // A lowered order usually concerns one field of a wave: a field takes
+      // the lower-order weights and the per-lane select only where some lane
+      // of the wave lowers it (evaluated per such field, which keeps them
+      // out of the registers live across fields).
 #pragma unroll
       for (int f = 0; f < nf; ++f) {
         const int m = pick_order(g.order_max, or6, or4, f);
-        const int drop = g.order_max - m;  // 0, 1 or 2 orders below the top
         c0 += m == 0;
         c1 += m == 1;
+        if (__ballot(m != g.order_max) == 0ull) {
+          field_value(f, w2x, w2y);
+          continue;
+        }
+        T w1x[6], w1y[6], w0x[6], w0y[6];
+        zspline_weights<T>(g.order_max > 1 ? 1 : 0, tx, w1x);
+        zspline_weights<T>(g.order_max > 1 ? 1 : 0, ty, w1y);
+        zspline_weights<T>(0, tx, w0x);
+        zspline_weights<T>(0, ty, w0y);
+        const int drop = g.order_max - m;  // 0, 1 or 2 orders below the top
         T wx[6], wy[6];
 #pragma unroll
         for (int q = 0; q < 6; ++q) {
