@@ -25,7 +25,7 @@ _LIB = os.path.join(_HERE, "libsl_oracle.so")
 
 OK, EINVAL, ESEARCH, ENEWTON = 0, -1, -4, -5
 RK4, RK3_WILLIAMSON = 0, 1
-VEL_UNIFORM, VEL_SOLID_BODY, VEL_SWIRL2D, VEL_DEFORM3D, VEL_FOURIER = range(5)
+VEL_UNIFORM, VEL_SOLID_BODY, VEL_SWIRL2D, VEL_DEFORM3D, VEL_FOURIER, VEL_GRIDDED = range(6)
 
 
 def build(force: bool = True) -> str:
@@ -49,6 +49,7 @@ class _Problem(C.Structure):
         ("newton_max_iter", C.c_int), ("newton_tol", C.c_double),
         ("walk_max", C.c_int), ("eps_inside", C.c_double),
         ("scan_radius", C.c_int),
+        ("ugrid", C.POINTER(C.c_double) * 3),
     ]
 
 
@@ -132,6 +133,9 @@ class Problem:
     walk_max: int = 32
     eps_inside: float = 1e-12
     scan_radius: int = 4
+    # VEL_GRIDDED: velocity components on the mesh nodes, each of `shape`
+    # (array order), listed x-first; vp[0] is the interpolation order.
+    ugrid: Sequence[np.ndarray] | None = None
 
     @property
     def dim(self) -> int:
@@ -167,6 +171,11 @@ class Problem:
         p.walk_max = self.walk_max
         p.eps_inside = self.eps_inside
         p.scan_radius = self.scan_radius
+        if self.ugrid is not None:
+            keep = [np.ascontiguousarray(u, dtype=np.float64) for u in self.ugrid]
+            self._ugrid_keep = keep
+            for a, u in enumerate(keep):
+                p.ugrid[a] = u.ctypes.data_as(C.POINTER(C.c_double))
         return p
 
 

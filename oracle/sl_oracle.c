@@ -52,7 +52,8 @@ enum {
   ORC_VEL_SOLID_BODY = 1,
   ORC_VEL_SWIRL2D = 2,
   ORC_VEL_DEFORM3D = 3,
-  ORC_VEL_FOURIER = 4
+  ORC_VEL_FOURIER = 4,
+  ORC_VEL_GRIDDED = 5
 };
 
 /* Problem description, mirrored field by field by the ctypes binding. */
@@ -74,6 +75,7 @@ typedef struct {
   int walk_max;
   double eps_inside;    /* slack on the unit cube when accepting an element */
   int scan_radius;      /* half-width of the fallback scan box */
+  const double *ugrid[3]; /* GRIDDED: velocity components on the mesh nodes */
 } orc_problem;
 
 typedef struct {
@@ -126,6 +128,12 @@ void orc_weights(int m, double t, double *w) {
   for (int k = -m; k <= m + 1; ++k) w[k + m] = orc_zspline(m, t - (double)k);
 }
 
+/* Periodic index in [0, n). */
+static int64_t orc_wrap(int64_t i, int64_t n) {
+  int64_t r = i % n;
+  return r < 0 ? r + n : r;
+}
+
 /* ------------------------------------------------------------------------- */
 /* Prescribed velocity fields u(x,t) in physical coordinates.
  *   UNIFORM     u = (p0, p1, p2)
@@ -138,7 +146,9 @@ void orc_weights(int m, double t, double *w) {
  *   FOURIER     divergence-free sum of modes (k, a, phase), theta = 2 pi k.x/L + phase
  *               2-D: psi = sum a0/|k|^2 sin(theta), u = (d psi/dy, -d psi/dx)
  *               3-D: A = sum a/|k|^2 sin(theta),     u = curl A
- *               all scaled by p0.                                            */
+ *               all scaled by p0.
+ *   GRIDDED     samples of u on the mesh nodes (ugrid), interpolated with
+ *               the Z-spline of order p0                                     */
 void orc_velocity(const orc_problem *P, const double *x, double t, double *u) {
   const double pi = M_PI;
   u[0] = u[1] = u[2] = 0.0;
@@ -190,6 +200,34 @@ void orc_velocity(const orc_problem *P, const double *x, double t, double *u) {
         }
       }
       for (int a = 0; a < P->dim; ++a) u[a] *= P->vp[0];
+      break;
+    }
+    case ORC_VEL_GRIDDED: {
+      /* Velocity given on the reference mesh, interpolated at x with the
+       * tensor-product cardinal Z-spline of order vp[0] (eq. "multiZ" applied
+       * to the velocity samples; periodic). */
+      const int m = (int)P->vp[0];
+      int64_t r[3] = {0, 0, 0};
+      double w[3][6];
+      for (int a = 0; a < 3; ++a)
+        for (int k = 0; k < 6; ++k) w[a][k] = a < P->dim ? 0.0 : 1.0;
+      for (int a = 0; a < P->dim; ++a) {
+        const double s = x[a] / (P->len[a] / (double)P->n[a]);
+        r[a] = (int64_t)floor(s);
+        orc_weights(m, s - (double)r[a], w[a]);
+      }
+      const int np = 2 * m + 2;
+      const int nz = P->dim == 3 ? np : 1;
+      for (int kz = 0; kz < nz; ++kz)
+        for (int ky = 0; ky < np; ++ky)
+          for (int kx = 0; kx < np; ++kx) {
+            const int64_t ix = orc_wrap(r[0] - m + kx, P->n[0]);
+            const int64_t iy = orc_wrap(r[1] - m + ky, P->n[1]);
+            const int64_t iz = P->dim == 3 ? orc_wrap(r[2] - m + kz, P->n[2]) : 0;
+            const int64_t lin = ix + P->n[0] * (iy + P->n[1] * iz);
+            const double wt = w[0][kx] * w[1][ky] * (P->dim == 3 ? w[2][kz] : 1.0);
+            for (int a = 0; a < P->dim; ++a) u[a] += wt * P->ugrid[a][lin];
+          }
       break;
     }
     default:

@@ -1,0 +1,78 @@
+"""Write the oracle's results of long runs of the benchmark workloads, sampled
+at a fixed set of mesh nodes, for the GPU full-run parity tests.
+
+Only the oracle (oracle/) and the seeded input generators run here; nothing
+comes from the GPU path.  Each case stores, as a compressed .npz:
+  nodes   flat indices of the sampled mesh nodes (random, plus nodes next to
+          the initial discontinuity of field 0)
+  values  the oracle's field values there after `steps` steps, shape
+          (len(nodes), nfields)
+  l1      sum over all nodes of |value| per field (a whole-grid check)
+  t0, dt, steps
+
+Run from the repository root:  python tests/golden/make_oracle_runs.py [case ...]
+(several minutes per case on a few cores).
+"""
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+from paper_1410_2817_amd import workloads as W  # noqa: E402
+
+
+def cases():
+    # name: (workload factory, steps, t0); the oracle runs in FP64 from the
+    # values as stored by the GPU form named in the workload (FP32-rounded for
+    # the split form).
+    return {
+        "swirl1024_period": (lambda: W.swirl_three_fields(1024, value_prec="f32"), 1280, 0.0),
+        "fourier3d256_50": (lambda: W.fourier3d_three_fields(256, value_prec="f32"), 50, 0.0),
+        "deform3d512_10": (lambda: W.deform3d_slotted_sphere(512), 10, 0.0),
+    }
+
+
+def stored(wl):
+    if wl.value_prec == "f32":
+        return [np.asarray(f, dtype=np.float32).astype(np.float64) for f in wl.fields]
+    return [np.asarray(f, dtype=np.float64) for f in wl.fields]
+
+
+def sample_nodes(wl, seed=2024, nrand=6000, nedge=2000):
+    g = np.random.Generator(np.random.PCG64(seed))
+    f0 = wl.fields[0].ravel()
+    edge = np.nonzero(np.abs(np.diff(f0, append=f0[:1])) > 0)[0]
+    pick = [g.integers(0, wl.nodes, nrand)]
+    if edge.size:
+        pick.append(g.choice(edge, min(nedge, edge.size), replace=False))
+    return np.unique(np.concatenate(pick)).astype(np.int64)
+
+
+def run(name):
+    make, steps, t0 = cases()[name]
+    wl = make()
+    prob = oracle.Problem(wl.shape, wl.nfields, wl.length, order_max=wl.order_max,
+                          limiter=wl.limiter, theta=wl.theta, integrator=wl.integrator,
+                          vel_kind=wl.velocity.kind, vp=wl.velocity.padded_params(),
+                          modes=wl.velocity.modes)
+    t = time.time()
+    rc, fields, st = oracle.run(prob, t0, wl.dt, steps, stored(wl))
+    assert rc == 0, (name, rc, st)
+    nodes = sample_nodes(wl)
+    values = np.stack([f.ravel()[nodes] for f in fields], axis=1)
+    l1 = np.array([np.abs(f).sum() for f in fields])
+    out = os.path.join(os.path.dirname(os.path.abspath(__file__)), "oracle_%s.npz" % name)
+    np.savez_compressed(out, nodes=nodes, values=values, l1=l1, t0=t0, dt=wl.dt, steps=steps)
+    print(name, "steps", steps, "oracle s %.0f" % (time.time() - t), "threads", oracle.threads(),
+          "->", os.path.basename(out), flush=True)
+
+
+if __name__ == "__main__":
+    oracle.build()
+    for name in (sys.argv[1:] or list(cases())):
+        run(name)

@@ -518,3 +518,76 @@ def test_swirl_returns_after_one_period(orc):
     assert e[2] < 3e-3 and math.log2(e[1] / e[2]) > 2.3, e
     e = errs[True]
     assert e[0] > e[1] > e[2] and e[2] < 0.2, e
+
+
+# --------------------------------------------------------------------------
+# Gridded velocity (velocity given on the reference mesh, interpolated with
+# the Z-spline of eq. "multiZ"; the paper's velocity "given ... or as part of
+# the transported quantities", Sec. 2)
+
+def _gridded_problem(orc, shape, ugrid, m, length=None):
+    return orc.Problem(shape, 1, length, vel_kind=orc.VEL_GRIDDED, vp=[float(m)], ugrid=ugrid)
+
+
+@pytest.mark.parametrize("m", [0, 1, 2])
+def test_gridded_velocity_is_cardinal_and_uniform_exact(orc, m):
+    # At a mesh node the interpolant returns the sample itself; a constant
+    # field moves every lattice node by u dt exactly (up to rounding).
+    shape = (12, 16)
+    g = np.random.default_rng(3)
+    ux, uy = g.normal(size=shape), g.normal(size=shape)
+    prob = _gridded_problem(orc, shape, [ux, uy], m)
+    h = 1.0 / np.array([16, 12])
+    for (j, i) in [(0, 0), (5, 7), (11, 15)]:
+        u = orc.velocity(prob, [i * h[0], j * h[1]], 0.0)
+        assert abs(u[0] - ux[j, i]) < 1e-15 and abs(u[1] - uy[j, i]) < 1e-15
+    c = [np.full(shape, 0.37), np.full(shape, -0.21)]
+    prob = _gridded_problem(orc, shape, c, m)
+    d = orc.trajectory(prob, [3, 4], 0.0, 0.05)
+    assert np.allclose(d, [0.37 * 0.05 * 16, -0.21 * 0.05 * 12], rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("m", [1, 2])
+def test_gridded_velocity_reproduces_polynomials(orc, m):
+    # Polynomials of degree <= 2m are reproduced away from the periodic seam
+    # (property (b)); degree 2m+1 is not.
+    n = 32
+    shape = (n, n)
+    y, x = np.meshgrid(np.arange(n) / n, np.arange(n) / n, indexing="ij")
+    g = np.random.default_rng(5)
+    pts = g.uniform(0.35, 0.65, size=(20, 2))
+
+    def poly(deg, X, Y):
+        return (0.3 + X - 0.5 * Y) * (X - 0.4) ** (deg - 1) + 0.1 * Y ** deg
+
+    for deg, exact in [(2 * m, True), (2 * m + 1, False)]:
+        ux = poly(deg, x, y)
+        uy = poly(deg, y, x)
+        prob = _gridded_problem(orc, shape, [ux, uy], m)
+        err = max(max(abs(orc.velocity(prob, p, 0.0)[0] - poly(deg, p[0], p[1])),
+                      abs(orc.velocity(prob, p, 0.0)[1] - poly(deg, p[1], p[0])))
+                  for p in pts)
+        if exact:
+            assert err < 1e-12, (deg, err)
+        else:
+            assert err > 1e-9, (deg, err)
+
+
+def test_gridded_velocity_converges_to_the_analytic_flow(orc):
+    # Sampling the analytic Fourier flow on finer meshes: the Z2 interpolant
+    # converges at order >= 4 (it reproduces quartics).
+    errs = []
+    g = np.random.default_rng(8)
+    pts = g.uniform(0, 1, size=(30, 2))
+    w2 = W.serving_request(W.rng(4), 0, 0.0, sides=(128,)).workload
+    for n in (16, 32, 64):
+        ana = orc.Problem((n, n), 1, vel_kind=orc.VEL_FOURIER, vp=[1.0], modes=w2.velocity.modes)
+        xs = np.arange(n) / n
+        ux = np.zeros((n, n)); uy = np.zeros((n, n))
+        for j in range(n):
+            for i in range(n):
+                ux[j, i], uy[j, i] = orc.velocity(ana, [xs[i], xs[j]], 0.0)
+        grid = _gridded_problem(orc, (n, n), [ux, uy], 2)
+        errs.append(max(np.abs(orc.velocity(grid, p, 0.0) - orc.velocity(ana, p, 0.0)).max()
+                        for p in pts))
+    assert errs[0] / errs[1] > 2 ** 3.5 and errs[1] / errs[2] > 2 ** 3.5, errs
