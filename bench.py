@@ -264,6 +264,7 @@ def main():
             "bytes_per_node": per_node, "avg_ms": recon_ms,
             "launches": prof["recon_launches"],
         },
+        "field_node_updates_per_s": value * wl.nfields,
         "kernels": {"trajectories_avg_ms": traj_ms, "reconstruction_avg_ms": recon_ms,
                     "order_words_avg_ms": orders_ms, "event_period": args.event_period},
         "accuracy": acc,

@@ -90,13 +90,21 @@ enum { SL_RK4 = 0, SL_RK3_WILLIAMSON = 1 };
  *                      length[a] + phase and |k|^2 = sum_a k_a^2:
  *                      2-D: psi = sum a_x / |k|^2 sin(theta), u = (psi_y, -psi_x)
  *                      3-D: A = sum a / |k|^2 sin(theta),     u = curl A
- *                      all multiplied by p0.                                   */
+ *                      all multiplied by p0.
+ *   SL_VEL_GRIDDED     u given on the mesh nodes (sl_set_velocity_field) and
+ *                      interpolated at the trajectory points with the
+ *                      tensor-product cardinal Z-spline of order p0 = 0, 1 or
+ *                      2 (eq. "multiZ" applied to the samples; periodic).  The
+ *                      paper lets the velocity be given or carried with the
+ *                      fields (Sec. 2); the samples are held fixed within a
+ *                      step (all stages of a step use them).                  */
 enum {
   SL_VEL_UNIFORM = 0,
   SL_VEL_SOLID_BODY = 1,
   SL_VEL_SWIRL2D = 2,
   SL_VEL_DEFORM3D = 3,
-  SL_VEL_FOURIER = 4
+  SL_VEL_FOURIER = 4,
+  SL_VEL_GRIDDED = 5
 };
 
 typedef struct sl_velocity {
@@ -156,10 +164,18 @@ int sl_destroy_grid(sl_grid *grid);
  * workspace must be 256-byte aligned and zero-filled before its first use. */
 size_t sl_workspace_bytes(const sl_grid *grid);
 
+/* SL_VEL_GRIDDED: the velocity samples for later sl_step / sl_advance calls.
+ * `components` holds `dim` device pointers (x first), each n[0]*n[1](*n[2])
+ * FP64 values in physical units on the mesh nodes, x fastest.  The caller
+ * owns them; they must stay valid until the launches that use them have run
+ * (each launch reads the pointers current when it is queued).
+ * Errors: SL_EINVAL (NULL argument, or the grid's velocity is not gridded). */
+int sl_set_velocity_field(sl_grid *grid, const double *const *components);
+
 /* Integrate the lattice trajectories over [t, t+dt] (Sec. 2).  The first step
  * after a reset starts every lattice node on its mesh node; later steps
  * continue from the stored displacement.  Asynchronous on `stream`.
- * Errors: SL_EINVAL, SL_EHIP. */
+ * Errors: SL_EINVAL, SL_ESTATE (gridded velocity without samples), SL_EHIP. */
 int sl_step(sl_grid *grid, void *workspace, double t, double dt, void *stream);
 
 /* Reconstruct all fields on the mesh from the moved lattice and reset the
@@ -258,7 +274,8 @@ int sl_server_destroy(sl_server *server);
  * value precision; the copy is queued on the server's stream, so the sources
  * must stay valid until that stream reaches it) into the arena and schedule
  * nsteps steps of dt from t0.  *id identifies it.
- * Errors: SL_EINVAL (bad descriptor, 3-D grid, reconstruct_every != 1),
+ * Errors: SL_EINVAL (bad descriptor, 3-D grid, gridded velocity,
+ * reconstruct_every != 1),
  * SL_EBUSY (no room), SL_EHIP. */
 int sl_server_admit(sl_server *server, const sl_grid_desc *desc,
                     const void *const *fields_in, double t0, double dt, int nsteps,

@@ -77,6 +77,7 @@ SIGNATURES = {
     "sl_create_grid": (C.c_int, [C.POINTER(SlGridDesc), C.POINTER(_VP)]),
     "sl_destroy_grid": (C.c_int, [_VP]),
     "sl_workspace_bytes": (C.c_size_t, [_VP]),
+    "sl_set_velocity_field": (C.c_int, [_VP, C.POINTER(C.POINTER(C.c_double))]),
     "sl_step": (C.c_int, [_VP, _VP, C.c_double, C.c_double, _VP]),
     "sl_reconstruct": (C.c_int, [_VP, _VP, C.POINTER(_VP), C.POINTER(_VP), _VP]),
     "sl_sync": (C.c_int, [_VP, _VP, _VP, C.POINTER(SlStats)]),
@@ -212,7 +213,20 @@ class Grid:
                   reconstruct_every=wl.reconstruct_every, vel_kind=wl.velocity.kind,
                   vel_params=wl.velocity.padded_params(), modes=wl.velocity.modes)
         kw.update(over)
-        return cls(wl.shape, wl.nfields, device=device, **kw)
+        g = cls(wl.shape, wl.nfields, device=device, **kw)
+        if getattr(wl, "ugrid", None) is not None and kw["vel_kind"] == 5:
+            g.set_velocity_field(wl.ugrid)
+        return g
+
+    def set_velocity_field(self, components):
+        """Gridded velocity: copy the samples (components x-first, each of the
+        grid's shape) to the device and hand them to the library."""
+        import torch
+        self._ugrid = [torch.as_tensor(np.asarray(u, dtype=np.float64), device=self.device)
+                       .contiguous() for u in components]
+        ptrs = (C.POINTER(C.c_double) * len(self._ugrid))(
+            *[C.cast(C.c_void_p(u.data_ptr()), C.POINTER(C.c_double)) for u in self._ugrid])
+        check(load().sl_set_velocity_field(self._h, ptrs), "sl_set_velocity_field")
 
     @property
     def nodes(self) -> int:

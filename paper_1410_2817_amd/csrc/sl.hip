@@ -141,7 +141,9 @@ int check_desc(const sl_grid_desc* d) {
   // Launch-grid limits of the y and z grid dimensions.
   if (d->n[1] > 4 * 65535 || (d->dim == 3 && d->n[2] > 65535)) return SL_EINVAL;
   const sl_velocity& v = d->vel;
-  if (v.kind < SL_VEL_UNIFORM || v.kind > SL_VEL_FOURIER) return SL_EINVAL;
+  if (v.kind < SL_VEL_UNIFORM || v.kind > SL_VEL_GRIDDED) return SL_EINVAL;
+  if (v.kind == SL_VEL_GRIDDED && !(v.p[0] == 0.0 || v.p[0] == 1.0 || v.p[0] == 2.0))
+    return SL_EINVAL;
   if (v.kind == SL_VEL_SWIRL2D && (d->dim != 2 || !(v.p[0] != 0.0))) return SL_EINVAL;
   if (v.kind == SL_VEL_DEFORM3D && (d->dim != 3 || !(v.p[0] != 0.0))) return SL_EINVAL;
   if (v.kind == SL_VEL_FOURIER) {
@@ -201,6 +203,8 @@ hipError_t launch_traj(sl_grid* gr, double* disp, double t, double dt, int accum
       return launch(sl::traj_kernel<D, SL_VEL_SWIRL2D>, blocks, threads, 0, s, e0, e1, gr->g, gr->v, disp, st, dt, accumulate, integ);
     case SL_VEL_DEFORM3D:
       return launch(sl::traj_kernel<D, SL_VEL_DEFORM3D>, blocks, threads, 0, s, e0, e1, gr->g, gr->v, disp, st, dt, accumulate, integ);
+    case SL_VEL_GRIDDED:
+      return launch(sl::traj_kernel<D, SL_VEL_GRIDDED>, blocks, threads, 0, s, e0, e1, gr->g, gr->v, disp, st, dt, accumulate, integ);
     default:
       return launch(sl::traj_kernel<D, SL_VEL_FOURIER>, blocks, threads, 0, s, e0, e1, gr->g, gr->v, disp, st, dt, accumulate, integ);
   }
@@ -383,6 +387,13 @@ int sl_create_grid(const sl_grid_desc* desc, sl_grid** out) {
   memset(&v, 0, sizeof(v));
   v.kind = desc->vel.kind;
   for (int c = 0; c < 8; ++c) v.p[c] = desc->vel.p[c];
+  if (v.kind == SL_VEL_GRIDDED) {
+    v.ug_m = (int)desc->vel.p[0];
+    for (int a = 0; a < 3; ++a) {
+      v.ug_n[a] = g.n[a];
+      v.ug_h[a] = g.h[a];
+    }
+  }
   if (v.kind == SL_VEL_FOURIER) {
     v.nmodes = desc->vel.nmodes;
     const double pi = M_PI;
@@ -443,8 +454,17 @@ int sl_destroy_grid(sl_grid* grid) {
 
 size_t sl_workspace_bytes(const sl_grid* grid) { return grid ? grid->ws_bytes : 0; }
 
+int sl_set_velocity_field(sl_grid* gr, const double* const* components) {
+  if (!gr || !components || gr->v.kind != SL_VEL_GRIDDED) return SL_EINVAL;
+  for (int a = 0; a < gr->desc.dim; ++a)
+    if (!components[a]) return SL_EINVAL;
+  for (int a = 0; a < gr->desc.dim; ++a) gr->v.ug[a] = components[a];
+  return SL_OK;
+}
+
 int sl_step(sl_grid* gr, void* workspace, double t, double dt, void* stream) {
   if (!gr || !workspace || !isfinite(t) || !isfinite(dt)) return SL_EINVAL;
+  if (gr->v.kind == SL_VEL_GRIDDED && !gr->v.ug[0]) return SL_ESTATE;
   if (((uintptr_t)workspace) % kAlign) return SL_EINVAL;
   hipStream_t s = static_cast<hipStream_t>(stream);
   double* disp = reinterpret_cast<double*>(static_cast<char*>(workspace) + gr->off_disp);
@@ -579,7 +599,8 @@ int sl_advance(sl_grid* gr, void* workspace, void* const* fields_a, void* const*
   const int K = gr->desc.reconstruct_every;
   if (nsteps % K) return SL_EINVAL;
   if (gr->steps_since_reset != 0) return SL_ESTATE;
-  if (K == 1 && nsteps > 0) {
+  if (gr->v.kind == SL_VEL_GRIDDED && !gr->v.ug[0]) return SL_ESTATE;
+  if (K == 1 && nsteps > 0 && gr->v.kind != SL_VEL_GRIDDED) {
     // Each reconstruction also integrates the next step's trajectories into
     // the other displacement buffer, so a step is one reconstruction launch
     // (plus the limiter order words) after the first step's trajectories.

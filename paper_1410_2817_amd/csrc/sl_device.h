@@ -44,6 +44,12 @@ struct VelArgs {
   int nmodes;
   double p[8];
   Mode mode[SL_MAX_MODES];
+  // SL_VEL_GRIDDED: samples on the mesh (x first), mesh spacing and size,
+  // interpolation order.
+  const double* ug[3];
+  double ug_h[3];
+  int ug_n[3];
+  int ug_m;
 };
 
 struct FieldPtrs {
@@ -104,6 +110,9 @@ __device__ __forceinline__ void wave_count(unsigned long long* ctr, bool pred) {
 // Prescribed velocity u(x, t) (physical units).  `tf` is the time factor
 // cos(pi t / p0) of the periodic families, evaluated once per stage.
 
+template <typename T>
+__device__ __forceinline__ void zspline_weights(int m, T t, T* w);
+
 template <int VK, int D>
 __device__ __forceinline__ void velocity(const VelArgs& v, const double* x, double tf,
                                          double* u) {
@@ -140,6 +149,52 @@ __device__ __forceinline__ void velocity(const VelArgs& v, const double* x, doub
       for (int a = 0; a < D; ++a) th += md.c[a] * x[a];
       const double cs = cospi(th);
       for (int a = 0; a < D; ++a) u[a] += md.amp[a] * cs;
+    }
+  } else if constexpr (VK == SL_VEL_GRIDDED) {
+    // Tensor-product Z-spline interpolation of the mesh samples (eq. "multiZ"
+    // applied to the velocity), periodic; slot k holds node r - 2 + k.
+    int r[3] = {0, 0, 0};
+    double w[3][6];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const double sa = x[a] / v.ug_h[a];
+      r[a] = (int)floor(sa);
+      zspline_weights<double>(v.ug_m, sa - (double)r[a], w[a]);
+    }
+#pragma unroll
+    for (int a = 0; a < D; ++a) u[a] = 0.0;
+    // Slots outside the order's window carry zero weight and are skipped
+    // (wave-uniform tests on constant indices, so the weights stay in
+    // registers).
+    const int lo = 2 - v.ug_m, hi = 3 + v.ug_m;
+    const int nx = v.ug_n[0], ny = v.ug_n[1];
+#pragma unroll 1
+    for (int kz = (D == 3 ? lo : 0); kz <= (D == 3 ? hi : 0); ++kz) {
+      const int iz = D == 3 ? wrap_index(r[2] - 2 + kz, v.ug_n[2]) : 0;
+      // Rolled loop: wz by selects (a dynamic index would go to scratch).
+      double wz = 1.0;
+      if (D == 3) {
+        wz = w[2][5];
+#pragma unroll
+        for (int q = 4; q >= 0; --q) wz = kz == q ? w[2][q] : wz;
+      }
+#pragma unroll
+      for (int ky = 0; ky < 6; ++ky) {
+        if (ky < lo || ky > hi) continue;
+        const int iy = wrap_index(r[1] - 2 + ky, ny);
+        const int row = nx * (iy + ny * iz);
+        double sx[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kx = 0; kx < 6; ++kx) {
+          if (kx < lo || kx > hi) continue;
+          const int lin = row + wrap_index(r[0] - 2 + kx, nx);
+#pragma unroll
+          for (int a = 0; a < D; ++a) sx[a] = fma(v.ug[a][lin], w[0][kx], sx[a]);
+        }
+        const double wyz = w[1][ky] * wz;
+#pragma unroll
+        for (int a = 0; a < D; ++a) u[a] = fma(sx[a], wyz, u[a]);
+      }
     }
   } else {
     // Combinations rejected at grid creation (a 3-D family on a 2-D grid).

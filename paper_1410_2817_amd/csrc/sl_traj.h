@@ -102,6 +102,8 @@ __device__ __forceinline__ void traj_node(const GridArgs& g, const VelArgs& v,
 
 // Trajectory of lattice node idx from its mesh node (a fresh lattice) for
 // the grid's velocity family, chosen at run time (a wave-uniform switch).
+// Gridded velocities are not integrated here (their interpolation would
+// raise the register budget of every kernel that embeds this switch).
 template <int D>
 __device__ __forceinline__ void traj_any(const GridArgs& g, const VelArgs& v,
                                          double* __restrict__ disp, const StageTimes& st,

@@ -19,7 +19,7 @@ from typing import Sequence
 import numpy as np
 
 # Velocity kinds, numbered as in the C interface.
-VEL_UNIFORM, VEL_SOLID_BODY, VEL_SWIRL2D, VEL_DEFORM3D, VEL_FOURIER = range(5)
+VEL_UNIFORM, VEL_SOLID_BODY, VEL_SWIRL2D, VEL_DEFORM3D, VEL_FOURIER, VEL_GRIDDED = range(6)
 
 
 def rng(seed: int) -> np.random.Generator:
@@ -165,6 +165,9 @@ class Workload:
     value_prec: str = "f64"  # "f64" or "f32" (FP32 values, FP64 positions)
     integrator: int = 0      # 0 RK4, 1 Williamson low-storage RK3
     reconstruct_every: int = 1
+    # VEL_GRIDDED: velocity samples on the mesh, components x-first, each an
+    # array of `shape` (physical units).
+    ugrid: list | None = None
 
     @property
     def dim(self):
@@ -177,6 +180,64 @@ class Workload:
     @property
     def nodes(self):
         return int(np.prod(self.shape))
+
+
+def sample_velocity(wl: "Workload", t: float = 0.0) -> list:
+    """The analytic velocity of workload wl at the mesh nodes at time t
+    (components x-first, each an array of wl.shape): the input of a gridded
+    velocity run.  Part of the problem definition, not of the method."""
+    d = wl.dim
+    X = _xyz(wl.shape, wl.length)  # x, y[, z], broadcastable
+    L = list(wl.length)[::-1]      # physical-axis order
+    p = wl.velocity.padded_params()
+    kind = wl.velocity.kind
+    zero = np.zeros(wl.shape)
+    full = lambda a: np.broadcast_to(np.asarray(a, dtype=np.float64), wl.shape).copy()
+    pi = np.pi
+    if kind == VEL_UNIFORM:
+        u = [full(p[a]) for a in range(d)]
+    elif kind == VEL_SOLID_BODY:
+        u = [full(-p[0] * (X[1] - p[2])), full(p[0] * (X[0] - p[1]))] + ([zero.copy()] if d == 3 else [])
+    elif kind == VEL_SWIRL2D:
+        c = np.cos(pi * t / p[0])
+        u = [full(p[1] * np.sin(pi * X[0]) ** 2 * np.sin(2 * pi * X[1]) * c),
+             full(-p[1] * np.sin(pi * X[1]) ** 2 * np.sin(2 * pi * X[0]) * c)]
+    elif kind == VEL_DEFORM3D:
+        c = np.cos(pi * t / p[0])
+        s1 = [np.sin(pi * X[a]) for a in range(3)]
+        s2 = [np.sin(2 * pi * X[a]) for a in range(3)]
+        u = [full(2 * p[1] * s1[0] ** 2 * s2[1] * s2[2] * c),
+             full(-p[1] * s2[0] * s1[1] ** 2 * s2[2] * c),
+             full(-p[1] * s2[0] * s2[1] * s1[2] ** 2 * c)]
+    elif kind == VEL_FOURIER:
+        u = [zero.copy() for _ in range(d)]
+        for md in wl.velocity.modes:
+            k = md[0:d]
+            k2 = float(np.dot(k, k))
+            th = md[6] + 2 * pi * sum(k[a] * X[a] / L[a] for a in range(d))
+            g = [np.cos(th) * 2 * pi * k[a] / L[a] / k2 for a in range(d)]
+            if d == 2:
+                u[0] = u[0] + md[3] * g[1]
+                u[1] = u[1] - md[3] * g[0]
+            else:
+                a_ = md[3:6]
+                u[0] = u[0] + g[1] * a_[2] - g[2] * a_[1]
+                u[1] = u[1] + g[2] * a_[0] - g[0] * a_[2]
+                u[2] = u[2] + g[0] * a_[1] - g[1] * a_[0]
+        u = [full(ui * p[0]) for ui in u]
+    else:
+        raise ValueError("no analytic velocity for kind %d" % kind)
+    return u
+
+
+def gridded(wl: "Workload", order: int = 2, t: float = 0.0) -> "Workload":
+    """Workload wl with its velocity replaced by the mesh samples of its
+    analytic velocity at time t (held fixed), interpolated with the Z-spline
+    of the given order."""
+    import dataclasses
+    return dataclasses.replace(wl, name=wl.name + "_gridded%d" % order,
+                               velocity=Velocity(VEL_GRIDDED, [float(order)]),
+                               ugrid=sample_velocity(wl, t))
 
 
 def solid_body_gaussian(n: int = 64, steps: int = 100, order_max: int = 2) -> Workload:

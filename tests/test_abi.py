@@ -125,3 +125,29 @@ def test_fourier_modes_are_copied(lib):
     assert rc == 0
     keep[:] = np.nan  # the library must not read the caller's array later
     lib.sl_destroy_grid(h)
+
+
+def test_gridded_velocity_state_and_validation(lib):
+    """A gridded velocity needs its samples before stepping (checked on the
+    host, before any device work); the order must be 0..2; the setter only
+    applies to gridded grids and rejects NULL."""
+    d, _ = _desc(shape=(16, 16), vel_kind=5, vel_params=[2.0])
+    rc, h = _create(d)
+    assert rc == B.SL_OK
+    ws = C.c_void_p(1 << 20)
+    assert lib.sl_step(h, ws, 0.0, 0.1, None) == B.SL_ESTATE
+    assert lib.sl_advance(h, ws, None, None, 0.0, 0.1, 0, None, None) in (B.SL_EINVAL, B.SL_ESTATE)
+    assert lib.sl_set_velocity_field(h, None) == B.SL_EINVAL
+    null2 = (C.POINTER(C.c_double) * 2)()
+    assert lib.sl_set_velocity_field(h, null2) == B.SL_EINVAL
+    assert lib.sl_destroy_grid(h) == B.SL_OK
+    for order in (3.0, 0.5, -1.0):
+        d, _ = _desc(shape=(16, 16), vel_kind=5, vel_params=[order])
+        rc, h = _create(d)
+        assert rc == B.SL_EINVAL
+    d, _ = _desc(shape=(16, 16))
+    rc, h = _create(d)
+    fake = (C.POINTER(C.c_double) * 2)(C.cast(C.c_void_p(4096), C.POINTER(C.c_double)),
+                                      C.cast(C.c_void_p(8192), C.POINTER(C.c_double)))
+    assert lib.sl_set_velocity_field(h, fake) == B.SL_EINVAL
+    assert lib.sl_destroy_grid(h) == B.SL_OK

@@ -105,6 +105,10 @@ def _traj_cases():
     w2 = W.serving_request(W.rng(5), 0, 0.0, sides=(64,)).workload
     w2.value_prec = "f64"
     yield "fourier2d", w2
+    # Velocity given on the mesh (Z-spline interpolation of the samples).
+    yield "gridded_swirl_z2", W.gridded(W.swirl_three_fields(40, value_prec="f64"), 2, t=0.4)
+    yield "gridded_swirl_z0", W.gridded(W.swirl_three_fields(36, value_prec="f64"), 0, t=0.4)
+    yield "gridded_fourier3d_z1", W.gridded(W.fourier3d_three_fields(12, seed=3), 1)
 
 
 @pytest.mark.parametrize("name,wl", list(_traj_cases()))
@@ -145,6 +149,8 @@ def _step_cases():
     # ragged edge tile in every axis.
     yield "fourier3d_f32_50", W.fourier3d_three_fields(50, value_prec="f32"), 0.0
     yield "deform3d_f64_42", W.deform3d_slotted_sphere(42), 1.0
+    yield "gridded_swirl_f32", W.gridded(W.swirl_three_fields(96, value_prec="f32"), 2, t=1.3), 1.3
+    yield "gridded_deform3d_f64", W.gridded(W.deform3d_slotted_sphere(24), 1, t=0.5), 0.5
 
 
 @pytest.mark.parametrize("name,wl,t0", list(_step_cases()))
@@ -166,6 +172,7 @@ def test_single_step_parity(B, torch, orc, name, wl, t0):
     ("swirl64_f64", W.swirl_three_fields(64, value_prec="f64"), 20),
     ("swirl64_f32", W.swirl_three_fields(64, value_prec="f32"), 20),
     ("fourier3d16_f64", W.fourier3d_three_fields(16, value_prec="f64"), 6),
+    ("gridded_swirl64_f64", W.gridded(W.swirl_three_fields(64, value_prec="f64"), 2), 10),
 ])
 def test_multi_step_parity(B, torch, orc, name, wl, nsteps):
     say("run", name, nsteps)

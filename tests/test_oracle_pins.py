@@ -591,3 +591,33 @@ def test_gridded_velocity_converges_to_the_analytic_flow(orc):
         errs.append(max(np.abs(orc.velocity(grid, p, 0.0) - orc.velocity(ana, p, 0.0)).max()
                         for p in pts))
     assert errs[0] / errs[1] > 2 ** 3.5 and errs[1] / errs[2] > 2 ** 3.5, errs
+
+
+@pytest.mark.parametrize("name", ["swirl", "deform3d", "fourier2d", "fourier3d", "sbr"])
+def test_sampled_velocity_matches_the_analytic_family(orc, name):
+    # The gridded runs' inputs (mesh samples of an analytic flow, generated by
+    # the workload module) agree with the oracle's analytic velocity.
+    if name == "swirl":
+        wl, t = W.swirl_three_fields(20), 0.7
+    elif name == "deform3d":
+        wl, t = W.deform3d_slotted_sphere(10), 0.4
+    elif name == "fourier2d":
+        wl, t = W.serving_request(W.rng(2), 0, 0.0, sides=(128,)).workload, 0.0
+        wl.fields = [f[:24, :32].copy() for f in wl.fields]
+        wl.shape, wl.length = (24, 32), (0.75, 1.0)
+    elif name == "fourier3d":
+        wl, t = W.fourier3d_three_fields(10), 0.0
+    else:
+        wl, t = W.solid_body_gaussian(16), 0.0
+    u = W.sample_velocity(wl, t)
+    prob = orc.Problem(wl.shape, 1, wl.length, vel_kind=wl.velocity.kind,
+                       vp=wl.velocity.padded_params(), modes=wl.velocity.modes)
+    g = np.random.default_rng(1)
+    L = list(wl.length)[::-1]
+    n = list(wl.shape)[::-1]
+    for _ in range(25):
+        idx = [int(g.integers(0, n[a])) for a in range(wl.dim)]
+        x = [idx[a] * L[a] / n[a] for a in range(wl.dim)]
+        want = orc.velocity(prob, x, t)
+        got = [u[a][tuple(idx[::-1])] for a in range(wl.dim)]
+        assert np.allclose(got, want, rtol=1e-12, atol=1e-12), (idx, got, want)

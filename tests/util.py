@@ -7,7 +7,7 @@ def oracle_problem(orc, wl, **kw):
     return orc.Problem(wl.shape, wl.nfields, wl.length, order_max=wl.order_max,
                        limiter=wl.limiter, theta=wl.theta, integrator=wl.integrator,
                        vel_kind=wl.velocity.kind, vp=wl.velocity.padded_params(),
-                       modes=wl.velocity.modes, **kw)
+                       modes=wl.velocity.modes, ugrid=getattr(wl, "ugrid", None), **kw)
 
 
 def stored_values(wl):
