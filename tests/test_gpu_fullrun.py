@@ -65,7 +65,10 @@ def B():
 @pytest.mark.parametrize("case", list(WORKLOADS))
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_full_run_vs_oracle(B, torch, case, prec):
-    ref = np.load(os.path.join(GOLDEN, "oracle_%s.npz" % case), allow_pickle=False)
+    path = os.path.join(GOLDEN, "oracle_%s.npz" % case)
+    if not os.path.exists(path):
+        pytest.skip("oracle run not stored yet (tests/golden/make_oracle_runs.py %s)" % case)
+    ref = np.load(path, allow_pickle=False)
     wl = WORKLOADS[case]()
     steps, t0 = int(ref["steps"]), float(ref["t0"])
     assert abs(float(ref["dt"]) - wl.dt) < 1e-15
