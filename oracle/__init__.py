@@ -25,7 +25,7 @@ _LIB = os.path.join(_HERE, "libsl_oracle.so")
 
 OK, EINVAL, ESEARCH, ENEWTON = 0, -1, -4, -5
 RK4, RK3_WILLIAMSON = 0, 1
-VEL_UNIFORM, VEL_SOLID_BODY, VEL_SWIRL2D, VEL_DEFORM3D, VEL_FOURIER, VEL_GRIDDED = range(6)
+VEL_UNIFORM, VEL_SOLID_BODY, VEL_SWIRL2D, VEL_DEFORM3D, VEL_FOURIER, VEL_GRIDDED, VEL_CARRIED = range(7)
 
 
 def build(force: bool = True) -> str:

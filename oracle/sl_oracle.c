@@ -53,7 +53,8 @@ enum {
   ORC_VEL_SWIRL2D = 2,
   ORC_VEL_DEFORM3D = 3,
   ORC_VEL_FOURIER = 4,
-  ORC_VEL_GRIDDED = 5
+  ORC_VEL_GRIDDED = 5,
+  ORC_VEL_CARRIED = 6
 };
 
 /* Problem description, mirrored field by field by the ctypes binding. */
@@ -75,7 +76,8 @@ typedef struct {
   int walk_max;
   double eps_inside;    /* slack on the unit cube when accepting an element */
   int scan_radius;      /* half-width of the fallback scan box */
-  const double *ugrid[3]; /* GRIDDED: velocity components on the mesh nodes */
+  const double *ugrid[3]; /* GRIDDED: velocity components on the mesh nodes;
+                           * CARRIED: set internally to the fields at reset */
 } orc_problem;
 
 typedef struct {
@@ -148,7 +150,12 @@ static int64_t orc_wrap(int64_t i, int64_t n) {
  *               3-D: A = sum a/|k|^2 sin(theta),     u = curl A
  *               all scaled by p0.
  *   GRIDDED     samples of u on the mesh nodes (ugrid), interpolated with
- *               the Z-spline of order p0                                     */
+ *               the Z-spline of order p0
+ *   CARRIED     u is transported with the fields (fields 0..dim-1 are its
+ *               components) and has no right-hand side (Burgers' equation
+ *               Du/Dt = 0): each lattice node keeps the velocity it had at
+ *               the last reset, so it moves on a straight line; see
+ *               orc_trajectory.                                              */
 void orc_velocity(const orc_problem *P, const double *x, double t, double *u) {
   const double pi = M_PI;
   u[0] = u[1] = u[2] = 0.0;
@@ -247,6 +254,14 @@ void orc_trajectory(const orc_problem *P, const int64_t *node, double t,
   for (int a = 0; a < d; ++a) {
     h[a] = P->len[a] / (double)P->n[a];
     x[a] = ((double)node[a] + disp[a]) * h[a];
+  }
+  if (P->vel_kind == ORC_VEL_CARRIED) {
+    /* Du/Dt = 0: the node's own velocity (its field values at the reset,
+     * held in ugrid) is constant along its path; every integrator is exact. */
+    int64_t lin = 0;
+    for (int a = d - 1; a >= 0; --a) lin = lin * P->n[a] + node[a];
+    for (int a = 0; a < d; ++a) disp[a] += dt * P->ugrid[a][lin] / h[a];
+    return;
   }
   if (P->integrator == ORC_RK4) {
     orc_velocity(P, x, t, k1);
@@ -675,6 +690,7 @@ static int check_problem(const orc_problem *P) {
   if (P->order_max < 0 || P->order_max > 2) return ORC_EINVAL;
   for (int a = 0; a < P->dim; ++a)
     if (P->n[a] < 2 * P->order_max + 2 || !(P->len[a] > 0.0)) return ORC_EINVAL;
+  if (P->vel_kind == ORC_VEL_CARRIED && P->nfields < P->dim) return ORC_EINVAL;
   return ORC_OK;
 }
 
@@ -748,7 +764,11 @@ int orc_step_sampled(const orc_problem *P, double t, double dt, int ksteps,
     orc_stats st;
     memset(&st, 0, sizeof(st));
     int err = ORC_OK;
-    traj_ctx tc = {P, t, dt, ksteps};
+    /* A carried velocity is the fields themselves. */
+    orc_problem Q = *P;
+    if (P->vel_kind == ORC_VEL_CARRIED)
+      for (int a = 0; a < P->dim; ++a) Q.ugrid[a] = fin[a];
+    traj_ctx tc = {&Q, t, dt, ksteps};
     flagfly_ctx fc = {P, fin};
 #pragma omp for schedule(dynamic, 16)
     for (int64_t s = 0; s < count; ++s) {
@@ -797,9 +817,13 @@ int orc_run(const orc_problem *P, double t0, double dt, int nsteps, int kevery,
   orc_stats tot;
   memset(&tot, 0, sizeof(tot));
   int rc = ORC_OK;
+  /* A carried velocity is the fields at each reset. */
+  orc_problem Q = *P;
+  if (P->vel_kind == ORC_VEL_CARRIED)
+    for (int a = 0; a < P->dim; ++a) Q.ugrid[a] = fields[a];
   for (int s = 0; s < nsteps && rc == ORC_OK; s += kevery) {
     memset(disp, 0, sizeof(double) * (size_t)(N * P->dim));
-    for (int k = 0; k < kevery; ++k) orc_trajectories(P, t0 + (s + k) * dt, dt, disp);
+    for (int k = 0; k < kevery; ++k) orc_trajectories(&Q, t0 + (s + k) * dt, dt, disp);
     orc_stats st;
     rc = orc_reconstruct(P, disp, (const double *const *)fields, outp, &st, NULL);
     for (int f = 0; f < nf; ++f) memcpy(fields[f], outp[f], sizeof(double) * (size_t)N);

@@ -621,3 +621,68 @@ def test_sampled_velocity_matches_the_analytic_family(orc, name):
         want = orc.velocity(prob, x, t)
         got = [u[a][tuple(idx[::-1])] for a in range(wl.dim)]
         assert np.allclose(got, want, rtol=1e-12, atol=1e-12), (idx, got, want)
+
+
+# --------------------------------------------------------------------------
+# Carried velocity: Burgers' equation Du/Dt = 0 (Sec. 3, Burgers): the
+# velocity is one of the transported fields and each material point keeps it.
+
+def test_carried_velocity_trajectories_are_straight(orc):
+    shape = (12, 16)
+    g = np.random.default_rng(4)
+    ux, uy = g.normal(size=shape), g.normal(size=shape)
+    prob = orc.Problem(shape, 2, vel_kind=orc.VEL_CARRIED, ugrid=[ux, uy])
+    d = orc.trajectories(prob, 0.0, 0.01)
+    assert np.array_equal(d[0], 0.01 * ux / (1.0 / 16)) and np.array_equal(d[1], 0.01 * uy / (1.0 / 12))
+    # a second step of the same period continues on the same line
+    d2 = orc.trajectories(prob, 0.01, 0.01, d)
+    assert np.allclose(d2, 2 * d, rtol=0, atol=1e-13)
+
+
+def _burgers_1d_exact(u0, x, t):
+    # u = u0(xi) with xi + u0(xi) t = x (characteristics, before breaking)
+    xi = x - u0(x) * t
+    for _ in range(60):
+        f = xi + u0(xi) * t - x
+        fp = 1.0 + t * 2 * np.pi * 0.1 * np.cos(2 * np.pi * xi)
+        xi = xi - f / fp
+    return u0(xi)
+
+
+def test_burgers_smooth_solution_converges(orc):
+    # Before the characteristics cross, the exact solution follows from the
+    # characteristics; the FSL solution converges to it.  The lattice is
+    # compressed non-uniformly, and the element map is multilinear per cell
+    # (Z0, as throughout the paper), so the reference coordinates carry an
+    # O(h^2) error: second order overall (ratios 4.6 and 4.0 here).
+    u0 = lambda x: 0.2 + 0.1 * np.sin(2 * np.pi * x)  # noqa: E731  breaks at t = 1.59
+    t_end = 0.5
+    errs = []
+    for n in (32, 64, 128):
+        shape = (6, n)
+        x = np.arange(n) / n
+        ux = np.tile(u0(x), (6, 1))
+        uy = np.zeros(shape)
+        dt = 0.5 / n
+        steps = int(round(t_end / dt))
+        prob = orc.Problem(shape, 2, vel_kind=orc.VEL_CARRIED, order_max=2, limiter=False)
+        rc, fs, _ = orc.run(prob, 0.0, dt, steps, [ux, uy])
+        assert rc == 0
+        exact = _burgers_1d_exact(u0, x, steps * dt)
+        errs.append(np.abs(fs[0][0] - exact).max())
+        assert np.abs(fs[1]).max() == 0.0  # the y component stays zero
+    assert errs[0] / errs[1] > 3.5 and errs[1] / errs[2] > 3.5, errs
+
+
+def test_burgers_shock_stays_within_initial_bounds(orc):
+    # A compressive step (fast behind slow) steepens into a shock; with the
+    # jump criterion the values stay within the initial range (no new
+    # extrema, as the paper reports for its shock test).
+    n = 128
+    x = np.arange(n) / n
+    u0 = np.where((x > 0.25) & (x < 0.5), 0.6, 0.2) + 0.05 * np.sin(2 * np.pi * x)
+    shape = (6, n)
+    prob = orc.Problem(shape, 2, vel_kind=orc.VEL_CARRIED, order_max=2, limiter=True)
+    rc, fs, st = orc.run(prob, 0.0, 0.4 / n, 60, [np.tile(u0, (6, 1)), np.zeros(shape)])
+    assert rc == 0 and st["search_fail"] == 0
+    assert fs[0].max() <= u0.max() + 1e-12 and fs[0].min() >= u0.min() - 1e-12
