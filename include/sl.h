@@ -97,14 +97,21 @@ enum { SL_RK4 = 0, SL_RK3_WILLIAMSON = 1 };
  *                      2 (eq. "multiZ" applied to the samples; periodic).  The
  *                      paper lets the velocity be given or carried with the
  *                      fields (Sec. 2); the samples are held fixed within a
- *                      step (all stages of a step use them).                  */
+ *                      step (all stages of a step use them).
+ *   SL_VEL_CARRIED     u is transported with the fields: fields 0..dim-1 hold
+ *                      its components.  With no right-hand side (Burgers'
+ *                      equation Du/Dt = 0, Sec. 3) each lattice node keeps the
+ *                      velocity it had at the last reset and moves on a
+ *                      straight line.  Runs through sl_advance (which holds
+ *                      the fields); needs nfields >= dim.                     */
 enum {
   SL_VEL_UNIFORM = 0,
   SL_VEL_SOLID_BODY = 1,
   SL_VEL_SWIRL2D = 2,
   SL_VEL_DEFORM3D = 3,
   SL_VEL_FOURIER = 4,
-  SL_VEL_GRIDDED = 5
+  SL_VEL_GRIDDED = 5,
+  SL_VEL_CARRIED = 6
 };
 
 typedef struct sl_velocity {
@@ -175,7 +182,8 @@ int sl_set_velocity_field(sl_grid *grid, const double *const *components);
 /* Integrate the lattice trajectories over [t, t+dt] (Sec. 2).  The first step
  * after a reset starts every lattice node on its mesh node; later steps
  * continue from the stored displacement.  Asynchronous on `stream`.
- * Errors: SL_EINVAL, SL_ESTATE (gridded velocity without samples), SL_EHIP. */
+ * Errors: SL_EINVAL (also for a carried velocity, which needs the fields:
+ * use sl_advance), SL_ESTATE (gridded velocity without samples), SL_EHIP. */
 int sl_step(sl_grid *grid, void *workspace, double t, double dt, void *stream);
 
 /* Reconstruct all fields on the mesh from the moved lattice and reset the
@@ -274,7 +282,7 @@ int sl_server_destroy(sl_server *server);
  * value precision; the copy is queued on the server's stream, so the sources
  * must stay valid until that stream reaches it) into the arena and schedule
  * nsteps steps of dt from t0.  *id identifies it.
- * Errors: SL_EINVAL (bad descriptor, 3-D grid, gridded velocity,
+ * Errors: SL_EINVAL (bad descriptor, 3-D grid, gridded or carried velocity,
  * reconstruct_every != 1),
  * SL_EBUSY (no room), SL_EHIP. */
 int sl_server_admit(sl_server *server, const sl_grid_desc *desc,

@@ -141,7 +141,8 @@ int check_desc(const sl_grid_desc* d) {
   // Launch-grid limits of the y and z grid dimensions.
   if (d->n[1] > 4 * 65535 || (d->dim == 3 && d->n[2] > 65535)) return SL_EINVAL;
   const sl_velocity& v = d->vel;
-  if (v.kind < SL_VEL_UNIFORM || v.kind > SL_VEL_GRIDDED) return SL_EINVAL;
+  if (v.kind < SL_VEL_UNIFORM || v.kind > SL_VEL_CARRIED) return SL_EINVAL;
+  if (v.kind == SL_VEL_CARRIED && d->nfields < d->dim) return SL_EINVAL;
   if (v.kind == SL_VEL_GRIDDED && !(v.p[0] == 0.0 || v.p[0] == 1.0 || v.p[0] == 2.0))
     return SL_EINVAL;
   if (v.kind == SL_VEL_SWIRL2D && (d->dim != 2 || !(v.p[0] != 0.0))) return SL_EINVAL;
@@ -174,6 +175,21 @@ int hip_status(hipError_t e) {
 void clear_stale_error() { (void)hipGetLastError(); }
 
 using sl::launch;
+
+// Carried velocity: straight-line displacement from the fields `fp.in`.
+template <int D>
+hipError_t launch_carried(sl_grid* gr, const sl::FieldPtrs& fp, double* disp, double dt,
+                          int accumulate, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  const dim3 blocks((unsigned)((gr->g.n[0] + sl::kTrajBX - 1) / sl::kTrajBX),
+                    (unsigned)((gr->g.n[1] + sl::kTrajBY - 1) / sl::kTrajBY),
+                    (unsigned)gr->g.n[2]);
+  const dim3 threads(sl::kTrajBX, sl::kTrajBY);
+  if (gr->desc.value_prec == SL_FP32)
+    return launch(sl::carried_traj_kernel<D, float>, blocks, threads, 0, s, e0, e1, gr->g, fp,
+                  disp, dt, accumulate);
+  return launch(sl::carried_traj_kernel<D, double>, blocks, threads, 0, s, e0, e1, gr->g, fp,
+                disp, dt, accumulate);
+}
 
 // Time factors of the stages of a step over [t, t + dt].
 sl::StageTimes stage_times(const sl_grid* gr, double t, double dt) {
@@ -464,6 +480,7 @@ int sl_set_velocity_field(sl_grid* gr, const double* const* components) {
 
 int sl_step(sl_grid* gr, void* workspace, double t, double dt, void* stream) {
   if (!gr || !workspace || !isfinite(t) || !isfinite(dt)) return SL_EINVAL;
+  if (gr->v.kind == SL_VEL_CARRIED) return SL_EINVAL;  // needs the fields: sl_advance
   if (gr->v.kind == SL_VEL_GRIDDED && !gr->v.ug[0]) return SL_ESTATE;
   if (((uintptr_t)workspace) % kAlign) return SL_EINVAL;
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -614,10 +631,15 @@ int sl_advance(sl_grid* gr, void* workspace, void* const* fields_a, void* const*
     double* dbuf[2] = {reinterpret_cast<double*>(ws + gr->off_disp),
                        reinterpret_cast<double*>(ws + gr->off_disp2)};
     clear_stale_error();
+    const bool carried = gr->v.kind == SL_VEL_CARRIED;
     const ProfSlot ps = prof_begin(gr, 0);
-    hipError_t e = gr->desc.dim == 2
-                       ? launch_traj<2>(gr, dbuf[0], t0, dt, 0, s, ps.start, ps.stop)
-                       : launch_traj<3>(gr, dbuf[0], t0, dt, 0, s, ps.start, ps.stop);
+    hipError_t e;
+    if (carried)
+      e = gr->desc.dim == 2 ? launch_carried<2>(gr, ab, dbuf[0], dt, 0, s, ps.start, ps.stop)
+                            : launch_carried<3>(gr, ab, dbuf[0], dt, 0, s, ps.start, ps.stop);
+    else
+      e = gr->desc.dim == 2 ? launch_traj<2>(gr, dbuf[0], t0, dt, 0, s, ps.start, ps.stop)
+                            : launch_traj<3>(gr, dbuf[0], t0, dt, 0, s, ps.start, ps.stop);
     prof_end(gr, ps, 0, e);
     for (int k = 0; k < nsteps && e == hipSuccess; ++k) {
       gr->steps_launched++;
@@ -627,6 +649,7 @@ int sl_advance(sl_grid* gr, void* workspace, void* const* fields_a, void* const*
         nt.st = stage_times(gr, t0 + (double)(k + 1) * dt, dt);
         nt.dt = dt;
         nt.integrator = gr->desc.integrator;
+        nt.carried = carried ? 1 : 0;
       }
       e = reconstruct_launches(gr, ws, (k & 1) ? ba : ab, dbuf[k & 1], nt, s);
       if (e == hipSuccess) gr->reconstructs_launched++;
@@ -639,6 +662,26 @@ int sl_advance(sl_grid* gr, void* workspace, void* const* fields_a, void* const*
   int in_b = 0;
   for (int s = 0; s < nsteps; s += K) {
     for (int k = 0; k < K; ++k) {
+      if (gr->v.kind == SL_VEL_CARRIED) {
+        // Straight lines with the velocity of the last reset (the fields `cur`).
+        sl::FieldPtrs fp;
+        int rc = field_ptrs(gr, (const void* const*)cur, nxt, &fp);
+        if (rc != SL_OK) return rc;
+        if (((uintptr_t)workspace) % kAlign) return SL_EINVAL;
+        double* disp = reinterpret_cast<double*>(static_cast<char*>(workspace) + gr->off_disp);
+        clear_stale_error();
+        const ProfSlot ps = prof_begin(gr, 0);
+        const hipStream_t hs = static_cast<hipStream_t>(stream);
+        const hipError_t e =
+            gr->desc.dim == 2 ? launch_carried<2>(gr, fp, disp, dt, k > 0, hs, ps.start, ps.stop)
+                              : launch_carried<3>(gr, fp, disp, dt, k > 0, hs, ps.start, ps.stop);
+        prof_end(gr, ps, 0, e);
+        rc = hip_status(e);
+        if (rc != SL_OK) return rc;
+        gr->steps_since_reset++;
+        gr->steps_launched++;
+        continue;
+      }
       const int rc = sl_step(gr, workspace, t0 + (double)(s + k) * dt, dt, stream);
       if (rc != SL_OK) return rc;
     }

@@ -59,8 +59,8 @@ struct Tile2D {
 // spills (the LDS boxes allow more).
 template <typename T, int NF>
 constexpr int tile2d_waves() {
-  if (sizeof(T) == 4) return (NF >= 2 && NF <= 4) ? 6 : (NF <= 5 ? 5 : 4);
-  return (NF == 1 || NF == 3 || NF == 4) ? 4 : 3;
+  if (sizeof(T) == 4) return (NF >= 2 && NF <= 4) ? 6 : (NF == 1 ? 5 : 4);
+  return (NF == 1 || NF == 3) ? 4 : 3;
 }
 
 __device__ __forceinline__ int xcd_tile(int b, int nblocks) {
@@ -230,7 +230,7 @@ __device__ __forceinline__ void recon2d_tile(const GridArgs& g, const FieldPtrs&
   // The next step's trajectories of the tile's own nodes (NextTraj); they
   // touch nothing the reconstruction below reads.
   if constexpr (std::is_same<VelT, VelArgs>::value) {
-    if (nt.disp) {
+    if (nt.disp && !nt.carried) {
 #pragma unroll 1
       for (int k = 0; k < C::NPT; ++k) {
         const int idx[2] = {tx0 + lx, ty0 + ly0 + ROWS * k};
@@ -413,6 +413,10 @@ __device__ __forceinline__ void recon2d_tile(const GridArgs& g, const FieldPtrs&
       nfail += loc == LOC_NEWTON_FAIL;
 #pragma unroll
       for (int f = 0; f < nf; ++f) static_cast<T*>(fp.out[f])[lin] = T(NAN);
+      if (nt.carried && nt.disp) {
+        nt.disp[lin] = NAN;
+        nt.disp[(size_t)g.ntot + lin] = NAN;
+      }
       continue;
     }
     const int sx = r[0] - 2 - bx0, sy = r[1] - 2 - by0;  // stencil origin in box
@@ -465,6 +469,9 @@ __device__ __forceinline__ void recon2d_tile(const GridArgs& g, const FieldPtrs&
       }
       bad += !isfinite(v);
       static_cast<T*>(fp.out[f])[lin] = v;
+      // Carried velocity: fields 0 and 1 give the next step's displacement.
+      if (f < 2 && nt.carried && nt.disp)
+        nt.disp[(size_t)f * g.ntot + lin] = nt.dt * (double)v / g.h[f];
     };
     if (__ballot(low) == 0ull) {
       c0 += g.order_max == 0 ? nf : 0;

@@ -191,7 +191,7 @@ __global__ __launch_bounds__(kTileThreads, (Box3D<T, NF>::WAVES)) void recon3d_k
 
   // The next step's trajectory of this work-item's lattice node (NextTraj);
   // it touches nothing the reconstruction below reads.
-  if (nt.disp && act) traj_any<3>(g, v, nt.disp, nt.st, nt.dt, nt.integrator, tgt);
+  if (nt.disp && !nt.carried && act) traj_any<3>(g, v, nt.disp, nt.st, nt.dt, nt.integrator, tgt);
 
   // 1. Own displacement and start cell.
   double d0[3] = {0.0, 0.0, 0.0};
@@ -253,7 +253,10 @@ __global__ __launch_bounds__(kTileThreads, (Box3D<T, NF>::WAVES)) void recon3d_k
       nfail = loc == LOC_NEWTON_FAIL;
 #pragma unroll
       for (int f = 0; f < nf; ++f) static_cast<T*>(fp.out[f])[lin] = T(NAN);
+      if (nt.carried && nt.disp)
+        for (int a = 0; a < 3; ++a) nt.disp[(size_t)a * g.ntot + lin] = NAN;
     } else {
+
       int w0[3], lb[3];
       bool interior = true, inbox = X::STAGE;
       constexpr int B[3] = {X::BX, X::BY, X::BZ};
@@ -316,6 +319,12 @@ __global__ __launch_bounds__(kTileThreads, (Box3D<T, NF>::WAVES)) void recon3d_k
         }
         bad += !isfinite(v);
         static_cast<T*>(fp.out[f])[lin] = v;
+        // Carried velocity: fields 0..2 give the next step's displacement
+        // (the spacing by selects: the field index may be a loop variable).
+        if (f < 3 && nt.carried && nt.disp) {
+          const double hf = f == 0 ? g.h[0] : (f == 1 ? g.h[1] : g.h[2]);
+          nt.disp[(size_t)f * g.ntot + lin] = nt.dt * (double)v / hf;
+        }
       };
       const unsigned fmask = nf >= 32 ? 0xffffffffu : ((1u << nf) - 1u);
       const bool low = lim && (((or6 | or4) & fmask) != 0u);

@@ -356,7 +356,9 @@ int sl_server_admit(sl_server* s, const sl_grid_desc* desc, const void* const* f
   if (!s || !desc || !fields_in || !id || nsteps < 1 || !isfinite(t0) || !isfinite(dt))
     return SL_EINVAL;
   if (desc->dim != 2 || desc->reconstruct_every != 1) return SL_EINVAL;
-  if (desc->vel.kind == SL_VEL_DEFORM3D || desc->vel.kind == SL_VEL_GRIDDED) return SL_EINVAL;
+  if (desc->vel.kind == SL_VEL_DEFORM3D || desc->vel.kind == SL_VEL_GRIDDED ||
+      desc->vel.kind == SL_VEL_CARRIED)
+    return SL_EINVAL;
   sl_grid* gr = nullptr;
   int rc = sl_create_grid(desc, &gr);
   if (rc != SL_OK) return rc;

@@ -131,15 +131,40 @@ __device__ __forceinline__ void traj_any(const GridArgs& g, const VelArgs& v,
 // own tile's lattice nodes: they start on the mesh (the lattice is reset each
 // step) and so do not depend on the fields being reconstructed.  `disp` null:
 // nothing to do.
+// carried: the velocity is transported with the fields (fields 0..dim-1),
+// so the next step's displacement of a node is dt times the velocity the
+// reconstruction has just produced there, in cells.
 struct NextTraj {
   double* disp;
   StageTimes st;
   double dt;
   int integrator;
+  int carried;
 };
 
 // Stand-in for the velocity argument of kernels that never integrate.
 struct NoVel {};
+
+// Carried velocity (fields 0..D-1 hold it; no right-hand side): each lattice
+// node moves on a straight line with its own velocity, for every integrator.
+// Same (64 x 4) grid as traj_kernel.
+template <int D, typename T>
+__global__ __launch_bounds__(kBlock) void carried_traj_kernel(GridArgs g, FieldPtrs fp,
+                                                              double* __restrict__ disp,
+                                                              double dt, int accumulate) {
+  int idx[D];
+  idx[0] = blockIdx.x * kTrajBX + threadIdx.x;
+  idx[1] = blockIdx.y * kTrajBY + threadIdx.y;
+  if constexpr (D == 3) idx[2] = blockIdx.z;
+  if (idx[0] >= g.n[0] || idx[1] >= g.n[1]) return;
+  const int lin = flatten<D>(g, idx);
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    const double u = (double)static_cast<const T*>(fp.in[a])[lin];
+    const double d0 = accumulate ? disp[(size_t)a * g.ntot + lin] : 0.0;
+    disp[(size_t)a * g.ntot + lin] = d0 + dt * u / g.h[a];
+  }
+}
 
 template <int D, int VK>
 __global__ __launch_bounds__(kBlock) void traj_kernel(GridArgs g, VelArgs v,

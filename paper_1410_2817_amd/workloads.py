@@ -19,7 +19,7 @@ from typing import Sequence
 import numpy as np
 
 # Velocity kinds, numbered as in the C interface.
-VEL_UNIFORM, VEL_SOLID_BODY, VEL_SWIRL2D, VEL_DEFORM3D, VEL_FOURIER, VEL_GRIDDED = range(6)
+VEL_UNIFORM, VEL_SOLID_BODY, VEL_SWIRL2D, VEL_DEFORM3D, VEL_FOURIER, VEL_GRIDDED, VEL_CARRIED = range(7)
 
 
 def rng(seed: int) -> np.random.Generator:
@@ -238,6 +238,25 @@ def gridded(wl: "Workload", order: int = 2, t: float = 0.0) -> "Workload":
     return dataclasses.replace(wl, name=wl.name + "_gridded%d" % order,
                                velocity=Velocity(VEL_GRIDDED, [float(order)]),
                                ugrid=sample_velocity(wl, t))
+
+
+def burgers(n: int = 256, dim: int = 2, t_end: float = 0.3, cfl: float = 0.5,
+            value_prec: str = "f64") -> Workload:
+    """Burgers' equation Du/Dt = 0 with the radial initial velocity of the
+    paper's shock test (Sec. 3): u = exp(-150 (r - 0.2)^2) (x - c) / r for
+    r = |x - c| > 0.001 (c the box centre), 0 otherwise; the velocity is
+    carried by the fields (fields 0..dim-1), limiter on, Z2.  Max speed 1, so
+    dt = cfl h; the run covers t_end."""
+    shape = (n,) * dim
+    X = _xyz(shape)
+    rel = [X[a] - 0.5 for a in range(dim)]
+    r = np.sqrt(sum(q * q for q in rel))
+    amp = np.where(r > 0.001, np.exp(-150.0 * (r - 0.2) ** 2) / np.maximum(r, 1e-300), 0.0)
+    fs = [np.broadcast_to(amp * rel[a], shape).astype(np.float64).copy() for a in range(dim)]
+    dt = cfl / n
+    return Workload("burgers%dd_%d_%s" % (dim, n, value_prec), shape, (1.0,) * dim, fs,
+                    Velocity(VEL_CARRIED), dt=dt, nsteps=int(round(t_end / dt)),
+                    order_max=2, limiter=True, value_prec=value_prec)
 
 
 def solid_body_gaussian(n: int = 64, steps: int = 100, order_max: int = 2) -> Workload:

@@ -151,3 +151,16 @@ def test_gridded_velocity_state_and_validation(lib):
                                       C.cast(C.c_void_p(8192), C.POINTER(C.c_double)))
     assert lib.sl_set_velocity_field(h, fake) == B.SL_EINVAL
     assert lib.sl_destroy_grid(h) == B.SL_OK
+
+
+def test_carried_velocity_validation(lib):
+    """A carried velocity needs the velocity components among the fields and
+    runs through sl_advance (sl_step has no fields)."""
+    d, _ = _desc(shape=(16, 16), nfields=1, vel_kind=6)
+    rc, h = _create(d)
+    assert rc == B.SL_EINVAL
+    d, _ = _desc(shape=(16, 16), nfields=2, vel_kind=6)
+    rc, h = _create(d)
+    assert rc == B.SL_OK
+    assert lib.sl_step(h, C.c_void_p(1 << 20), 0.0, 0.1, None) == B.SL_EINVAL
+    assert lib.sl_destroy_grid(h) == B.SL_OK
