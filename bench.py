@@ -391,6 +391,23 @@ def other_configs():
         del out
     # Split form against plain FP64 after the same 60 steps.
     res["deform3d_512_f32"]["l1_rel_vs_f64_plain"] = _l1(keep["f32"], keep["f64"])
+
+    # Burgers' equation (velocity carried by the fields), the paper's radial
+    # shock test at 512^2 up to t = 0.3, plus its first 20 steps against the
+    # oracle.
+    wl = W.burgers(512)
+    out, el, prof, st = run_gpu(wl, wl.nsteps)
+    res["burgers2d_512_f64"] = {"node_updates_per_s": wl.nodes * wl.nsteps / el,
+                                "ms_per_step": el * 1e3 / wl.nsteps, "steps": wl.nsteps,
+                                "t_end": wl.nsteps * wl.dt, "search_fail": st["search_fail"],
+                                "order_hist": st["order_hist"],
+                                "max_speed": float(max(np.abs(f.double().cpu().numpy()).max()
+                                                       for f in out))}
+    out20, _, _, _ = run_gpu(wl, 20, profile=0, warmup=0)
+    rc, ofs, _ = oracle.run(_oracle_problem(oracle, wl), 0.0, wl.dt, 20,
+                            [np.asarray(f, np.float64) for f in wl.fields])
+    res["burgers2d_512_f64"]["l1_rel_vs_oracle_20_steps"] = [
+        _l1(g.double().cpu().numpy(), o) for g, o in zip(out20, ofs)]
     return res
 
 
