@@ -26,6 +26,7 @@ _LIB = os.path.join(_HERE, "libsl_oracle.so")
 OK, EINVAL, ESEARCH, ENEWTON = 0, -1, -4, -5
 RK4, RK3_WILLIAMSON = 0, 1
 VEL_UNIFORM, VEL_SOLID_BODY, VEL_SWIRL2D, VEL_DEFORM3D, VEL_FOURIER, VEL_GRIDDED, VEL_CARRIED = range(7)
+SRC_NONE, SRC_SHALLOW_WATER = 0, 1
 
 
 def build(force: bool = True) -> str:
@@ -50,6 +51,7 @@ class _Problem(C.Structure):
         ("walk_max", C.c_int), ("eps_inside", C.c_double),
         ("scan_radius", C.c_int),
         ("ugrid", C.POINTER(C.c_double) * 3),
+        ("src_kind", C.c_int), ("sp", C.c_double * 4),
     ]
 
 
@@ -103,6 +105,13 @@ def _load():
         lib.orc_run.argtypes = [P, C.c_double, C.c_double, C.c_int, C.c_int,
                                 C.POINTER(dp), C.POINTER(_Stats)]
         lib.orc_run.restype = C.c_int
+        lib.orc_fd_weights.argtypes = [C.c_int, C.c_int, dp]
+        lib.orc_fd_weights.restype = C.c_int
+        lib.orc_source_mesh.argtypes = [P, C.POINTER(dp), C.POINTER(dp)]
+        lib.orc_source_mesh.restype = C.c_int
+        lib.orc_run_source.argtypes = [P, C.c_double, C.c_double, C.c_int,
+                                       C.POINTER(dp), C.POINTER(_Stats)]
+        lib.orc_run_source.restype = C.c_int
         lib.orc_threads.argtypes = []
         lib.orc_threads.restype = C.c_int
         _lib = lib
@@ -136,6 +145,10 @@ class Problem:
     # VEL_GRIDDED: velocity components on the mesh nodes, each of `shape`
     # (array order), listed x-first; vp[0] is the interpolation order.
     ugrid: Sequence[np.ndarray] | None = None
+    # Source term (orc_source_mesh): SRC_SHALLOW_WATER with sp = (fc, beta,
+    # y0, nu); fields are u1, u2, h (x-first velocity), then passive ones.
+    src_kind: int = SRC_NONE
+    sp: Sequence[float] = field(default_factory=lambda: [0.0] * 4)
 
     @property
     def dim(self) -> int:
@@ -171,6 +184,10 @@ class Problem:
         p.walk_max = self.walk_max
         p.eps_inside = self.eps_inside
         p.scan_radius = self.scan_radius
+        p.src_kind = int(self.src_kind)
+        spv = list(self.sp) + [0.0] * (4 - len(self.sp))
+        for i in range(4):
+            p.sp[i] = float(spv[i])
         if self.ugrid is not None:
             keep = [np.ascontiguousarray(u, dtype=np.float64) for u in self.ugrid]
             self._ugrid_keep = keep
@@ -331,6 +348,37 @@ def run(prob: Problem, t0: float, dt: float, nsteps: int, fields, kevery: int = 
     p = prob._c()
     rc = _load().orc_run(C.byref(p), float(t0), float(dt), int(nsteps), int(kevery),
                          _fields_ptrs(fs), C.byref(st))
+    return rc, fs, st.as_dict()
+
+
+def fd_weights(half_width: int, deriv: int) -> np.ndarray:
+    """Centred finite-difference weights of the given derivative on a unit
+    grid, offsets -half_width..half_width."""
+    c = np.zeros(2 * half_width + 1)
+    rc = _load().orc_fd_weights(int(half_width), int(deriv), _dp(c))
+    if rc != OK:
+        raise ValueError("orc_fd_weights failed")
+    return c
+
+
+def source_mesh(prob: Problem, fields):
+    """Right-hand side of the shallow-water system on the mesh for the given
+    fields (u1, u2, h, ...); returns (status, [S_u1, S_u2, S_h])."""
+    fs = _as_fields(prob, fields)
+    outs = [np.empty(prob.shape) for _ in range(3)]
+    p = prob._c()
+    rc = _load().orc_source_mesh(C.byref(p), _fields_ptrs(fs), _fields_ptrs(outs))
+    return rc, outs
+
+
+def run_source(prob: Problem, t0: float, dt: float, nsteps: int, fields):
+    """nsteps steps of the source-term scheme (orc_run_source); returns
+    (status, fields, accumulated stats)."""
+    fs = [f.copy() for f in _as_fields(prob, fields)]
+    st = _Stats()
+    p = prob._c()
+    rc = _load().orc_run_source(C.byref(p), float(t0), float(dt), int(nsteps),
+                                _fields_ptrs(fs), C.byref(st))
     return rc, fs, st.as_dict()
 
 

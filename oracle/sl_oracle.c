@@ -18,6 +18,9 @@
  *      flagged point enters the stencil (Sec. 2.3) and evaluate the tensor
  *      product Z-spline sum of eq. "multiZ" with the cardinal basis of the
  *      Appendix.
+ * With a source term (orc_run_source) the lattice nodes also carry their
+ * values, integrated with Williamson's low-storage RK3 against a right-hand
+ * side taken by finite differences on the mesh from the stage fields.
  *
  * Conventions (readings of points the paper leaves open):
  *   - node-centred periodic grid, x_i = i*h, h = L/N, values stored x fastest;
@@ -47,6 +50,7 @@
 
 enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_ESEARCH = -4, ORC_ENEWTON = -5 };
 enum { ORC_RK4 = 0, ORC_RK3_WILLIAMSON = 1 };
+enum { ORC_SRC_NONE = 0, ORC_SRC_SHALLOW_WATER = 1 };
 enum {
   ORC_VEL_UNIFORM = 0,
   ORC_VEL_SOLID_BODY = 1,
@@ -78,6 +82,8 @@ typedef struct {
   int scan_radius;      /* half-width of the fallback scan box */
   const double *ugrid[3]; /* GRIDDED: velocity components on the mesh nodes;
                            * CARRIED: set internally to the fields at reset */
+  int src_kind;         /* ORC_SRC_*: right-hand side S_i of eq. "momento" */
+  double sp[4];         /* SHALLOW_WATER: fc, beta, y0, nu (see orc_source_mesh) */
 } orc_problem;
 
 typedef struct {
@@ -134,6 +140,35 @@ void orc_weights(int m, double t, double *w) {
 static int64_t orc_wrap(int64_t i, int64_t n) {
   int64_t r = i % n;
   return r < 0 ? r + n : r;
+}
+
+/* Tensor-product cardinal Z-spline interpolation of order m (eq. "multiZ") of
+ * ng mesh fields g[0..ng-1] at the physical point x, periodic; out[c] receives
+ * the value of field c.                                                      */
+static void orc_zinterp(const orc_problem *P, int m, int ng,
+                        const double *const *g, const double *x, double *out) {
+  int64_t r[3] = {0, 0, 0};
+  double w[3][6];
+  for (int a = 0; a < 3; ++a)
+    for (int k = 0; k < 6; ++k) w[a][k] = a < P->dim ? 0.0 : 1.0;
+  for (int a = 0; a < P->dim; ++a) {
+    const double s = x[a] / (P->len[a] / (double)P->n[a]);
+    r[a] = (int64_t)floor(s);
+    orc_weights(m, s - (double)r[a], w[a]);
+  }
+  for (int c = 0; c < ng; ++c) out[c] = 0.0;
+  const int np = 2 * m + 2;
+  const int nz = P->dim == 3 ? np : 1;
+  for (int kz = 0; kz < nz; ++kz)
+    for (int ky = 0; ky < np; ++ky)
+      for (int kx = 0; kx < np; ++kx) {
+        const int64_t ix = orc_wrap(r[0] - m + kx, P->n[0]);
+        const int64_t iy = orc_wrap(r[1] - m + ky, P->n[1]);
+        const int64_t iz = P->dim == 3 ? orc_wrap(r[2] - m + kz, P->n[2]) : 0;
+        const int64_t lin = ix + P->n[0] * (iy + P->n[1] * iz);
+        const double wt = w[0][kx] * w[1][ky] * (P->dim == 3 ? w[2][kz] : 1.0);
+        for (int c = 0; c < ng; ++c) out[c] += wt * g[c][lin];
+      }
 }
 
 /* ------------------------------------------------------------------------- */
@@ -209,34 +244,12 @@ void orc_velocity(const orc_problem *P, const double *x, double t, double *u) {
       for (int a = 0; a < P->dim; ++a) u[a] *= P->vp[0];
       break;
     }
-    case ORC_VEL_GRIDDED: {
+    case ORC_VEL_GRIDDED:
       /* Velocity given on the reference mesh, interpolated at x with the
        * tensor-product cardinal Z-spline of order vp[0] (eq. "multiZ" applied
        * to the velocity samples; periodic). */
-      const int m = (int)P->vp[0];
-      int64_t r[3] = {0, 0, 0};
-      double w[3][6];
-      for (int a = 0; a < 3; ++a)
-        for (int k = 0; k < 6; ++k) w[a][k] = a < P->dim ? 0.0 : 1.0;
-      for (int a = 0; a < P->dim; ++a) {
-        const double s = x[a] / (P->len[a] / (double)P->n[a]);
-        r[a] = (int64_t)floor(s);
-        orc_weights(m, s - (double)r[a], w[a]);
-      }
-      const int np = 2 * m + 2;
-      const int nz = P->dim == 3 ? np : 1;
-      for (int kz = 0; kz < nz; ++kz)
-        for (int ky = 0; ky < np; ++ky)
-          for (int kx = 0; kx < np; ++kx) {
-            const int64_t ix = orc_wrap(r[0] - m + kx, P->n[0]);
-            const int64_t iy = orc_wrap(r[1] - m + ky, P->n[1]);
-            const int64_t iz = P->dim == 3 ? orc_wrap(r[2] - m + kz, P->n[2]) : 0;
-            const int64_t lin = ix + P->n[0] * (iy + P->n[1] * iz);
-            const double wt = w[0][kx] * w[1][ky] * (P->dim == 3 ? w[2][kz] : 1.0);
-            for (int a = 0; a < P->dim; ++a) u[a] += wt * P->ugrid[a][lin];
-          }
+      orc_zinterp(P, (int)P->vp[0], P->dim, P->ugrid, x, u);
       break;
-    }
     default:
       u[0] = u[1] = u[2] = NAN;
   }
@@ -794,6 +807,16 @@ int orc_step_sampled(const orc_problem *P, double t, double dt, int ksteps,
   return first_err;
 }
 
+static void accumulate_stats(orc_stats *tot, const orc_stats *st) {
+  tot->nodes += st->nodes;
+  tot->search_fail += st->search_fail;
+  tot->newton_fail += st->newton_fail;
+  for (int m = 0; m < 3; ++m) tot->order_hist[m] += st->order_hist[m];
+  tot->flagged += st->flagged;
+  tot->walk_steps += st->walk_steps;
+  tot->newton_iters += st->newton_iters;
+}
+
 /* nsteps full steps, fields updated in place.  Each cycle resets the lattice,
  * integrates its trajectories over kevery sub-steps of dt and reconstructs the
  * fields on the mesh (Sec. 2: the lattice moves for a number of steps and is
@@ -827,16 +850,223 @@ int orc_run(const orc_problem *P, double t0, double dt, int nsteps, int kevery,
     orc_stats st;
     rc = orc_reconstruct(P, disp, (const double *const *)fields, outp, &st, NULL);
     for (int f = 0; f < nf; ++f) memcpy(fields[f], outp[f], sizeof(double) * (size_t)N);
-    tot.nodes += st.nodes;
-    tot.search_fail += st.search_fail;
-    tot.newton_fail += st.newton_fail;
-    for (int m = 0; m < 3; ++m) tot.order_hist[m] += st.order_hist[m];
-    tot.flagged += st.flagged;
-    tot.walk_steps += st.walk_steps;
-    tot.newton_iters += st.newton_iters;
+    accumulate_stats(&tot, &st);
   }
   free(disp);
   free(buf);
+  if (stats) *stats = tot;
+  return rc;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Source terms (Sec. 2: the right-hand side S_i of eq. "momento" may hold
+ * spatial derivatives, taken by finite differences on the reference mesh).   */
+
+/* Centred finite-difference weights c[0..2M] (offsets -M..M) of the p-th
+ * derivative on a unit grid: the unique weights for which the rule is exact on
+ * every polynomial of degree <= 2M, i.e. sum_k c_k k^q = q! [q == p] for
+ * q = 0..2M.  Solved by Gaussian elimination with partial pivoting in long
+ * double.  These are the "Taylor series from 2m+1 points" derivatives that the
+ * cardinal Z-splines match at their knots (eq. "matchder").                   */
+int orc_fd_weights(int M, int p, double *c) {
+  if (M < 1 || M > 3 || p < 0 || p > 2 * M) return ORC_EINVAL;
+  const int n = 2 * M + 1;
+  long double A[7][8];
+  for (int q = 0; q < n; ++q) {
+    for (int j = 0; j < n; ++j) {
+      long double k = (long double)(j - M), v = 1.0L;
+      for (int e = 0; e < q; ++e) v *= k;
+      A[q][j] = v;                       /* row q: k^q over the offsets */
+    }
+    long double fact = 1.0L;
+    for (int e = 2; e <= q; ++e) fact *= (long double)e;
+    A[q][n] = q == p ? fact : 0.0L;
+  }
+  for (int col = 0; col < n; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < n; ++r)
+      if (fabsl(A[r][col]) > fabsl(A[piv][col])) piv = r;
+    if (A[piv][col] == 0.0L) return ORC_EINVAL;
+    if (piv != col)
+      for (int j = 0; j <= n; ++j) {
+        long double t = A[col][j];
+        A[col][j] = A[piv][j];
+        A[piv][j] = t;
+      }
+    for (int r = 0; r < n; ++r) {
+      if (r == col) continue;
+      long double f = A[r][col] / A[col][col];
+      for (int j = col; j <= n; ++j) A[r][j] -= f * A[col][j];
+    }
+  }
+  for (int j = 0; j < n; ++j) c[j] = (double)(A[j][n] / A[j][j]);
+  return ORC_OK;
+}
+
+/* Half-width of the finite-difference rules: the 2m+1 points of the Z-spline
+ * order in use, at least three points (Z0 matches no derivative).           */
+static int fd_half_width(const orc_problem *P) {
+  return P->order_max < 1 ? 1 : P->order_max;
+}
+
+/* Value of mesh field g at (i + di, j + dj), periodic (2-D). */
+static double at2(const orc_problem *P, const double *g, int64_t i, int64_t j,
+                  int di, int dj) {
+  return g[orc_wrap(i + di, P->n[0]) + P->n[0] * orc_wrap(j + dj, P->n[1])];
+}
+
+/* Right-hand side of the shallow-water system, eq. "nlsw", at every mesh node
+ * (2-D).  Fields: G[0] = u1, G[1] = u2 (the carried velocity), G[2] = h; any
+ * further field is passive (no source).  With f = fc + beta (y - y0) and the
+ * orthogonal velocity (-u2, u1):
+ *   S_h  = -(1 + h) div u
+ *   S_u1 = -dh/dx1 + f u2 + nu V1
+ *   S_u2 = -dh/dx2 - f u1 + nu V2
+ * where V = div[(1 + h)(grad u + grad u^T)], written out as
+ *   V_i = (1 + h)(lap u_i + d_i div u) + sum_j (d_j h)(d_j u_i + d_i u_j).
+ * Pure derivatives use the centred (2M+1)-point rules along one axis, mixed
+ * ones the product of the two first-derivative rules.  The paper's equatorial
+ * beta plane is fc = 0, beta = f0, y0 the equator.                           */
+int orc_source_mesh(const orc_problem *P, const double *const *G, double *const *S) {
+  if (P->dim != 2 || P->nfields < 3 || P->src_kind != ORC_SRC_SHALLOW_WATER)
+    return ORC_EINVAL;
+  const int M = fd_half_width(P);
+  double c1[7], c2[7];
+  if (orc_fd_weights(M, 1, c1) != ORC_OK || orc_fd_weights(M, 2, c2) != ORC_OK)
+    return ORC_EINVAL;
+  const double hx = P->len[0] / (double)P->n[0], hy = P->len[1] / (double)P->n[1];
+  const double fc = P->sp[0], beta = P->sp[1], y0 = P->sp[2], nu = P->sp[3];
+  const int64_t N = total_nodes(P);
+#pragma omp parallel for schedule(static)
+  for (int64_t lin = 0; lin < N; ++lin) {
+    const int64_t i = lin % P->n[0], j = lin / P->n[0];
+    double d1x[3] = {0, 0, 0}, d1y[3] = {0, 0, 0};
+    double d2x[3] = {0, 0, 0}, d2y[3] = {0, 0, 0}, dxy[3] = {0, 0, 0};
+    for (int c = 0; c < 3; ++c) {
+      for (int k = -M; k <= M; ++k) {
+        d1x[c] += c1[k + M] * at2(P, G[c], i, j, k, 0);
+        d1y[c] += c1[k + M] * at2(P, G[c], i, j, 0, k);
+        d2x[c] += c2[k + M] * at2(P, G[c], i, j, k, 0);
+        d2y[c] += c2[k + M] * at2(P, G[c], i, j, 0, k);
+      }
+      for (int b = -M; b <= M; ++b)
+        for (int a = -M; a <= M; ++a)
+          dxy[c] += c1[a + M] * c1[b + M] * at2(P, G[c], i, j, a, b);
+      d1x[c] /= hx;
+      d1y[c] /= hy;
+      d2x[c] /= hx * hx;
+      d2y[c] /= hy * hy;
+      dxy[c] /= hx * hy;
+    }
+    const double u = G[0][lin], v = G[1][lin], h = G[2][lin];
+    const double f = fc + beta * ((double)j * hy - y0);
+    const double div = d1x[0] + d1y[1];
+    double su = -d1x[2] + f * v;
+    double sv = -d1y[2] - f * u;
+    const double sh = -(1.0 + h) * div;
+    if (nu != 0.0) {
+      /* V_1 = (1+h)(u_xx + u_yy + u_xx + v_xy) + h_x (2 u_x) + h_y (u_y + v_x)
+       * V_2 = (1+h)(v_xx + v_yy + u_xy + v_yy) + h_x (v_x + u_y) + h_y (2 v_y) */
+      const double V1 = (1.0 + h) * (d2x[0] + d2y[0] + d2x[0] + dxy[1]) +
+                        d1x[2] * (d1x[0] + d1x[0]) + d1y[2] * (d1y[0] + d1x[1]);
+      const double V2 = (1.0 + h) * (d2x[1] + d2y[1] + dxy[0] + d2y[1]) +
+                        d1x[2] * (d1x[1] + d1y[0]) + d1y[2] * (d1y[1] + d1y[1]);
+      su += nu * V1;
+      sv += nu * V2;
+    }
+    S[0][lin] = su;
+    S[1][lin] = sv;
+    S[2][lin] = sh;
+  }
+  return ORC_OK;
+}
+
+/* nsteps steps of a system with source terms (2-D shallow water, carried
+ * velocity), lattice reset every step.  Within the step [t, t+dt] every
+ * lattice node carries its position X and its values H, integrated with the
+ * low-storage third-order Runge-Kutta of Williamson (Sec. 2):
+ *   stage s = 0, 1, 2:
+ *     G   = the stage fields on the mesh: the fields at t for s = 0, else the
+ *           reconstruction (Sec. 2.1-2.3) of the lattice values H at X;
+ *     S   = the right-hand side on the mesh from G (orc_source_mesh);
+ *     per lattice node:  u = its own velocity H[0..1],
+ *                        s_hat = S interpolated at X (Z-spline, order_max),
+ *       qX = A_s qX + dt u,      X += B_s qX,
+ *       qH = A_s qH + dt s_hat,  H += B_s qH   (fields 0..2; others passive);
+ *   then the fields at t+dt are the reconstruction of H at X (the reset).
+ * Stats accumulate over all three reconstructions of each step.             */
+int orc_run_source(const orc_problem *P, double t0, double dt, int nsteps,
+                   double *const *fields, orc_stats *stats) {
+  if (check_problem(P) != ORC_OK || P->dim != 2 || P->nfields < 3 ||
+      P->src_kind != ORC_SRC_SHALLOW_WATER || P->vel_kind != ORC_VEL_CARRIED ||
+      nsteps < 0)
+    return ORC_EINVAL;
+  static const double A[3] = {0.0, -5.0 / 9.0, -153.0 / 128.0};
+  static const double B[3] = {1.0 / 3.0, 15.0 / 16.0, 8.0 / 15.0};
+  (void)t0;  /* the shallow-water source does not depend on t explicitly */
+  const int64_t N = total_nodes(P);
+  const int nf = P->nfields;
+  double *disp = (double *)calloc((size_t)(2 * N), sizeof(double));
+  double *qx = (double *)calloc((size_t)(2 * N), sizeof(double));
+  double *H = (double *)calloc((size_t)(nf * N), sizeof(double));
+  double *qh = (double *)calloc((size_t)(3 * N), sizeof(double));
+  double *G = (double *)calloc((size_t)(nf * N), sizeof(double));
+  double *S = (double *)calloc((size_t)(3 * N), sizeof(double));
+  int rc = ORC_OK;
+  if (!disp || !qx || !H || !qh || !G || !S) rc = ORC_EINVAL;
+  double *Hp[ORC_MAX_FIELDS], *Gp[ORC_MAX_FIELDS], *Sp[3];
+  for (int f = 0; f < nf; ++f) {
+    Hp[f] = H ? H + f * N : NULL;
+    Gp[f] = G ? G + f * N : NULL;
+  }
+  for (int c = 0; c < 3; ++c) Sp[c] = S ? S + c * N : NULL;
+  const double hx[2] = {P->len[0] / (double)P->n[0], P->len[1] / (double)P->n[1]};
+  orc_stats tot;
+  memset(&tot, 0, sizeof(tot));
+  for (int step = 0; step < nsteps && rc == ORC_OK; ++step) {
+    for (int f = 0; f < nf; ++f) memcpy(Hp[f], fields[f], sizeof(double) * (size_t)N);
+    memset(disp, 0, sizeof(double) * (size_t)(2 * N));
+    memset(qx, 0, sizeof(double) * (size_t)(2 * N));
+    memset(qh, 0, sizeof(double) * (size_t)(3 * N));
+    for (int s = 0; s < 3 && rc == ORC_OK; ++s) {
+      const double *const *Gs = (const double *const *)fields;
+      if (s > 0) {
+        orc_stats st;
+        rc = orc_reconstruct(P, disp, (const double *const *)Hp, Gp, &st, NULL);
+        accumulate_stats(&tot, &st);
+        Gs = (const double *const *)Gp;
+      }
+      if (rc == ORC_OK) rc = orc_source_mesh(P, Gs, Sp);
+      if (rc != ORC_OK) break;
+#pragma omp parallel for schedule(static)
+      for (int64_t lin = 0; lin < N; ++lin) {
+        const int64_t idx[2] = {lin % P->n[0], lin / P->n[0]};
+        double x[3] = {0.0, 0.0, 0.0}, sh[3];
+        for (int a = 0; a < 2; ++a) x[a] = ((double)idx[a] + disp[a * N + lin]) * hx[a];
+        orc_zinterp(P, P->order_max, 3, (const double *const *)Sp, x, sh);
+        for (int a = 0; a < 2; ++a) {
+          const double ua = Hp[a][lin];
+          qx[a * N + lin] = A[s] * qx[a * N + lin] + dt * ua / hx[a];
+          disp[a * N + lin] += B[s] * qx[a * N + lin];
+        }
+        for (int c = 0; c < 3; ++c) {
+          qh[c * N + lin] = A[s] * qh[c * N + lin] + dt * sh[c];
+          Hp[c][lin] += B[s] * qh[c * N + lin];
+        }
+      }
+    }
+    if (rc != ORC_OK) break;
+    orc_stats st;
+    rc = orc_reconstruct(P, disp, (const double *const *)Hp, (double *const *)fields, &st,
+                         NULL);
+    accumulate_stats(&tot, &st);
+  }
+  free(disp);
+  free(qx);
+  free(H);
+  free(qh);
+  free(G);
+  free(S);
   if (stats) *stats = tot;
   return rc;
 }

@@ -20,6 +20,8 @@ import numpy as np
 
 # Velocity kinds, numbered as in the C interface.
 VEL_UNIFORM, VEL_SOLID_BODY, VEL_SWIRL2D, VEL_DEFORM3D, VEL_FOURIER, VEL_GRIDDED, VEL_CARRIED = range(7)
+# Source kinds, numbered as in the C interface.
+SRC_NONE, SRC_SHALLOW_WATER = 0, 1
 
 
 def rng(seed: int) -> np.random.Generator:
@@ -168,6 +170,10 @@ class Workload:
     # VEL_GRIDDED: velocity samples on the mesh, components x-first, each an
     # array of `shape` (physical units).
     ugrid: list | None = None
+    # Source term: SRC_SHALLOW_WATER with sp = (fc, beta, y0, nu); the fields
+    # are then u1, u2, h and the velocity is VEL_CARRIED.
+    source: int = SRC_NONE
+    sp: tuple = (0.0, 0.0, 0.0, 0.0)
 
     @property
     def dim(self):
@@ -257,6 +263,41 @@ def burgers(n: int = 256, dim: int = 2, t_end: float = 0.3, cfl: float = 0.5,
     return Workload("burgers%dd_%d_%s" % (dim, n, value_prec), shape, (1.0,) * dim, fs,
                     Velocity(VEL_CARRIED), dt=dt, nsteps=int(round(t_end / dt)),
                     order_max=2, limiter=True, value_prec=value_prec)
+
+
+def kelvin_fields(shape, t: float, amp: float, f0: float, x0: float = 0.5,
+                  y0: float = 0.5) -> list:
+    """The equatorial Kelvin wave of the linearised shallow-water system
+    (eq. "kelvin"): h = u1 = exp(-f0 y^2/2) K(x - t), u2 = 0, with
+    K(s) = amp exp(-f0 s^2/2), y measured from the equator y0 and s from x0,
+    periodic in x (nearest image) on the unit box.  Returns [u1, u2, h]."""
+    X = _xyz(shape)
+    s = X[0] - x0 - t
+    s = s - np.round(s)
+    y = X[1] - y0
+    h = np.broadcast_to(amp * np.exp(-0.5 * f0 * s * s) * np.exp(-0.5 * f0 * y * y),
+                        tuple(shape)).astype(np.float64).copy()
+    return [h.copy(), np.zeros(tuple(shape)), h]
+
+
+def kelvin(n: int = 256, amp: float = 1e-4, f0: float = 250.0, nu: float = 0.0,
+           t_end: float = 1.0, cfl: float = 0.5, value_prec: str = "f64",
+           limiter: bool = False) -> Workload:
+    """Shallow-water Kelvin-wave test of Sec. 3 (eq. "nlsw" with the equatorial
+    beta plane f = f0 (y - 0.5) on the unit box, bi-periodic): the initial
+    state is the Kelvin wave at t = 0 with K(x) = amp exp(-f0 x^2/2) centred on
+    x = 0.5.  amp = 1e-4, nu = 0 is the linear convergence test (the exact
+    solution travels east at unit speed, so at t = 1 it is back where it
+    started); amp = 0.5, nu = 5e-4 is the non-linear run.  Fields u1, u2, h;
+    carried velocity; Z2; dt = t_end / ceil(t_end / (cfl h)) (unit gravity-wave
+    speed)."""
+    shape = (n, n)
+    fs = kelvin_fields(shape, 0.0, amp, f0)
+    nsteps = int(math.ceil(t_end * n / cfl - 1e-9))
+    return Workload("kelvin_%d_%s" % (n, value_prec), shape, (1.0, 1.0), fs,
+                    Velocity(VEL_CARRIED), dt=t_end / nsteps, nsteps=nsteps,
+                    order_max=2, limiter=limiter, value_prec=value_prec,
+                    integrator=1, source=SRC_SHALLOW_WATER, sp=(0.0, f0, 0.5, nu))
 
 
 def solid_body_gaussian(n: int = 64, steps: int = 100, order_max: int = 2) -> Workload:
