@@ -114,6 +114,32 @@ enum {
   SL_VEL_CARRIED = 6
 };
 
+/* Source terms, the right-hand side S_i of the transport equations (Sec. 2,
+ * eq. "momento"), with spatial derivatives taken by centred finite differences
+ * on the reference mesh (2m+1 points for the Z-spline order m in use, at least
+ * three: the rules whose values the Z-splines' derivatives take at the knots,
+ * eq. "matchder"):
+ *   SL_SRC_NONE           pure transport
+ *   SL_SRC_SHALLOW_WATER  the 2-D shallow-water system of eq. "nlsw" with
+ *                         fields (u1, u2, h, passive ...), a carried velocity
+ *                         and source_p = (fc, beta, y0, nu):
+ *                           S_h  = -(1 + h) div u
+ *                           S_u  = -grad h - f u_perp + nu div[(1 + h)(grad u +
+ *                                  grad u^T)],  u_perp = (-u2, u1),
+ *                           f    = fc + beta (y - y0)
+ *                         (the paper's equatorial beta plane is fc = 0, beta =
+ *                         f0, y0 the equator).  Needs dim 2, SL_VEL_CARRIED,
+ *                         nfields >= 3, SL_RK3_WILLIAMSON and
+ *                         reconstruct_every 1; runs through sl_advance only.
+ *   A step integrates every lattice node's position and values with the
+ *   low-storage RK3 of Williamson: each stage takes the stage fields on the
+ *   mesh (the fields at t, then the reconstruction of the lattice's stage
+ *   values), evaluates S there, and advances each node with its own velocity
+ *   and S interpolated at its position with the order-m Z-spline; the fields
+ *   at t + dt are the reconstruction of the final lattice values (three
+ *   reconstructions per step). */
+enum { SL_SRC_NONE = 0, SL_SRC_SHALLOW_WATER = 1 };
+
 typedef struct sl_velocity {
   int kind;
   double p[8];
@@ -138,6 +164,8 @@ typedef struct sl_grid_desc {
   int walk_max;           /* element-walk moves before the fallback scan, 32 */
   int scan_radius;        /* half-width of the fallback scan box, 4 */
   double eps_inside;      /* slack on the unit cube when accepting, 1e-12 */
+  int source;             /* SL_SRC_NONE or SL_SRC_SHALLOW_WATER */
+  double source_p[4];     /* source parameters, see SL_SRC_SHALLOW_WATER */
 } sl_grid_desc;
 
 /* Counters accumulated on the device since the last sl_sync. */
@@ -206,7 +234,8 @@ int sl_sync(sl_grid *grid, void *workspace, void *stream, sl_stats *stats);
  * *result_in_b (may be NULL) tells which set holds the result.  nsteps must be
  * a multiple of reconstruct_every and the lattice must be reset (no pending
  * sl_step).  Asynchronous on `stream`; equivalent to the sequence of sl_step /
- * sl_reconstruct calls but without per-call host overhead.
+ * sl_reconstruct calls but without per-call host overhead.  With a source term
+ * it is the only way to step (see SL_SRC_SHALLOW_WATER).
  * Errors: SL_EINVAL, SL_ESTATE, SL_EHIP. */
 int sl_advance(sl_grid *grid, void *workspace, void *const *fields_a,
                void *const *fields_b, double t0, double dt, int nsteps,
@@ -214,8 +243,9 @@ int sl_advance(sl_grid *grid, void *workspace, void *const *fields_a,
 
 /* Kernel timing: when enabled, the timed launches of the grid carry HIP
  * events in their dispatch packets.  Kinds: trajectories (sl_step), the
- * reconstruction kernel, and the limiter order-word kernels that precede it
- * in sl_reconstruct (none when the limiter is off). */
+ * reconstruction kernel, the limiter order-word kernels that precede it in
+ * sl_reconstruct (none when the limiter is off), and the source-term kernels
+ * (SL_SRC_SHALLOW_WATER). */
 typedef struct sl_profile {
   int64_t traj_launches;
   double traj_ms;          /* summed kernel time of the timed trajectory launches */
@@ -223,6 +253,8 @@ typedef struct sl_profile {
   double recon_ms;         /* summed kernel time of the timed reconstruction launches */
   int64_t orders_launches;
   double orders_ms;        /* first order-word kernel start to last one's end, summed */
+  int64_t source_launches;
+  double source_ms;        /* source-term kernels (mesh right-hand side, lattice stage) */
 } sl_profile;
 
 /* Time every `period`-th launch of each kind from now on (1: every launch;

@@ -20,6 +20,7 @@ SL_OK, SL_EINVAL, SL_ENOMEM, SL_EHIP, SL_ESEARCH, SL_ENEWTON, SL_ENONFINITE, \
     SL_EBUSY, SL_ESTATE, SL_ENOTFOUND = 0, -1, -2, -3, -4, -5, -6, -7, -8, -9
 SL_FP64, SL_FP32 = 0, 1
 SL_RK4, SL_RK3_WILLIAMSON = 0, 1
+SL_SRC_NONE, SL_SRC_SHALLOW_WATER = 0, 1
 SL_MAX_FIELDS = 8
 SL_MAX_MODES = 32
 
@@ -37,6 +38,7 @@ class SlGridDesc(C.Structure):
         ("reconstruct_every", C.c_int), ("vel", SlVelocity),
         ("newton_max_iter", C.c_int), ("newton_tol", C.c_double),
         ("walk_max", C.c_int), ("scan_radius", C.c_int), ("eps_inside", C.c_double),
+        ("source", C.c_int), ("source_p", C.c_double * 4),
     ]
 
 
@@ -58,7 +60,8 @@ class SlStats(C.Structure):
 class SlProfile(C.Structure):
     _fields_ = [("traj_launches", C.c_int64), ("traj_ms", C.c_double),
                 ("recon_launches", C.c_int64), ("recon_ms", C.c_double),
-                ("orders_launches", C.c_int64), ("orders_ms", C.c_double)]
+                ("orders_launches", C.c_int64), ("orders_ms", C.c_double),
+                ("source_launches", C.c_int64), ("source_ms", C.c_double)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -152,7 +155,7 @@ def make_desc(shape: Sequence[int], nfields: int, *, length=None, value_prec="f6
               order_max=2, limiter=False, theta=0.25, integrator=SL_RK4,
               reconstruct_every=1, vel_kind=0, vel_params=None, modes=None,
               newton_max_iter=20, newton_tol=1e-14, walk_max=32, scan_radius=4,
-              eps_inside=1e-12):
+              eps_inside=1e-12, source=SL_SRC_NONE, source_p=None):
     """Descriptor for a grid whose arrays have `shape` (array order, x last)."""
     d = SlGridDesc()
     load().sl_grid_desc_init(C.byref(d))
@@ -183,6 +186,10 @@ def make_desc(shape: Sequence[int], nfields: int, *, length=None, value_prec="f6
     d.walk_max = int(walk_max)
     d.scan_radius = int(scan_radius)
     d.eps_inside = float(eps_inside)
+    d.source = int(source)
+    sp = list(source_p or []) + [0.0] * 4
+    for i in range(4):
+        d.source_p[i] = float(sp[i])
     return d, keep
 
 
@@ -211,7 +218,9 @@ class Grid:
         kw = dict(length=wl.length, value_prec=wl.value_prec, order_max=wl.order_max,
                   limiter=wl.limiter, theta=wl.theta, integrator=wl.integrator,
                   reconstruct_every=wl.reconstruct_every, vel_kind=wl.velocity.kind,
-                  vel_params=wl.velocity.padded_params(), modes=wl.velocity.modes)
+                  vel_params=wl.velocity.padded_params(), modes=wl.velocity.modes,
+                  source=getattr(wl, "source", SL_SRC_NONE),
+                  source_p=list(getattr(wl, "sp", (0.0,) * 4)))
         kw.update(over)
         g = cls(wl.shape, wl.nfields, device=device, **kw)
         if getattr(wl, "ugrid", None) is not None and kw["vel_kind"] == 5:

@@ -32,6 +32,7 @@
 #include "sl_orders.h"
 #include "sl_recon2d.h"
 #include "sl_recon3d.h"
+#include "sl_source.h"
 #include "sl_traj.h"
 
 namespace sl {
@@ -159,6 +160,14 @@ int check_desc(const sl_grid_desc* d) {
   }
   for (int c = 0; c < 8; ++c)
     if (!isfinite(v.p[c])) return SL_EINVAL;
+  if (d->source != SL_SRC_NONE) {
+    if (d->source != SL_SRC_SHALLOW_WATER) return SL_EINVAL;
+    if (d->dim != 2 || v.kind != SL_VEL_CARRIED || d->nfields < 3) return SL_EINVAL;
+    if (d->integrator != SL_RK3_WILLIAMSON || d->reconstruct_every != 1) return SL_EINVAL;
+    for (int c = 0; c < 4; ++c)
+      if (!isfinite(d->source_p[c])) return SL_EINVAL;
+    if (d->source_p[3] < 0.0) return SL_EINVAL;
+  }
   return SL_OK;
 }
 
@@ -443,6 +452,16 @@ int sl_create_grid(const sl_grid_desc* desc, sl_grid** out) {
   // trajectories there while the current step reconstructs.
   gr->off_disp2 = align_up(gr->off_ord + 4 * (size_t)gr->ntot);
   gr->ws_bytes = align_up(gr->off_disp2 + sizeof(double) * (size_t)D * (size_t)gr->ntot);
+  if (desc->source != SL_SRC_NONE) {
+    const size_t vbytes = (desc->value_prec == SL_FP32 ? 4 : 8) * (size_t)gr->ntot;
+    const size_t plane = sizeof(double) * (size_t)gr->ntot;
+    gr->off_src_h = gr->ws_bytes;
+    gr->off_src_g = align_up(gr->off_src_h + (size_t)desc->nfields * vbytes);
+    gr->off_src_qx = align_up(gr->off_src_g + (size_t)desc->nfields * vbytes);
+    gr->off_src_qh = align_up(gr->off_src_qx + 2 * plane);
+    gr->off_src_s = align_up(gr->off_src_qh + 3 * plane);
+    gr->ws_bytes = align_up(gr->off_src_s + 3 * plane);
+  }
   // 2-D grids evaluate the limiter flags inside the reconstruction tiles
   // (the values are staged there anyway) unless the grid is large, where a
   // separate order-word pass costs less than the tiles' redundant flag work.
@@ -547,6 +566,83 @@ hipError_t reconstruct_launches(sl_grid* gr, char* ws, const sl::FieldPtrs& fp,
   return e;
 }
 
+// sl_advance with a source term (SL_SRC_SHALLOW_WATER): per step three
+// Runge-Kutta stages of the lattice (mesh right-hand side, then the stage
+// kernel), the stage fields between them reconstructed on the mesh, and the
+// final reconstruction into the other field set.
+template <typename T, int M>
+hipError_t advance_source(sl_grid* gr, char* ws, void* const* fields_a, void* const* fields_b,
+                          double dt, int nsteps, hipStream_t s) {
+  // Williamson's 2N-storage third-order scheme.
+  static const double kA[3] = {0.0, -5.0 / 9.0, -153.0 / 128.0};
+  static const double kB[3] = {1.0 / 3.0, 15.0 / 16.0, 8.0 / 15.0};
+  const int nf = gr->desc.nfields;
+  const size_t vbytes = sizeof(T) * (size_t)gr->ntot;
+  const size_t N = (size_t)gr->ntot;
+  double* disp = reinterpret_cast<double*>(ws + gr->off_disp);
+  double* qx = reinterpret_cast<double*>(ws + gr->off_src_qx);
+  double* qh = reinterpret_cast<double*>(ws + gr->off_src_qh);
+  double* S = reinterpret_cast<double*>(ws + gr->off_src_s);
+  T* H[SL_MAX_FIELDS];
+  T* G[SL_MAX_FIELDS];
+  for (int f = 0; f < nf; ++f) {
+    H[f] = reinterpret_cast<T*>(ws + gr->off_src_h + (size_t)f * vbytes);
+    G[f] = reinterpret_cast<T*>(ws + gr->off_src_g + (size_t)f * vbytes);
+  }
+  sl::FieldPtrs to_stage, to_next;  // lattice values -> stage fields / result
+  memset(&to_stage, 0, sizeof(to_stage));
+  for (int f = 0; f < nf; ++f) {
+    to_stage.in[f] = H[f];
+    to_stage.out[f] = G[f];
+  }
+  const sl::SrcArgs sa{gr->desc.source_p[0], gr->desc.source_p[1], gr->desc.source_p[2],
+                       gr->desc.source_p[3]};
+  const dim3 blocks((unsigned)((gr->g.n[0] + sl::kTrajBX - 1) / sl::kTrajBX),
+                    (unsigned)((gr->g.n[1] + sl::kTrajBY - 1) / sl::kTrajBY));
+  const dim3 threads(sl::kTrajBX, sl::kTrajBY);
+  hipError_t e = hipSuccess;
+  for (int k = 0; k < nsteps && e == hipSuccess; ++k) {
+    void* const* cur = (k & 1) ? fields_b : fields_a;
+    void* const* nxt = (k & 1) ? fields_a : fields_b;
+    gr->steps_launched++;
+    for (int st = 0; st < 3 && e == hipSuccess; ++st) {
+      if (st > 0) {
+        e = reconstruct_launches(gr, ws, to_stage, disp, sl::NextTraj{}, s);
+        if (e != hipSuccess) break;
+        gr->reconstructs_launched++;
+      }
+      const T* gs[3];
+      for (int c = 0; c < 3; ++c)
+        gs[c] = st == 0 ? static_cast<const T*>(cur[c]) : static_cast<const T*>(G[c]);
+      const ProfSlot p0 = prof_begin(gr, 3);
+      e = launch(sl::sw_source_kernel<T, M>, blocks, threads, 0, s, p0.start, p0.stop, gr->g,
+                 sa, gs[0], gs[1], gs[2], S, S + N, S + 2 * N);
+      prof_end(gr, p0, 3, e);
+      if (e != hipSuccess) break;
+      sl::FieldPtrs fp;
+      memset(&fp, 0, sizeof(fp));
+      for (int f = 0; f < nf; ++f) {
+        fp.in[f] = cur[f];
+        fp.out[f] = H[f];
+      }
+      const sl::SrcStage ss{kA[st], kB[st], dt, st == 0 ? 1 : 0};
+      const ProfSlot p1 = prof_begin(gr, 3);
+      e = launch(sl::sw_stage_kernel<T>, blocks, threads, 0, s, p1.start, p1.stop, gr->g, ss, fp,
+                 disp, qx, qh, (const double*)S);
+      prof_end(gr, p1, 3, e);
+    }
+    if (e != hipSuccess) break;
+    memset(&to_next, 0, sizeof(to_next));
+    for (int f = 0; f < nf; ++f) {
+      to_next.in[f] = H[f];
+      to_next.out[f] = nxt[f];
+    }
+    e = reconstruct_launches(gr, ws, to_next, disp, sl::NextTraj{}, s);
+    if (e == hipSuccess) gr->reconstructs_launched++;
+  }
+  return e;
+}
+
 }  // namespace
 
 extern "C" {
@@ -617,6 +713,28 @@ int sl_advance(sl_grid* gr, void* workspace, void* const* fields_a, void* const*
   if (nsteps % K) return SL_EINVAL;
   if (gr->steps_since_reset != 0) return SL_ESTATE;
   if (gr->v.kind == SL_VEL_GRIDDED && !gr->v.ug[0]) return SL_ESTATE;
+  if (gr->desc.source != SL_SRC_NONE) {
+    if (((uintptr_t)workspace) % kAlign) return SL_EINVAL;
+    sl::FieldPtrs ab, ba;
+    int rc = field_ptrs(gr, (const void* const*)fields_a, fields_b, &ab);
+    if (rc == SL_OK) rc = field_ptrs(gr, (const void* const*)fields_b, fields_a, &ba);
+    if (rc != SL_OK) return rc;
+    if (!isfinite(dt)) return SL_EINVAL;
+    char* ws = static_cast<char*>(workspace);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    clear_stale_error();
+    const bool f32 = gr->desc.value_prec == SL_FP32;
+    const bool m1 = gr->desc.order_max < 2;  // three-point rules below Z2
+    hipError_t e;
+    if (f32)
+      e = m1 ? advance_source<float, 1>(gr, ws, fields_a, fields_b, dt, nsteps, s)
+             : advance_source<float, 2>(gr, ws, fields_a, fields_b, dt, nsteps, s);
+    else
+      e = m1 ? advance_source<double, 1>(gr, ws, fields_a, fields_b, dt, nsteps, s)
+             : advance_source<double, 2>(gr, ws, fields_a, fields_b, dt, nsteps, s);
+    if (e == hipSuccess && result_in_b) *result_in_b = nsteps & 1;
+    return hip_status(e);
+  }
   if (K == 1 && nsteps > 0 && gr->v.kind != SL_VEL_GRIDDED) {
     // Each reconstruction also integrates the next step's trajectories into
     // the other displacement buffer, so a step is one reconstruction launch
@@ -699,7 +817,7 @@ int sl_advance(sl_grid* gr, void* workspace, void* const* fields_a, void* const*
 int sl_profile_enable(sl_grid* gr, int period) {
   if (!gr) return SL_EINVAL;
   gr->prof_period = period > 0 ? period : 0;
-  gr->prof_count[0] = gr->prof_count[1] = gr->prof_count[2] = 0;
+  gr->prof_count[0] = gr->prof_count[1] = gr->prof_count[2] = gr->prof_count[3] = 0;
   return SL_OK;
 }
 
@@ -713,9 +831,13 @@ int sl_profile_read(sl_grid* gr, sl_profile* out) {
     out->recon_ms = gr->prof_ms[1];
     out->orders_launches = gr->prof_n[2];
     out->orders_ms = gr->prof_ms[2];
+    out->source_launches = gr->prof_n[3];
+    out->source_ms = gr->prof_ms[3];
   }
-  gr->prof_n[0] = gr->prof_n[1] = gr->prof_n[2] = 0;
-  gr->prof_ms[0] = gr->prof_ms[1] = gr->prof_ms[2] = 0.0;
+  for (int k = 0; k < 4; ++k) {
+    gr->prof_n[k] = 0;
+    gr->prof_ms[k] = 0.0;
+  }
   return SL_OK;
 }
 

@@ -1,0 +1,136 @@
+"""GPU source-term path (shallow-water right-hand side by finite differences on
+the mesh, Williamson RK3 along the lattice; Sec. 2, eq. "nlsw") against the
+FP64 oracle on the same seeded inputs.  Tolerance on the relative L1 over all
+nodes and fields: 1e-12 for FP64 values, 1e-5 for FP32 values after one step;
+each field that carries at least 1e-3 of the total is also held to it."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1410_2817_amd import workloads as W
+from tests.util import linf, oracle_problem, stored_values, tol
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as T
+    if not T.cuda.is_available():
+        pytest.fail("no GPU visible")
+    return T
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_1410_2817_amd import binding
+    binding.load()
+    return binding
+
+
+def sw_workload(shape, amp=0.3, nu=0.0, fc=0.0, beta=50.0, m=2, limiter=False,
+                value_prec="f64", passive=False, cfl=0.5, seed=5):
+    """A shallow-water problem on a possibly ragged grid: a Gaussian bump of h
+    with a smooth random velocity (4 modes), optionally a passive slotted disc."""
+    g = W.rng(seed)
+    x, y = W._xyz(shape)
+    h = amp * np.exp(-((x - 0.45) ** 2 + (y - 0.55) ** 2) / (2 * 0.08 ** 2))
+    u = np.zeros(shape)
+    v = np.zeros(shape)
+    for _ in range(4):
+        kx, ky = g.integers(1, 3, 2)
+        a, b, ph = g.normal(0, 0.1), g.normal(0, 0.1), g.uniform(0, 2 * np.pi)
+        u = u + a * np.sin(2 * np.pi * (kx * x + ky * y) + ph)
+        v = v + b * np.cos(2 * np.pi * (kx * x - ky * y) + ph)
+    fs = [np.broadcast_to(q, shape).astype(np.float64).copy() for q in (u, v, h)]
+    if passive:
+        fs.append(W.slotted_disk(shape, (0.5, 0.7), 0.15, 0.05, 0.25))
+    dt = cfl * min(1.0 / shape[0], 1.0 / shape[1])
+    return W.Workload("sw_%dx%d" % (shape[1], shape[0]), tuple(shape), (1.0, 1.0), fs,
+                      W.Velocity(W.VEL_CARRIED), dt=dt, nsteps=1, order_max=m,
+                      limiter=limiter, value_prec=value_prec, integrator=1,
+                      source=W.SRC_SHALLOW_WATER, sp=(fc, beta, 0.5, nu))
+
+
+def gpu_run(B, wl, nsteps):
+    g = B.Grid.from_workload(wl)
+    fin = g.new_fields(stored_values(wl))
+    out = g.advance(fin, 0.0, wl.dt, nsteps)
+    rc, st = g.sync()
+    return [f.double().cpu().numpy() for f in out], st, rc
+
+
+def oracle_run(orc, wl, nsteps):
+    rc, fs, st = orc.run_source(oracle_problem(orc, wl), 0.0, wl.dt, nsteps, stored_values(wl))
+    return fs, st, rc
+
+
+def check(name, wl, got, want, bound):
+    num = sum(float(np.abs(a - b).sum()) for a, b in zip(got, want))
+    den = sum(float(np.abs(b).sum()) for b in want)
+    say(" ", name, "relative L1 over fields", num / den)
+    assert num / den <= bound, (name, num / den)
+    for f, (a, b) in enumerate(zip(got, want)):
+        share = float(np.abs(b).sum()) / den
+        e = float(np.abs(a - b).sum()) / max(float(np.abs(b).sum()), 1e-300)
+        say("  field", f, "L1", e, "share", share, "Linf", linf(a, b))
+        if share >= 1e-3:
+            assert e <= bound, (name, f, e)
+
+
+def _cases():
+    yield "kelvin64_f64", W.kelvin(64, amp=1e-4, t_end=0.25), 1
+    yield "kelvin64_f64_8", W.kelvin(64, amp=1e-4, t_end=0.25), 8
+    yield "kelvin64_f32", W.kelvin(64, amp=1e-4, t_end=0.25, value_prec="f32"), 1
+    yield "nonlinear_visc_80x96", sw_workload((80, 96), amp=0.5, nu=5e-3), 3
+    yield "nonlinear_limiter_70x90", sw_workload((70, 90), amp=0.5, limiter=True), 3
+    yield "fplane_passive_f64", sw_workload((48, 64), fc=4.0, beta=0.0, passive=True,
+                                            limiter=True), 4
+    yield "three_point_rules_z1", sw_workload((40, 56), m=1, nu=2e-3), 3
+    yield "nonlinear_f32_1step", sw_workload((80, 96), amp=0.5, nu=5e-3, value_prec="f32"), 1
+    yield "passive_f32_1step", sw_workload((48, 64), passive=True, limiter=True,
+                                           value_prec="f32"), 1
+
+
+@pytest.mark.parametrize("name,wl,nsteps", list(_cases()))
+def test_source_parity(B, torch, orc, name, wl, nsteps):
+    say("source", name, wl.shape, wl.value_prec, "steps", nsteps)
+    got, st, rc = gpu_run(B, wl, nsteps)
+    want, ost, orc_rc = oracle_run(orc, wl, nsteps)
+    assert rc == 0 and orc_rc == 0, (rc, orc_rc)
+    assert st["search_fail"] == 0 and st["newton_fail"] == 0
+    # three reconstructions per step
+    assert st["reconstructs"] == 3 * nsteps
+    check(name, wl, got, want, tol(wl))
+    if wl.value_prec == "f64":
+        assert st["order_hist"] == ost["order_hist"]
+
+
+def test_zero_steps_leave_fields(B, torch):
+    wl = sw_workload((32, 40))
+    got, st, rc = gpu_run(B, wl, 0)
+    assert rc == 0
+    for a, b in zip(got, stored_values(wl)):
+        assert np.array_equal(a, b)
+
+
+def test_kelvin_wave_error_matches_the_oracle(B, torch, orc):
+    """The Kelvin-wave test of Sec. 3 at 128^2 to t = 0.25 (64 steps): the GPU
+    run equals the oracle's, so its error against the exact wave is the
+    oracle's (third-order convergence is pinned on the oracle)."""
+    wl = W.kelvin(128, amp=1e-4, t_end=0.25)
+    got, st, rc = gpu_run(B, wl, wl.nsteps)
+    want, ost, orc_rc = oracle_run(orc, wl, wl.nsteps)
+    assert rc == 0 and orc_rc == 0
+    check("kelvin128", wl, got, want, 1e-12)
+    ex = W.kelvin_fields(wl.shape, 0.25, 1e-4, 250.0)
+    eg = np.sqrt(((got[2] - ex[2]) ** 2).sum() / (ex[2] ** 2).sum())
+    eo = np.sqrt(((want[2] - ex[2]) ** 2).sum() / (ex[2] ** 2).sum())
+    say("  L2 error vs exact: gpu", eg, "oracle", eo)
+    assert abs(eg - eo) <= 1e-9 * eo and eg < 5e-4

@@ -7,7 +7,9 @@ def oracle_problem(orc, wl, **kw):
     return orc.Problem(wl.shape, wl.nfields, wl.length, order_max=wl.order_max,
                        limiter=wl.limiter, theta=wl.theta, integrator=wl.integrator,
                        vel_kind=wl.velocity.kind, vp=wl.velocity.padded_params(),
-                       modes=wl.velocity.modes, ugrid=getattr(wl, "ugrid", None), **kw)
+                       modes=wl.velocity.modes, ugrid=getattr(wl, "ugrid", None),
+                       src_kind=getattr(wl, "source", 0),
+                       sp=list(getattr(wl, "sp", (0.0,) * 4)), **kw)
 
 
 def stored_values(wl):
