@@ -108,11 +108,13 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="swirl", choices=["swirl", "fourier3d", "deform3d"],
+    ap.add_argument("--workload", default="swirl",
+                    choices=["swirl", "fourier3d", "deform3d", "kelvin"],
                     help="swirl: the 2-D reversing swirl (default); fourier3d / deform3d: the "
-                         "3-D Fourier-mode and deformational flows (for profiling runs)")
+                         "3-D Fourier-mode and deformational flows; kelvin: the shallow-water "
+                         "Kelvin wave with source terms (for profiling runs)")
     ap.add_argument("--n", type=int, default=None,
-                    help="grid side (default 1024 swirl, 256 fourier3d, 512 deform3d)")
+                    help="grid side (default 1024 swirl and kelvin, 256 fourier3d, 512 deform3d)")
     ap.add_argument("--steps", type=int, default=None,
                     help="timed steps (default 1280 swirl = one period, 50 fourier3d, 60 deform3d)")
     ap.add_argument("--prec", default="f32", choices=["f32", "f64"])
@@ -169,11 +171,15 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
-    dim = 2 if args.workload == "swirl" else 3
+    dim = 2 if args.workload in ("swirl", "kelvin") else 3
     if args.workload == "swirl":
         args.n = args.n or 1024
         wl = W.swirl_three_fields(args.n, value_prec=args.prec)
         args.steps = args.steps or 1280
+    elif args.workload == "kelvin":
+        args.n = args.n or 1024
+        wl = W.kelvin(args.n, amp=1e-4, t_end=1.0, value_prec=args.prec)
+        args.steps = args.steps or wl.nsteps
     elif args.workload == "fourier3d":
         args.n = args.n or 256
         wl = W.fourier3d_three_fields(args.n, value_prec=args.prec)
@@ -216,6 +222,8 @@ def main():
     recon_ms = prof["recon_ms"] / max(prof["recon_launches"], 1)
     traj_ms = prof["traj_ms"] / max(prof["traj_launches"], 1)
     orders_ms = prof["orders_ms"] / max(prof["orders_launches"], 1)
+    source_ms = prof["source_ms"] / max(prof["source_launches"], 1)
+    sourced = bool(getattr(wl, "source", 0))
 
     value = nodes * args.steps / elapsed
     vb = 4 if args.prec == "f32" else 8
@@ -223,6 +231,9 @@ def main():
     # trajectories (all launches but the last), so it writes their
     # displacements too.
     per_node = recon_bytes_per_node(dim, wl.nfields, vb) + traj_bytes_per_node(dim)
+    if sourced:
+        # The source path's reconstructions integrate no trajectories.
+        per_node = recon_bytes_per_node(dim, wl.nfields, vb)
     achieved = per_node * nodes / (recon_ms * 1e-3) / 1e9 if recon_ms > 0 else None
 
     # Accuracy: after a whole period the exact solution is the initial state.
@@ -256,7 +267,8 @@ def main():
             "dt": wl.dt, "t_end": args.steps * wl.dt,
         },
         "roofline": {
-            "kernel": "reconstruction + next step's trajectories (%s)" % (
+            "kernel": ("reconstruction (%s)" if sourced else
+                       "reconstruction + next step's trajectories (%s)") % (
                 "recon2d_tiled_kernel" if dim == 2 else "recon3d_kernel"),
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS if achieved else None,
@@ -266,7 +278,8 @@ def main():
         },
         "field_node_updates_per_s": value * wl.nfields,
         "kernels": {"trajectories_avg_ms": traj_ms, "reconstruction_avg_ms": recon_ms,
-                    "order_words_avg_ms": orders_ms, "event_period": args.event_period},
+                    "order_words_avg_ms": orders_ms, "source_kernels_avg_ms": source_ms,
+                    "event_period": args.event_period},
         "accuracy": acc,
     }
     if not args.no_configs and headline:
@@ -408,6 +421,60 @@ def other_configs():
                             [np.asarray(f, np.float64) for f in wl.fields])
     res["burgers2d_512_f64"]["l1_rel_vs_oracle_20_steps"] = [
         _l1(g.double().cpu().numpy(), o) for g, o in zip(out20, ofs)]
+    res.update(kelvin_configs())
+    return res
+
+
+def kelvin_configs():
+    """Shallow-water source terms (Sec. 3): the equatorial Kelvin wave to t = 1,
+    relative L2 error of h against the exact wave and the observed order, at
+    the paper's amplitude 1e-4 on coarse grids and at 1e-7 (the linear limit,
+    where the exact wave is exact for the equations) up to 1024^2; the 1024^2
+    run timed; the non-linear viscous run at 1024^2; and 8 non-linear steps at
+    256^2 against the oracle."""
+    import oracle
+    from paper_1410_2817_amd import workloads as W
+    res = {}
+
+    def ladder(amp, sizes):
+        rows = []
+        for n in sizes:
+            wl = W.kelvin(n, amp=amp, t_end=1.0)
+            out, el, prof, st = run_gpu(wl, wl.nsteps, warmup=0 if n < 1024 else 2)
+            ex = W.kelvin_fields(wl.shape, 1.0, amp, 250.0)
+            h = out[2].double().cpu().numpy()
+            err = float(np.sqrt(((h - ex[2]) ** 2).sum() / (ex[2] ** 2).sum()))
+            rows.append({"n": n, "steps": wl.nsteps, "l2_rel_vs_exact": err})
+            if n == 1024 and amp == 1e-4:
+                rl, sl = max(prof["recon_launches"], 1), max(prof["source_launches"], 1)
+                res["kelvin_1024_f64"] = {
+                    "node_updates_per_s": wl.nodes * wl.nsteps / el,
+                    "ms_per_step": el * 1e3 / wl.nsteps, "steps": wl.nsteps,
+                    "reconstruction_avg_ms": prof["recon_ms"] / rl,
+                    "source_kernel_avg_ms": prof["source_ms"] / sl,
+                    "reconstructions_per_step": 3, "source_launches_per_step": 6,
+                    "search_fail": st["search_fail"], "l2_rel_vs_exact_t1": err}
+            del out
+        for a, b in zip(rows, rows[1:]):
+            b["order"] = float(np.log2(a["l2_rel_vs_exact"] / b["l2_rel_vs_exact"]))
+        return rows
+
+    res["kelvin_convergence_amp1e-4_f64"] = ladder(1e-4, (32, 64, 128, 256))
+    res["kelvin_convergence_amp1e-7_f64"] = ladder(1e-7, (64, 128, 256, 512, 1024))
+    ladder(1e-4, (1024,))
+    wl = W.kelvin(1024, amp=0.5, nu=5e-4, t_end=1.0)
+    out, el, prof, st = run_gpu(wl, wl.nsteps)
+    res["kelvin_nonlinear_1024_f64"] = {
+        "node_updates_per_s": wl.nodes * wl.nsteps / el, "ms_per_step": el * 1e3 / wl.nsteps,
+        "steps": wl.nsteps, "search_fail": st["search_fail"], "walked": st["walked"],
+        "max_h": float(out[2].double().abs().max().item())}
+    del out
+    wl = W.kelvin(256, amp=0.5, nu=5e-4, t_end=1.0)
+    out, _, _, _ = run_gpu(wl, 8, profile=0, warmup=0)
+    rc, ofs, _ = oracle.run_source(_oracle_problem(oracle, wl), 0.0, wl.dt, 8,
+                                   [np.asarray(f, np.float64) for f in wl.fields])
+    res["kelvin_nonlinear_256_f64"] = {"l1_rel_vs_oracle_8_steps": [
+        _l1(g.double().cpu().numpy(), o) for g, o in zip(out, ofs)]}
     return res
 
 
@@ -415,14 +482,18 @@ def _oracle_problem(oracle, wl):
     return oracle.Problem(wl.shape, wl.nfields, wl.length, order_max=wl.order_max,
                           limiter=wl.limiter, theta=wl.theta, integrator=wl.integrator,
                           vel_kind=wl.velocity.kind, vp=wl.velocity.padded_params(),
-                          modes=wl.velocity.modes)
+                          modes=wl.velocity.modes, src_kind=getattr(wl, "source", 0),
+                          sp=list(getattr(wl, "sp", (0.0,) * 4)))
 
 
 def gpu_vs_oracle(wl, stored, steps, ofields):
     """GPU result after the oracle sample's steps against the oracle's."""
     out, _, _, _ = run_gpu(wl, steps, profile=0, warmup=0)
     got = [f.double().cpu().numpy() for f in out]
-    return {"steps": steps, "l1_rel": [_l1(g, o) for g, o in zip(got, ofields)],
+    num = sum(float(np.abs(g - o).sum()) for g, o in zip(got, ofields))
+    den = sum(float(np.abs(o).sum()) for o in ofields)
+    return {"steps": steps, "l1_rel_all_fields": num / max(den, 1e-300),
+            "l1_rel": [_l1(g, o) for g, o in zip(got, ofields)],
             "linf": [float(np.abs(g - o).max()) for g, o in zip(got, ofields)]}
 
 
@@ -459,7 +530,10 @@ def run_cpu_baseline(wl, stored, seconds):
     steps, spent = 0, 0.0
     while spent < seconds:
         t0 = time.perf_counter()
-        rc, fields, _ = oracle.run(prob, steps * wl.dt, wl.dt, 1, fields)
+        if getattr(wl, "source", 0):
+            rc, fields, _ = oracle.run_source(prob, steps * wl.dt, wl.dt, 1, fields)
+        else:
+            rc, fields, _ = oracle.run(prob, steps * wl.dt, wl.dt, 1, fields)
         spent += time.perf_counter() - t0
         steps += 1
         if rc != 0:

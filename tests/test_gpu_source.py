@@ -88,12 +88,12 @@ def _cases():
     yield "kelvin64_f64", W.kelvin(64, amp=1e-4, t_end=0.25), 1
     yield "kelvin64_f64_8", W.kelvin(64, amp=1e-4, t_end=0.25), 8
     yield "kelvin64_f32", W.kelvin(64, amp=1e-4, t_end=0.25, value_prec="f32"), 1
-    yield "nonlinear_visc_80x96", sw_workload((80, 96), amp=0.5, nu=5e-3), 3
+    yield "nonlinear_visc_80x96", sw_workload((80, 96), amp=0.5, nu=1e-3), 3
     yield "nonlinear_limiter_70x90", sw_workload((70, 90), amp=0.5, limiter=True), 3
     yield "fplane_passive_f64", sw_workload((48, 64), fc=4.0, beta=0.0, passive=True,
                                             limiter=True), 4
     yield "three_point_rules_z1", sw_workload((40, 56), m=1, nu=2e-3), 3
-    yield "nonlinear_f32_1step", sw_workload((80, 96), amp=0.5, nu=5e-3, value_prec="f32"), 1
+    yield "nonlinear_f32_1step", sw_workload((80, 96), amp=0.5, nu=1e-3, value_prec="f32"), 1
     yield "passive_f32_1step", sw_workload((48, 64), passive=True, limiter=True,
                                            value_prec="f32"), 1
 
