@@ -34,16 +34,22 @@ TRAFFIC_JSON = os.path.join(PROFILES, "recon2d_swirl1024_traffic.json")
 RECON_KERNEL = "recon2d_tiled_kernel<float, 3>"
 
 
+# The sources recon2d_tiled_kernel is compiled from (the kernel the traffic
+# record is taken on): its own header and everything it includes.
+HEADLINE_KERNEL_SOURCES = ("include/sl.h", "paper_1410_2817_amd/csrc/sl_device.h",
+                           "paper_1410_2817_amd/csrc/sl_traj.h",
+                           "paper_1410_2817_amd/csrc/sl_recon2d.h")
+
+
 def source_hash() -> str:
-    """Hash of the HIP sources, to tell whether recorded counters still apply."""
+    """Hash of the headline kernel's sources, to tell whether recorded counters
+    still apply."""
     import hashlib
     h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_1410_2817_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".h", ".hip")):
-            h.update(name.encode())
-            with open(os.path.join(csrc, name), "rb") as fh:
-                h.update(fh.read())
+    for rel in HEADLINE_KERNEL_SOURCES:
+        h.update(rel.encode())
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()[:16]
 
 

@@ -459,8 +459,7 @@ int sl_create_grid(const sl_grid_desc* desc, sl_grid** out) {
     gr->off_src_g = align_up(gr->off_src_h + (size_t)desc->nfields * vbytes);
     gr->off_src_qx = align_up(gr->off_src_g + (size_t)desc->nfields * vbytes);
     gr->off_src_qh = align_up(gr->off_src_qx + 2 * plane);
-    gr->off_src_s = align_up(gr->off_src_qh + 3 * plane);
-    gr->ws_bytes = align_up(gr->off_src_s + 3 * plane);
+    gr->ws_bytes = align_up(gr->off_src_qh + 3 * plane);
   }
   // 2-D grids evaluate the limiter flags inside the reconstruction tiles
   // (the values are staged there anyway) unless the grid is large, where a
@@ -567,8 +566,8 @@ hipError_t reconstruct_launches(sl_grid* gr, char* ws, const sl::FieldPtrs& fp,
 }
 
 // sl_advance with a source term (SL_SRC_SHALLOW_WATER): per step three
-// Runge-Kutta stages of the lattice (mesh right-hand side, then the stage
-// kernel), the stage fields between them reconstructed on the mesh, and the
+// Runge-Kutta stages of the lattice (one fused right-hand-side + stage kernel
+// each), the stage fields between them reconstructed on the mesh, and the
 // final reconstruction into the other field set.
 template <typename T, int M>
 hipError_t advance_source(sl_grid* gr, char* ws, void* const* fields_a, void* const* fields_b,
@@ -578,11 +577,9 @@ hipError_t advance_source(sl_grid* gr, char* ws, void* const* fields_a, void* co
   static const double kB[3] = {1.0 / 3.0, 15.0 / 16.0, 8.0 / 15.0};
   const int nf = gr->desc.nfields;
   const size_t vbytes = sizeof(T) * (size_t)gr->ntot;
-  const size_t N = (size_t)gr->ntot;
   double* disp = reinterpret_cast<double*>(ws + gr->off_disp);
   double* qx = reinterpret_cast<double*>(ws + gr->off_src_qx);
   double* qh = reinterpret_cast<double*>(ws + gr->off_src_qh);
-  double* S = reinterpret_cast<double*>(ws + gr->off_src_s);
   T* H[SL_MAX_FIELDS];
   T* G[SL_MAX_FIELDS];
   for (int f = 0; f < nf; ++f) {
@@ -597,9 +594,9 @@ hipError_t advance_source(sl_grid* gr, char* ws, void* const* fields_a, void* co
   }
   const sl::SrcArgs sa{gr->desc.source_p[0], gr->desc.source_p[1], gr->desc.source_p[2],
                        gr->desc.source_p[3]};
-  const dim3 blocks((unsigned)((gr->g.n[0] + sl::kTrajBX - 1) / sl::kTrajBX),
-                    (unsigned)((gr->g.n[1] + sl::kTrajBY - 1) / sl::kTrajBY));
-  const dim3 threads(sl::kTrajBX, sl::kTrajBY);
+  constexpr int TT = sl::StageTile::T;
+  const int tiles_x = (gr->g.n[0] + TT - 1) / TT, tiles_y = (gr->g.n[1] + TT - 1) / TT;
+  const int ntiles = tiles_x * tiles_y;
   hipError_t e = hipSuccess;
   for (int k = 0; k < nsteps && e == hipSuccess; ++k) {
     void* const* cur = (k & 1) ? fields_b : fields_a;
@@ -614,21 +611,16 @@ hipError_t advance_source(sl_grid* gr, char* ws, void* const* fields_a, void* co
       const T* gs[3];
       for (int c = 0; c < 3; ++c)
         gs[c] = st == 0 ? static_cast<const T*>(cur[c]) : static_cast<const T*>(G[c]);
-      const ProfSlot p0 = prof_begin(gr, 3);
-      e = launch(sl::sw_source_kernel<T, M>, blocks, threads, 0, s, p0.start, p0.stop, gr->g,
-                 sa, gs[0], gs[1], gs[2], S, S + N, S + 2 * N);
-      prof_end(gr, p0, 3, e);
-      if (e != hipSuccess) break;
       sl::FieldPtrs fp;
       memset(&fp, 0, sizeof(fp));
       for (int f = 0; f < nf; ++f) {
         fp.in[f] = cur[f];
         fp.out[f] = H[f];
       }
-      const sl::SrcStage ss{kA[st], kB[st], dt, st == 0 ? 1 : 0};
+      const sl::SrcStage ss{kA[st], kB[st], dt, st == 0 ? 1 : 0, st == 2 ? 1 : 0};
       const ProfSlot p1 = prof_begin(gr, 3);
-      e = launch(sl::sw_stage_kernel<T>, blocks, threads, 0, s, p1.start, p1.stop, gr->g, ss, fp,
-                 disp, qx, qh, (const double*)S);
+      e = launch(sl::sw_stage_kernel<T, M>, dim3(ntiles), dim3(256), 0, s, p1.start, p1.stop,
+                 gr->g, sa, ss, fp, gs[0], gs[1], gs[2], disp, qx, qh, tiles_x, ntiles);
       prof_end(gr, p1, 3, e);
     }
     if (e != hipSuccess) break;

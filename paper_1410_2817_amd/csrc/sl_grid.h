@@ -22,9 +22,9 @@ struct sl_grid {
   int64_t ntot;
   size_t off_stats, off_disp, off_flags, off_ord, off_disp2, ws_bytes;
   // Source terms: lattice values and stage fields (nfields arrays of the value
-  // precision each), RK registers of positions (2 planes) and values (3), and
-  // the mesh right-hand side (3 planes), all per node.
-  size_t off_src_h, off_src_g, off_src_qx, off_src_qh, off_src_s;
+  // precision each) and the RK registers of positions (2 FP64 planes) and
+  // values (3), all per node.
+  size_t off_src_h, off_src_g, off_src_qx, off_src_qh;
   bool limiter_words;  // limiter order words from a separate pass
   int steps_since_reset;
   int64_t steps_launched, reconstructs_launched;
