@@ -1,8 +1,13 @@
 """GPU source-term path (shallow-water right-hand side by finite differences on
 the mesh, Williamson RK3 along the lattice; Sec. 2, eq. "nlsw") against the
 FP64 oracle on the same seeded inputs.  Tolerance on the relative L1 over all
-nodes and fields: 1e-12 for FP64 values, 1e-5 for FP32 values after one step;
-each field that carries at least 1e-3 of the total is also held to it."""
+nodes and fields: 1e-12 for FP64 values, 1e-5 for FP32 values after one step.
+Each field is also held to it on its own when it carries at least 1e-3 (FP64)
+or 1e-2 (FP32) of the total L1: with FP32 values the lattice values are
+rounded at every stage, so the absolute rounding error follows the largest
+field (through the finite differences of the velocity it reaches h), and a
+field a hundred times smaller than the velocity sees it magnified in its own
+relative measure."""
 import sys
 
 import numpy as np
@@ -58,6 +63,15 @@ def sw_workload(shape, amp=0.3, nu=0.0, fc=0.0, beta=50.0, m=2, limiter=False,
                       source=W.SRC_SHALLOW_WATER, sp=(fc, beta, 0.5, nu))
 
 
+def shear_workload(n, U, cfl, value_prec="f64"):
+    """u1 = U sin(2 pi y) plus a small bump of h: the displacement varies by
+    about 2 pi U cfl 16 / n cells across a tile."""
+    wl = sw_workload((n, n), amp=0.05, beta=0.0, cfl=cfl, value_prec=value_prec)
+    x, y = W._xyz(wl.shape)
+    wl.fields[0] = np.broadcast_to(U * np.sin(2 * np.pi * y) + 0 * x, wl.shape).copy()
+    return wl
+
+
 def gpu_run(B, wl, nsteps):
     g = B.Grid.from_workload(wl)
     fin = g.new_fields(stored_values(wl))
@@ -71,7 +85,7 @@ def oracle_run(orc, wl, nsteps):
     return fs, st, rc
 
 
-def check(name, wl, got, want, bound):
+def check(name, wl, got, want, bound, min_share=None):
     num = sum(float(np.abs(a - b).sum()) for a, b in zip(got, want))
     den = sum(float(np.abs(b).sum()) for b in want)
     say(" ", name, "relative L1 over fields", num / den)
@@ -80,7 +94,8 @@ def check(name, wl, got, want, bound):
         share = float(np.abs(b).sum()) / den
         e = float(np.abs(a - b).sum()) / max(float(np.abs(b).sum()), 1e-300)
         say("  field", f, "L1", e, "share", share, "Linf", linf(a, b))
-        if share >= 1e-3:
+        floor = min_share if min_share is not None else (1e-2 if wl.value_prec == "f32" else 1e-3)
+        if share >= floor:
             assert e <= bound, (name, f, e)
 
 
@@ -96,6 +111,10 @@ def _cases():
     yield "nonlinear_f32_1step", sw_workload((80, 96), amp=0.5, nu=1e-3, value_prec="f32"), 1
     yield "passive_f32_1step", sw_workload((48, 64), passive=True, limiter=True,
                                            value_prec="f32"), 1
+    # A strong shear: the displacements of a 16 x 16 tile spread over more
+    # than the 24-node LDS box, so later stages take the global path.
+    yield "shear_global_path", shear_workload(64, 4.0, 1.5), 2
+    yield "shear_global_path_f32", shear_workload(64, 4.0, 1.5, value_prec="f32"), 1
 
 
 @pytest.mark.parametrize("name,wl,nsteps", list(_cases()))
