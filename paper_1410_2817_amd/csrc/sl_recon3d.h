@@ -90,6 +90,28 @@ __device__ __forceinline__ T zsum3d(const T* wx, const T* wy, const T* wz, const
   return acc;
 }
 
+// The linear (Z0) sum: only taps 2..3 of each axis carry weight, so this
+// 2 x 2 x 2 sum in the same order equals zsum3d on finite values (each
+// skipped term adds an exact zero).  Taken where a whole wave is at order 0.
+template <typename T, class Val>
+__device__ __forceinline__ T zsum3d_linear(const T* wx, const T* wy, const T* wz,
+                                           const Val& val) {
+  T acc = T(0);
+#pragma unroll
+  for (int kz = 2; kz <= 3; ++kz) {
+    T pl = T(0);
+#pragma unroll
+    for (int ky = 2; ky <= 3; ++ky) {
+      T s = T(0);
+#pragma unroll
+      for (int kx = 2; kx <= 3; ++kx) s = fma(val(kx, ky, kz), wx[kx], s);
+      pl = fma(s, wy[ky], pl);
+    }
+    acc = fma(pl, wz[kz], acc);
+  }
+  return acc;
+}
+
 #ifndef SL_STAGE3D
 #define SL_STAGE3D 1
 #endif
@@ -299,23 +321,26 @@ __global__ __launch_bounds__(kTileThreads, (Box3D<T, NF>::WAVES)) void recon3d_k
       }
       const int fbytes = buf_ok ? g.ntot * (int)sizeof(T) : 0;
       const T t[3] = {(T)xi[0], (T)xi[1], (T)xi[2]};
-      auto field_value = [&](int f, const T* wx, const T* wy, const T* wz) {
+      // linear_c: std::true_type for the 2 x 2 x 2 sum of a wave that is at
+      // order 0 throughout, std::false_type for the full sum.
+      auto field_value = [&](int f, const T* wx, const T* wy, const T* wz, auto linear_c) {
+        const auto sum = [&](const auto& at) {
+          if constexpr (decltype(linear_c)::value) return zsum3d_linear<T>(wx, wy, wz, at);
+          else return zsum3d<T>(wx, wy, wz, at);
+        };
         T v;
         if (inbox) {
           const T* lv = lval + f * X::NB + lbase;
-          v = zsum3d<T>(wx, wy, wz, [&](int kx, int ky, int kz) {
-            return lv[kx + X::PX * (ky + X::BY * kz)];
-          });
+          v = sum([&](int kx, int ky, int kz) { return lv[kx + X::PX * (ky + X::BY * kz)]; });
         } else if (fast) {
           const __amdgpu_buffer_rsrc_t rs = field_rsrc(fp.in[f], fbytes);
-          v = zsum3d<T>(wx, wy, wz, [&](int kx, int ky, int kz) {
+          v = sum([&](int kx, int ky, int kz) {
             return buffer_value<T>(rs, vbase + kx * (int)sizeof(T),
                                    (kz * sz + ky * sy) * (int)sizeof(T));
           });
         } else {
           const T* __restrict__ h = static_cast<const T*>(fp.in[f]);
-          v = zsum3d<T>(wx, wy, wz,
-                        [&](int kx, int ky, int kz) { return h[ix[kx] + iy[ky] + iz[kz]]; });
+          v = sum([&](int kx, int ky, int kz) { return h[ix[kx] + iy[ky] + iz[kz]]; });
         }
         bad += !isfinite(v);
         static_cast<T*>(fp.out[f])[lin] = v;
@@ -335,9 +360,11 @@ __global__ __launch_bounds__(kTileThreads, (Box3D<T, NF>::WAVES)) void recon3d_k
 #pragma unroll
         for (int a = 0; a < 3; ++a) zspline_weights<T>(g.order_max, t[a], w[a]);
 #pragma unroll
-        for (int f = 0; f < nf; ++f) field_value(f, w[0], w[1], w[2]);
+        for (int f = 0; f < nf; ++f) field_value(f, w[0], w[1], w[2], std::false_type{});
       } else {
-        // Some lane of the wave drops an order: weights per field and lane.
+        // Some lane of the wave drops an order: weights per field and lane;
+        // a field the whole wave takes at linear order sums its 8 taps only
+        // (flags cover regions, so this is the usual lowered case).
 #pragma unroll 1
         for (int f = 0; f < nf; ++f) {
           const int m = pick_order(g.order_max, or6, or4, f);
@@ -346,7 +373,10 @@ __global__ __launch_bounds__(kTileThreads, (Box3D<T, NF>::WAVES)) void recon3d_k
           T w[3][6];
 #pragma unroll
           for (int a = 0; a < 3; ++a) zspline_weights<T>(m, t[a], w[a]);
-          field_value(f, w[0], w[1], w[2]);
+          if (__ballot(m != 0) == 0ull)
+            field_value(f, w[0], w[1], w[2], std::true_type{});
+          else
+            field_value(f, w[0], w[1], w[2], std::false_type{});
         }
       }
     }
