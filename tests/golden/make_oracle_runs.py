@@ -34,6 +34,11 @@ def cases():
         "swirl1024_period": (lambda: W.swirl_three_fields(1024, value_prec="f32"), 1280, 0.0),
         "fourier3d256_50": (lambda: W.fourier3d_three_fields(256, value_prec="f32"), 50, 0.0),
         "deform3d512_10": (lambda: W.deform3d_slotted_sphere(512), 10, 0.0),
+        # Shallow-water source terms (the oracle's run_source): the Kelvin
+        # wave to t = 1, linear and non-linear viscous.
+        "kelvin256_t1": (lambda: W.kelvin(256, amp=1e-4, t_end=1.0), 512, 0.0),
+        "kelvin_nonlinear256_t1": (lambda: W.kelvin(256, amp=0.5, nu=5e-4, t_end=1.0), 525, 0.0),
+        "kelvin1024_t1": (lambda: W.kelvin(1024, amp=1e-4, t_end=1.0), 2048, 0.0),
     }
 
 
@@ -59,9 +64,12 @@ def run(name):
     prob = oracle.Problem(wl.shape, wl.nfields, wl.length, order_max=wl.order_max,
                           limiter=wl.limiter, theta=wl.theta, integrator=wl.integrator,
                           vel_kind=wl.velocity.kind, vp=wl.velocity.padded_params(),
-                          modes=wl.velocity.modes)
+                          modes=wl.velocity.modes, src_kind=wl.source, sp=list(wl.sp))
     t = time.time()
-    rc, fields, st = oracle.run(prob, t0, wl.dt, steps, stored(wl))
+    if wl.source:
+        rc, fields, st = oracle.run_source(prob, t0, wl.dt, steps, stored(wl))
+    else:
+        rc, fields, st = oracle.run(prob, t0, wl.dt, steps, stored(wl))
     assert rc == 0, (name, rc, st)
     nodes = sample_nodes(wl)
     values = np.stack([f.ravel()[nodes] for f in fields], axis=1)
