@@ -427,6 +427,25 @@ def other_configs():
                             [np.asarray(f, np.float64) for f in wl.fields])
     res["burgers2d_512_f64"]["l1_rel_vs_oracle_20_steps"] = [
         _l1(g.double().cpu().numpy(), o) for g, o in zip(out20, ofs)]
+    # Gridded velocity: the swirl's velocity sampled on the mesh (at t = 1.25,
+    # held fixed) and interpolated with the Z2 spline at the trajectory
+    # points; 160 steps timed (unfused step: trajectories, then the
+    # reconstruction), and 3 steps against the oracle.
+    wl = W.gridded(W.swirl_three_fields(1024, value_prec="f32"), 2, t=1.25)
+    out, el, prof, st = run_gpu(wl, 160)
+    res["gridded_swirl1024_f32"] = {
+        "node_updates_per_s": wl.nodes * 160 / el, "ms_per_step": el * 1e3 / 160, "steps": 160,
+        "trajectories_avg_ms": prof["traj_ms"] / max(prof["traj_launches"], 1),
+        "reconstruction_avg_ms": prof["recon_ms"] / max(prof["recon_launches"], 1),
+        "search_fail": st["search_fail"]}
+    del out
+    out3, _, _, _ = run_gpu(wl, 3, profile=0, warmup=0)
+    stored3 = [np.asarray(f, np.float32).astype(np.float64) for f in wl.fields]
+    rc, ofs, _ = oracle.run(_oracle_problem(oracle, wl), 0.0, wl.dt, 3, stored3)
+    got = [g.double().cpu().numpy() for g in out3]
+    res["gridded_swirl1024_f32"]["l1_rel_vs_oracle_3_steps"] = (
+        sum(float(np.abs(g - o).sum()) for g, o in zip(got, ofs)) /
+        sum(float(np.abs(o).sum()) for o in ofs))
     res.update(kelvin_configs())
     return res
 
@@ -489,7 +508,8 @@ def _oracle_problem(oracle, wl):
                           limiter=wl.limiter, theta=wl.theta, integrator=wl.integrator,
                           vel_kind=wl.velocity.kind, vp=wl.velocity.padded_params(),
                           modes=wl.velocity.modes, src_kind=getattr(wl, "source", 0),
-                          sp=list(getattr(wl, "sp", (0.0,) * 4)))
+                          sp=list(getattr(wl, "sp", (0.0,) * 4)),
+                          ugrid=getattr(wl, "ugrid", None))
 
 
 def gpu_vs_oracle(wl, stored, steps, ofields):

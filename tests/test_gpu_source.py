@@ -108,6 +108,7 @@ def _cases():
     yield "fplane_passive_f64", sw_workload((48, 64), fc=4.0, beta=0.0, passive=True,
                                             limiter=True), 4
     yield "three_point_rules_z1", sw_workload((40, 56), m=1, nu=2e-3), 3
+    yield "three_point_rules_z0", sw_workload((40, 56), m=0, nu=2e-3, limiter=True), 3
     yield "nonlinear_f32_1step", sw_workload((80, 96), amp=0.5, nu=1e-3, value_prec="f32"), 1
     yield "passive_f32_1step", sw_workload((48, 64), passive=True, limiter=True,
                                            value_prec="f32"), 1
