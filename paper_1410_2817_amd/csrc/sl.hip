@@ -229,6 +229,13 @@ hipError_t launch_traj(sl_grid* gr, double* disp, double t, double dt, int accum
     case SL_VEL_DEFORM3D:
       return launch(sl::traj_kernel<D, SL_VEL_DEFORM3D>, blocks, threads, 0, s, e0, e1, gr->g, gr->v, disp, st, dt, accumulate, integ);
     case SL_VEL_GRIDDED:
+      if constexpr (D == 2) {
+        // Tiles with their velocity samples staged in LDS.
+        const int tx = (gr->g.n[0] + sl::kGridTile - 1) / sl::kGridTile;
+        const int ty = (gr->g.n[1] + sl::kGridTile - 1) / sl::kGridTile;
+        return launch(sl::traj_gridded2d_kernel<2>, dim3(tx * ty), dim3(256), 0, s, e0, e1, gr->g,
+                      gr->v, disp, st, dt, accumulate, integ, tx);
+      }
       return launch(sl::traj_kernel<D, SL_VEL_GRIDDED>, blocks, threads, 0, s, e0, e1, gr->g, gr->v, disp, st, dt, accumulate, integ);
     default:
       return launch(sl::traj_kernel<D, SL_VEL_FOURIER>, blocks, threads, 0, s, e0, e1, gr->g, gr->v, disp, st, dt, accumulate, integ);

@@ -44,12 +44,14 @@ struct StageTimes {
 constexpr int kTrajBX = 64, kTrajBY = 4;
 
 // Trajectory of lattice node idx over one step (or one more step when
-// `accumulate` is set).
-template <int D, int VK>
-__device__ __forceinline__ void traj_node(const GridArgs& g, const VelArgs& v,
-                                          double* __restrict__ disp, const StageTimes& st,
-                                          double dt, int accumulate, int integrator,
-                                          const int* idx) {
+// `accumulate` is set), with the velocity evaluator `vel` (init(x0), then
+// eval(v, x0, delta, tf, u) at x0 + delta).
+template <int D, class Vel>
+__device__ __forceinline__ void traj_node_with(const GridArgs& g, const VelArgs& v, Vel vel,
+                                               double* __restrict__ disp,
+                                               const StageTimes& st, double dt,
+                                               int accumulate, int integrator,
+                                               const int* idx) {
   const int lin = flatten<D>(g, idx);
   double d[D], x[D];
 #pragma unroll
@@ -57,7 +59,6 @@ __device__ __forceinline__ void traj_node(const GridArgs& g, const VelArgs& v,
     d[a] = accumulate ? disp[(size_t)a * g.ntot + lin] : 0.0;
     x[a] = ((double)idx[a] + d[a]) * g.h[a];
   }
-  NodeVelocity<VK, D> vel;
   vel.init(x);
   if (integrator == SL_RK4) {
     double k1[D], k2[D], k3[D], k4[D], o[D];
@@ -97,6 +98,100 @@ __device__ __forceinline__ void traj_node(const GridArgs& g, const VelArgs& v,
   }
 #pragma unroll
   for (int a = 0; a < D; ++a) disp[(size_t)a * g.ntot + lin] = d[a];
+}
+
+template <int D, int VK>
+__device__ __forceinline__ void traj_node(const GridArgs& g, const VelArgs& v,
+                                          double* __restrict__ disp, const StageTimes& st,
+                                          double dt, int accumulate, int integrator,
+                                          const int* idx) {
+  traj_node_with<D>(g, v, NodeVelocity<VK, D>{}, disp, st, dt, accumulate, integrator, idx);
+}
+
+// Gridded velocity in 2-D with the samples around a tile staged in LDS: the
+// same Z-spline sum as velocity<SL_VEL_GRIDDED> (same weights, same order of
+// taps), read from the box [bx0, bx0 + W) x [by0, by0 + W) of mesh nodes
+// (unwrapped coordinates) when the point's window lies in it, else from global
+// memory.
+struct GriddedBox2D {
+  const double* box;  // 2 planes of W x W samples
+  int bx0, by0, W;
+
+  __device__ __forceinline__ void init(const double*) {}
+
+  __device__ __forceinline__ void eval(const VelArgs& v, const double* x0, const double* delta,
+                                       double, double* u) const {
+    int r[2];
+    double w[2][6];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const double xa = delta ? x0[a] + delta[a] : x0[a];
+      const double sa = xa / v.ug_h[a];
+      r[a] = (int)floor(sa);
+      zspline_weights<double>(v.ug_m, sa - (double)r[a], w[a]);
+    }
+    u[0] = u[1] = 0.0;
+    const int lo = 2 - v.ug_m, hi = 3 + v.ug_m;
+    const int ox = r[0] - 2 - bx0, oy = r[1] - 2 - by0;  // window origin in the box
+    const bool in = ox + lo >= 0 && oy + lo >= 0 && ox + hi < W && oy + hi < W;
+    const int nx = v.ug_n[0], ny = v.ug_n[1];
+#pragma unroll
+    for (int ky = 0; ky < 6; ++ky) {
+      if (ky < lo || ky > hi) continue;
+      double sx[2] = {0.0, 0.0};
+      if (in) {
+        const int row = (oy + ky) * W + ox;
+#pragma unroll
+        for (int kx = 0; kx < 6; ++kx) {
+          if (kx < lo || kx > hi) continue;
+#pragma unroll
+          for (int a = 0; a < 2; ++a) sx[a] = fma(box[a * W * W + row + kx], w[0][kx], sx[a]);
+        }
+      } else {
+        const int grow = nx * wrap_index(r[1] - 2 + ky, ny);
+#pragma unroll
+        for (int kx = 0; kx < 6; ++kx) {
+          if (kx < lo || kx > hi) continue;
+          const int lin = grow + wrap_index(r[0] - 2 + kx, nx);
+#pragma unroll
+          for (int a = 0; a < 2; ++a) sx[a] = fma(v.ug[a][lin], w[0][kx], sx[a]);
+        }
+      }
+      // In 2-D the gridded sum's y-z weight is w_y * 1.
+#pragma unroll
+      for (int a = 0; a < 2; ++a) u[a] = fma(sx[a], w[1][ky] * 1.0, u[a]);
+    }
+  }
+};
+
+// Tiles of the 2-D gridded trajectory kernel: 16 x 16 lattice nodes and a box
+// reaching kGridMargin nodes beyond them on every side (stage points up to
+// kGridMargin - 3 cells from their node keep their windows in the box).
+constexpr int kGridTile = 16, kGridMargin = 8, kGridBox = kGridTile + 2 * kGridMargin;
+
+template <int D>
+__global__ __launch_bounds__(256) void traj_gridded2d_kernel(GridArgs g, VelArgs v,
+                                                             double* __restrict__ disp,
+                                                             StageTimes st, double dt,
+                                                             int accumulate, int integrator,
+                                                             int tiles_x) {
+  static_assert(D == 2, "2-D grids only");
+  __shared__ double sbox[2 * kGridBox * kGridBox];
+  const int i0 = (blockIdx.x % tiles_x) * kGridTile, j0 = (blockIdx.x / tiles_x) * kGridTile;
+  const int bx0 = i0 - kGridMargin, by0 = j0 - kGridMargin;
+  const int nx = g.n[0], ny = g.n[1];
+  constexpr int NB = kGridBox * kGridBox;
+  for (int e = threadIdx.x; e < NB; e += 256) {
+    const int gy = e / kGridBox, gx = e - gy * kGridBox;
+    const int lin = wrap_index(by0 + gy, ny) * nx + wrap_index(bx0 + gx, nx);
+    sbox[e] = v.ug[0][lin];
+    sbox[NB + e] = v.ug[1][lin];
+  }
+  __syncthreads();
+  const int idx[2] = {i0 + (int)(threadIdx.x % kGridTile), j0 + (int)(threadIdx.x / kGridTile)};
+  if (idx[0] >= nx || idx[1] >= ny) return;
+  traj_node_with<2>(g, v, GriddedBox2D{sbox, bx0, by0, kGridBox}, disp, st, dt, accumulate,
+                    integrator, idx);
 }
 
 
