@@ -84,6 +84,84 @@ def record_traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, command
     print(json.dumps(rec))
 
 
+# VALU issue: a wave64 VALU instruction holds one of the 1024 SIMDs (256 CUs x
+# 4) for 4 cycles (16 lanes), at 2.4 GHz.  With packed FP32 disabled this is
+# the roof of every kernel here (FP64 and FP32 issue at the same rate).
+VALU_SIMDS, VALU_CYCLES_PER_INST, CLOCK_HZ = 1024, 4, 2.4e9
+VALU_JSON = os.path.join(PROFILES, "valu_counters.json")
+# Workload of each counter directory -> the kernels whose counts are kept.
+VALU_KERNELS = {"swirl_f32": ["recon2d_tiled_kernel<float, 3>"],
+                "fourier3d_f32": ["recon3d_kernel<float, 3>"],
+                "deform3d_f64": ["recon3d_kernel<double, 1>"],
+                "deform3d_f32": ["recon3d_kernel<float, 1>"],
+                "kelvin_f64": ["recon2d_tiled_kernel<double, 3>", "sw_stage_kernel<double, 2>"]}
+
+
+def all_sources_hash() -> str:
+    """Hash of every HIP source and the C header."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1410_2817_amd", "csrc")
+    names = sorted(n for n in os.listdir(csrc) if n.endswith((".h", ".hip")))
+    for rel in ["include/sl.h"] + ["paper_1410_2817_amd/csrc/" + n for n in names]:
+        h.update(rel.encode())
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def record_valu(dirs, command):
+    """Instruction counts per wave (SQ_INSTS_VALU / SQ_WAVES and the SALU, LDS
+    and memory counts) of the kernels in VALU_KERNELS, from rocprofv3 --pmc
+    directories named sqc_<workload>_<prec>."""
+    import csv
+    import collections
+    rec = {"kernels": {}, "source_hash": all_sources_hash(), "command": command}
+    for d in dirs:
+        key = os.path.basename(os.path.normpath(d))[len("sqc_"):]
+        agg = collections.defaultdict(lambda: collections.defaultdict(list))
+        with open(os.path.join(d, "run_counter_collection.csv")) as fh:
+            for row in csv.DictReader(fh):
+                agg[row["Kernel_Name"]][row["Counter_Name"]].append(float(row["Counter_Value"]))
+        for want in VALU_KERNELS.get(key, []):
+            for name, c in agg.items():
+                if want in name:
+                    m = {n: sum(v) / len(v) for n, v in c.items()}
+                    waves = m["SQ_WAVES"]
+                    rec["kernels"]["%s/%s" % (key, want)] = {
+                        "waves_per_dispatch": waves,
+                        "valu_per_wave": m["SQ_INSTS_VALU"] / waves,
+                        "salu_per_wave": m["SQ_INSTS_SALU"] / waves,
+                        "lds_per_wave": m["SQ_INSTS_LDS"] / waves,
+                        "vmem_rd_per_wave": m["SQ_INSTS_VMEM_RD"] / waves,
+                        "vmem_wr_per_wave": m["SQ_INSTS_VMEM_WR"] / waves,
+                        "dispatches": len(c["SQ_WAVES"])}
+    os.makedirs(PROFILES, exist_ok=True)
+    with open(VALU_JSON, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(json.dumps(rec))
+
+
+def valu_roof(key, avg_ms):
+    """VALU issue roof of a kernel from its recorded instruction count and its
+    live average duration: the fraction of the SIMDs' issue cycles its VALU
+    instructions fill.  None when the record is missing or stale."""
+    try:
+        with open(VALU_JSON) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    k = rec.get("kernels", {}).get(key)
+    if k is None or rec.get("source_hash") != all_sources_hash() or not avg_ms:
+        return None
+    inst = k["valu_per_wave"] * k["waves_per_dispatch"]
+    achieved = inst / (avg_ms * 1e-3)  # wave-instructions per second
+    peak = VALU_SIMDS * CLOCK_HZ / VALU_CYCLES_PER_INST
+    return {"bound": "alu", "unit": "wave64 VALU instructions/s", "achieved": achieved,
+            "peak": peak, "frac": achieved / peak, "valu_per_wave": k["valu_per_wave"],
+            "waves": k["waves_per_dispatch"]}
+
+
 def recorded_traffic():
     """Traffic bytes per reconstruction launch from the committed counter
     record, or None when the kernel sources changed since it was taken."""
@@ -143,6 +221,9 @@ def parse():
                     help="write the traffic record from rocprofv3 --pmc output directories: "
                          "FETCH, WRITE, copy FETCH, copy WRITE")
     ap.add_argument("--record-command", default="", help="command line stored in the record")
+    ap.add_argument("--record-valu", nargs="+", metavar="DIR",
+                    help="write the VALU instruction record from rocprofv3 --pmc SQ counter "
+                         "directories named sqc_<workload>_<prec>")
     return ap.parse_args()
 
 
@@ -169,6 +250,9 @@ def main():
         return
     if args.record_traffic:
         record_traffic(*args.record_traffic, command=args.record_command)
+        return
+    if args.record_valu:
+        record_valu(args.record_valu, command=args.record_command)
         return
     import torch
 
@@ -282,6 +366,12 @@ def main():
             "bytes_per_node": per_node, "avg_ms": recon_ms,
             "launches": prof["recon_launches"],
         },
+        "valu_roof": valu_roof({("swirl", 1024, "f32"): "swirl_f32/recon2d_tiled_kernel<float, 3>",
+                                ("fourier3d", 256, "f32"): "fourier3d_f32/recon3d_kernel<float, 3>",
+                                ("deform3d", 512, "f64"): "deform3d_f64/recon3d_kernel<double, 1>",
+                                ("deform3d", 512, "f32"): "deform3d_f32/recon3d_kernel<float, 1>",
+                                ("kelvin", 1024, "f64"): "kelvin_f64/recon2d_tiled_kernel<double, 3>"}
+                               .get((args.workload, args.n, args.prec), ""), recon_ms),
         "field_node_updates_per_s": value * wl.nfields,
         "kernels": {"trajectories_avg_ms": traj_ms, "reconstruction_avg_ms": recon_ms,
                     "order_words_avg_ms": orders_ms, "source_kernels_avg_ms": source_ms,
@@ -404,6 +494,10 @@ def other_configs():
                      "trajectories_avg_ms": prof["traj_ms"] / max(prof["traj_launches"], 1),
                      "order_words_avg_ms": prof["orders_ms"] / max(prof["orders_launches"], 1),
                      "hbm_achieved_gbs": ach, "hbm_frac": ach / HBM_PEAK_GBS,
+                     "valu_roof": valu_roof({"fourier3d_256_f32": "fourier3d_f32/recon3d_kernel<float, 3>",
+                                             "deform3d_512_f64": "deform3d_f64/recon3d_kernel<double, 1>",
+                                             "deform3d_512_f32": "deform3d_f32/recon3d_kernel<float, 1>"}
+                                            .get(name, ""), rms),
                      "order_hist": st["order_hist"], "walked": st["walked"]}
         if name.startswith("deform3d"):
             keep[prec] = out[0].double().cpu().numpy()
@@ -416,8 +510,13 @@ def other_configs():
     # oracle.
     wl = W.burgers(512)
     out, el, prof, st = run_gpu(wl, wl.nsteps)
+    brms = prof["recon_ms"] / max(prof["recon_launches"], 1)
+    # Each launch reconstructs 2 FP64 fields and writes the next displacement.
+    bgbs = (recon_bytes_per_node(2, 2, 8) + traj_bytes_per_node(2)) * wl.nodes / (brms * 1e-3) / 1e9
     res["burgers2d_512_f64"] = {"node_updates_per_s": wl.nodes * wl.nsteps / el,
                                 "ms_per_step": el * 1e3 / wl.nsteps, "steps": wl.nsteps,
+                                "reconstruction_avg_ms": brms,
+                                "reconstruction_hbm_gbs": bgbs, "hbm_frac": bgbs / HBM_PEAK_GBS,
                                 "t_end": wl.nsteps * wl.dt, "search_fail": st["search_fail"],
                                 "order_hist": st["order_hist"],
                                 "max_speed": float(max(np.abs(f.double().cpu().numpy()).max()
@@ -433,10 +532,18 @@ def other_configs():
     # reconstruction), and 3 steps against the oracle.
     wl = W.gridded(W.swirl_three_fields(1024, value_prec="f32"), 2, t=1.25)
     out, el, prof, st = run_gpu(wl, 160)
+    grms = prof["recon_ms"] / max(prof["recon_launches"], 1)
+    gtms = prof["traj_ms"] / max(prof["traj_launches"], 1)
+    # Unfused step: the reconstruction reads the displacement and the values and
+    # writes the values; the trajectories read the two velocity samples of
+    # their node's window once (the rest comes from LDS) and write the
+    # displacement.
+    g_rec = recon_bytes_per_node(2, 3, 4) * wl.nodes / (grms * 1e-3) / 1e9
+    g_trj = (16 + traj_bytes_per_node(2)) * wl.nodes / (gtms * 1e-3) / 1e9
     res["gridded_swirl1024_f32"] = {
         "node_updates_per_s": wl.nodes * 160 / el, "ms_per_step": el * 1e3 / 160, "steps": 160,
-        "trajectories_avg_ms": prof["traj_ms"] / max(prof["traj_launches"], 1),
-        "reconstruction_avg_ms": prof["recon_ms"] / max(prof["recon_launches"], 1),
+        "trajectories_avg_ms": gtms, "reconstruction_avg_ms": grms,
+        "reconstruction_hbm_gbs": g_rec, "trajectories_hbm_gbs": g_trj,
         "search_fail": st["search_fail"]}
     del out
     out3, _, _, _ = run_gpu(wl, 3, profile=0, warmup=0)
@@ -472,11 +579,21 @@ def kelvin_configs():
             rows.append({"n": n, "steps": wl.nsteps, "l2_rel_vs_exact": err})
             if n == 1024 and amp == 1e-4:
                 rl, sl = max(prof["recon_launches"], 1), max(prof["source_launches"], 1)
+                krms, ksms = prof["recon_ms"] / rl, prof["source_ms"] / sl
+                # Reconstruction: 3 FP64 fields, no trajectories (64 B/node).
+                # Stage kernel, averaged over its three stages: 104 B (stage
+                # 0), 184 B (stage 1), 144 B (stage 2, no registers written).
+                k_rec = recon_bytes_per_node(2, 3, 8) * wl.nodes / (krms * 1e-3) / 1e9
+                k_stg = (104 + 184 + 144) / 3.0 * wl.nodes / (ksms * 1e-3) / 1e9
                 res["kelvin_1024_f64"] = {
                     "node_updates_per_s": wl.nodes * wl.nsteps / el,
                     "ms_per_step": el * 1e3 / wl.nsteps, "steps": wl.nsteps,
-                    "reconstruction_avg_ms": prof["recon_ms"] / rl,
-                    "source_kernel_avg_ms": prof["source_ms"] / sl,
+                    "reconstruction_avg_ms": krms,
+                    "source_kernel_avg_ms": ksms,
+                    "reconstruction_hbm_gbs": k_rec, "stage_hbm_gbs": k_stg,
+                    "valu_roof_reconstruction": valu_roof(
+                        "kelvin_f64/recon2d_tiled_kernel<double, 3>", krms),
+                    "valu_roof_stage": valu_roof("kelvin_f64/sw_stage_kernel<double, 2>", ksms),
                     "reconstructions_per_step": 3, "source_launches_per_step": 6,
                     "search_fail": st["search_fail"], "l2_rel_vs_exact_t1": err}
             del out
