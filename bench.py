@@ -658,9 +658,17 @@ def run_serving(count: int, budget_gib: float):
                        max_requests=256)
     keep = ("latency_p50_ms", "latency_p99_ms", "latency_mean_ms", "queue_wait_p50_ms",
             "queue_wait_p99_ms", "node_updates_per_s", "makespan_s", "ticks", "status")
+    # Whole-job effective HBM rate of the capacity run: the algorithmic bytes of
+    # every step of every request (FP32 values; each reconstruction also writes
+    # the next step's displacement) over the makespan, all launches and gaps
+    # included.
+    alg = sum(r.nodes * r.nsteps * (recon_bytes_per_node(2, r.nfields, 4) + traj_bytes_per_node(2))
+              for r in burst)
+    eff = alg / cap["makespan_s"] / 1e9
     return {"requests": count, "budget_gib": budget_gib,
             "capacity_node_updates_per_s": cap["node_updates_per_s"],
             "capacity_requests_per_s": count / cap["makespan_s"],
+            "capacity_effective_hbm_gbs": eff, "capacity_effective_hbm_frac": eff / HBM_PEAK_GBS,
             "poisson_rate_per_s": rate, **{k: rep[k] for k in keep}}
 
 
