@@ -604,13 +604,25 @@ def kelvin_configs():
     res["kelvin_convergence_amp1e-4_f64"] = ladder(1e-4, (32, 64, 128, 256))
     res["kelvin_convergence_amp1e-7_f64"] = ladder(1e-7, (64, 128, 256, 512, 1024))
     ladder(1e-4, (1024,))
-    wl = W.kelvin(1024, amp=0.5, nu=5e-4, t_end=1.0)
-    out, el, prof, st = run_gpu(wl, wl.nsteps)
-    res["kelvin_nonlinear_1024_f64"] = {
-        "node_updates_per_s": wl.nodes * wl.nsteps / el, "ms_per_step": el * 1e3 / wl.nsteps,
-        "steps": wl.nsteps, "search_fail": st["search_fail"], "walked": st["walked"],
-        "max_h": float(out[2].double().abs().max().item())}
-    del out
+    # Non-linear viscous run (Sec. 3, the Kelvin-Poincare dispersion of the
+    # paper's figure): timed at 1024^2, and its self-convergence at t = 1 from
+    # 256^2, 512^2 and 1024^2 (coarse node i is fine node 2i).
+    hs = {}
+    for n in (256, 512, 1024):
+        wl = W.kelvin(n, amp=0.5, nu=5e-4, t_end=1.0)
+        out, el, prof, st = run_gpu(wl, wl.nsteps, warmup=0 if n < 1024 else 2)
+        hs[n] = out[2].double().cpu().numpy()
+        if n == 1024:
+            res["kelvin_nonlinear_1024_f64"] = {
+                "node_updates_per_s": wl.nodes * wl.nsteps / el,
+                "ms_per_step": el * 1e3 / wl.nsteps, "steps": wl.nsteps,
+                "search_fail": st["search_fail"], "walked": st["walked"],
+                "max_h": float(out[2].double().abs().max().item())}
+        del out
+    d1 = float(np.abs(hs[512][::2, ::2] - hs[256]).sum() / np.abs(hs[256]).sum())
+    d2 = float(np.abs(hs[1024][::2, ::2] - hs[512]).sum() / np.abs(hs[512]).sum())
+    res["kelvin_nonlinear_1024_f64"]["self_convergence_t1"] = {
+        "l1_rel_512_vs_256": d1, "l1_rel_1024_vs_512": d2, "order": float(np.log2(d1 / d2))}
     wl = W.kelvin(256, amp=0.5, nu=5e-4, t_end=1.0)
     out, _, _, _ = run_gpu(wl, 8, profile=0, warmup=0)
     rc, ofs, _ = oracle.run_source(_oracle_problem(oracle, wl), 0.0, wl.dt, 8,
