@@ -526,6 +526,20 @@ def other_configs():
                             [np.asarray(f, np.float64) for f in wl.fields])
     res["burgers2d_512_f64"]["l1_rel_vs_oracle_20_steps"] = [
         _l1(g.double().cpu().numpy(), o) for g, o in zip(out20, ofs)]
+    # Self-convergence at t = 0.3 (the shock has formed): 256^2, 512^2, 1024^2
+    # compared at the shared nodes (coarse node i is fine node 2i).
+    us = {}
+    for n in (256, 512, 1024):
+        wln = W.burgers(n)
+        o, _, _, _ = run_gpu(wln, wln.nsteps, profile=0, warmup=0)
+        us[n] = [f.double().cpu().numpy() for f in o]
+        del o
+    def _d(a, b):
+        return (sum(float(np.abs(x[::2, ::2] - y).sum()) for x, y in zip(us[a], us[b])) /
+                sum(float(np.abs(y).sum()) for y in us[b]))
+    d1, d2 = _d(512, 256), _d(1024, 512)
+    res["burgers2d_512_f64"]["self_convergence_t03"] = {
+        "l1_rel_512_vs_256": d1, "l1_rel_1024_vs_512": d2, "order": float(np.log2(d1 / d2))}
     # Gridded velocity: the swirl's velocity sampled on the mesh (at t = 1.25,
     # held fixed) and interpolated with the Z2 spline at the trajectory
     # points; 160 steps timed (unfused step: trajectories, then the

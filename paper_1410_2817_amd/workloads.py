@@ -252,16 +252,16 @@ def burgers(n: int = 256, dim: int = 2, t_end: float = 0.3, cfl: float = 0.5,
     paper's shock test (Sec. 3): u = exp(-150 (r - 0.2)^2) (x - c) / r for
     r = |x - c| > 0.001 (c the box centre), 0 otherwise; the velocity is
     carried by the fields (fields 0..dim-1), limiter on, Z2.  Max speed 1, so
-    dt = cfl h; the run covers t_end."""
+    the step is at most cfl h; the run ends at t_end exactly."""
     shape = (n,) * dim
     X = _xyz(shape)
     rel = [X[a] - 0.5 for a in range(dim)]
     r = np.sqrt(sum(q * q for q in rel))
     amp = np.where(r > 0.001, np.exp(-150.0 * (r - 0.2) ** 2) / np.maximum(r, 1e-300), 0.0)
     fs = [np.broadcast_to(amp * rel[a], shape).astype(np.float64).copy() for a in range(dim)]
-    dt = cfl / n
+    nsteps = int(math.ceil(t_end * n / cfl - 1e-9))
     return Workload("burgers%dd_%d_%s" % (dim, n, value_prec), shape, (1.0,) * dim, fs,
-                    Velocity(VEL_CARRIED), dt=dt, nsteps=int(round(t_end / dt)),
+                    Velocity(VEL_CARRIED), dt=t_end / nsteps, nsteps=nsteps,
                     order_max=2, limiter=True, value_prec=value_prec)
 
 
