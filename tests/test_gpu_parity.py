@@ -392,6 +392,9 @@ def test_2d_limiter_paths_agree_bitwise(B, torch, name, wl, monkeypatch):
 @pytest.mark.parametrize("name,wl", [
     ("swirl", W.swirl_three_fields(64, value_prec="f64")),
     ("burgers", W.burgers(64)),
+    # The second lattice step starts ~4 cells out, so its stage points leave
+    # the gridded kernel's LDS box and take its global path.
+    ("gridded", W.gridded(W.swirl_three_fields(64, value_prec="f64"), 2, t=0.7)),
 ])
 def test_reconstruct_every_two_steps_carried_and_prescribed(B, torch, orc, name, wl):
     """Two lattice steps per reconstruction (K = 2): prescribed velocities
