@@ -504,6 +504,7 @@ def other_configs():
         del out
     # Split form against plain FP64 after the same 60 steps.
     res["deform3d_512_f32"]["l1_rel_vs_f64_plain"] = _l1(keep["f32"], keep["f64"])
+    res["deform3d_512_f64_shard"] = shard_config(W.deform3d_slotted_sphere(512), 60)
 
     # Burgers' equation (velocity carried by the fields), the paper's radial
     # shock test at 512^2 up to t = 0.3, plus its first 20 steps against the
@@ -569,6 +570,49 @@ def other_configs():
         sum(float(np.abs(o).sum()) for o in ofs))
     res.update(kelvin_configs())
     return res
+
+
+def shard_config(wl, nsteps, parts=8, halo=8):
+    """One GPU's share of `wl` split into `parts` slabs along the slowest axis:
+    the owned planes plus `halo` planes on each side, as a grid whose node 0 sits
+    at the slab's place in the whole lattice (offset).  Timing only: with one
+    GPU no halo exchange runs, so after the first step the halo holds stale
+    values (and its outermost nodes, which search across the shard's own
+    periodic seam, may report failed searches: `status`); node-updates/s
+    counts the owned nodes."""
+    import torch
+    from paper_1410_2817_amd import binding as B
+    own = wl.shape[0] // parts
+    lo = (parts // 2) * own
+    shape = list(wl.shape)
+    shape[0] = own + 2 * halo
+    length = list(wl.length)
+    length[0] = wl.length[0] * shape[0] / wl.shape[0]
+    off = [lo - halo] + [0] * (wl.dim - 1)
+    g = B.Grid(shape, wl.nfields, length=length, value_prec=wl.value_prec,
+               order_max=wl.order_max, limiter=wl.limiter, theta=wl.theta,
+               integrator=wl.integrator, vel_kind=wl.velocity.kind,
+               vel_params=wl.velocity.padded_params(), modes=wl.velocity.modes, offset=off)
+    init = [np.ascontiguousarray(f[lo - halo:lo + own + halo]) for f in wl.fields]
+    g.advance(g.new_fields(init), 0.0, wl.dt, 2)
+    torch.cuda.synchronize()
+    x = g.new_fields(init)
+    g.profile(4)
+    g.profile_read()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    g.advance(x, 0.0, wl.dt, nsteps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t1
+    prof = g.profile_read()
+    g.profile(0)
+    rc, st = g.sync()
+    owned = own * int(np.prod(wl.shape[1:]))
+    return {"share": "%d of %d slabs: %s owned + %d halo planes per side" % (
+                1, parts, "x".join(str(v) for v in [own] + list(wl.shape[1:])), halo),
+            "owned_node_updates_per_s": owned * nsteps / el, "ms_per_step": el * 1e3 / nsteps,
+            "steps": nsteps, "reconstruction_avg_ms": prof["recon_ms"] / max(prof["recon_launches"], 1),
+            "halo_overhead": shape[0] / own, "status": rc}
 
 
 def kelvin_configs():

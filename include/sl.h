@@ -166,6 +166,14 @@ typedef struct sl_grid_desc {
   double eps_inside;      /* slack on the unit cube when accepting, 1e-12 */
   int source;             /* SL_SRC_NONE or SL_SRC_SHALLOW_WATER */
   double source_p[4];     /* source parameters, see SL_SRC_SHALLOW_WATER */
+  int64_t offset[3];      /* index of node 0 in a larger periodic lattice (a shard of
+                           * it; x first, default 0): trajectories are integrated at
+                           * x_i = (i + offset) * h, so a shard's lattice moves exactly
+                           * as the same nodes of the whole grid.  Its field arrays
+                           * still wrap at n[a]: only nodes whose stencils stay clear
+                           * of the shard's edges (a halo of at least the largest
+                           * displacement plus 4 nodes) match the whole grid.  Not
+                           * with SL_VEL_GRIDDED or a source term; |offset| < 2^30. */
 } sl_grid_desc;
 
 /* Counters accumulated on the device since the last sl_sync. */

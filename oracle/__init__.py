@@ -52,6 +52,7 @@ class _Problem(C.Structure):
         ("scan_radius", C.c_int),
         ("ugrid", C.POINTER(C.c_double) * 3),
         ("src_kind", C.c_int), ("sp", C.c_double * 4),
+        ("offset", C.c_int64 * 3),
     ]
 
 
@@ -149,6 +150,8 @@ class Problem:
     # y0, nu); fields are u1, u2, h (x-first velocity), then passive ones.
     src_kind: int = SRC_NONE
     sp: Sequence[float] = field(default_factory=lambda: [0.0] * 4)
+    # Index of node 0 in a larger lattice (array order, like shape).
+    offset: Sequence[int] | None = None
 
     @property
     def dim(self) -> int:
@@ -184,6 +187,9 @@ class Problem:
         p.walk_max = self.walk_max
         p.eps_inside = self.eps_inside
         p.scan_radius = self.scan_radius
+        if self.offset is not None:
+            for a in range(self.dim):
+                p.offset[a] = int(self.offset[self.dim - 1 - a])
         p.src_kind = int(self.src_kind)
         spv = list(self.sp) + [0.0] * (4 - len(self.sp))
         for i in range(4):

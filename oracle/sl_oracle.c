@@ -84,6 +84,8 @@ typedef struct {
                            * CARRIED: set internally to the fields at reset */
   int src_kind;         /* ORC_SRC_*: right-hand side S_i of eq. "momento" */
   double sp[4];         /* SHALLOW_WATER: fc, beta, y0, nu (see orc_source_mesh) */
+  int64_t offset[3];    /* index of node 0 in a larger lattice (a shard): the
+                         * trajectory of node i starts at (i + offset) h */
 } orc_problem;
 
 typedef struct {
@@ -266,7 +268,7 @@ void orc_trajectory(const orc_problem *P, const int64_t *node, double t,
   double k1[3], k2[3], k3[3], k4[3];
   for (int a = 0; a < d; ++a) {
     h[a] = P->len[a] / (double)P->n[a];
-    x[a] = ((double)node[a] + disp[a]) * h[a];
+    x[a] = ((double)(node[a] + P->offset[a]) + disp[a]) * h[a];
   }
   if (P->vel_kind == ORC_VEL_CARRIED) {
     /* Du/Dt = 0: the node's own velocity (its field values at the reset,

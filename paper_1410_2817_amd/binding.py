@@ -39,6 +39,7 @@ class SlGridDesc(C.Structure):
         ("newton_max_iter", C.c_int), ("newton_tol", C.c_double),
         ("walk_max", C.c_int), ("scan_radius", C.c_int), ("eps_inside", C.c_double),
         ("source", C.c_int), ("source_p", C.c_double * 4),
+        ("offset", C.c_int64 * 3),
     ]
 
 
@@ -155,7 +156,7 @@ def make_desc(shape: Sequence[int], nfields: int, *, length=None, value_prec="f6
               order_max=2, limiter=False, theta=0.25, integrator=SL_RK4,
               reconstruct_every=1, vel_kind=0, vel_params=None, modes=None,
               newton_max_iter=20, newton_tol=1e-14, walk_max=32, scan_radius=4,
-              eps_inside=1e-12, source=SL_SRC_NONE, source_p=None):
+              eps_inside=1e-12, source=SL_SRC_NONE, source_p=None, offset=None):
     """Descriptor for a grid whose arrays have `shape` (array order, x last)."""
     d = SlGridDesc()
     load().sl_grid_desc_init(C.byref(d))
@@ -186,6 +187,9 @@ def make_desc(shape: Sequence[int], nfields: int, *, length=None, value_prec="f6
     d.walk_max = int(walk_max)
     d.scan_radius = int(scan_radius)
     d.eps_inside = float(eps_inside)
+    if offset is not None:  # array order, like shape
+        for a in range(dim):
+            d.offset[a] = int(offset[dim - 1 - a])
     d.source = int(source)
     sp = list(source_p or []) + [0.0] * 4
     for i in range(4):

@@ -160,6 +160,15 @@ int check_desc(const sl_grid_desc* d) {
   }
   for (int c = 0; c < 8; ++c)
     if (!isfinite(v.p[c])) return SL_EINVAL;
+  bool shard = false;
+  for (int a = 0; a < d->dim; ++a) {
+    if (d->offset[a] <= -(int64_t(1) << 30) || d->offset[a] >= (int64_t(1) << 30))
+      return SL_EINVAL;
+    shard = shard || d->offset[a] != 0;
+  }
+  // Gridded samples and the source term's Coriolis parameter are indexed by
+  // this grid's own nodes.
+  if (shard && (v.kind == SL_VEL_GRIDDED || d->source != SL_SRC_NONE)) return SL_EINVAL;
   if (d->source != SL_SRC_NONE) {
     if (d->source != SL_SRC_SHALLOW_WATER) return SL_EINVAL;
     if (d->dim != 2 || v.kind != SL_VEL_CARRIED || d->nfields < 3) return SL_EINVAL;
@@ -402,6 +411,7 @@ int sl_create_grid(const sl_grid_desc* desc, sl_grid** out) {
   for (int a = 0; a < 3; ++a) {
     g.n[a] = a < D ? (int)desc->n[a] : 1;
     g.h[a] = a < D ? desc->length[a] / (double)desc->n[a] : 1.0;
+    g.off[a] = a < D ? (int)desc->offset[a] : 0;
     if (a < D) gr->ntot *= desc->n[a];
   }
   g.ntot = (int)gr->ntot;

@@ -28,6 +28,7 @@ struct GridArgs {
   int walk_max;
   int scan_radius;
   double eps;
+  int off[3];  // index of node 0 in the whole lattice (a shard); 0 otherwise
 };
 
 // Fourier mode q: theta/pi = c[0] x + c[1] y + c[2] z + phase/pi, and the mode

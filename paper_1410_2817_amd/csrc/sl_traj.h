@@ -57,7 +57,7 @@ __device__ __forceinline__ void traj_node_with(const GridArgs& g, const VelArgs&
 #pragma unroll
   for (int a = 0; a < D; ++a) {
     d[a] = accumulate ? disp[(size_t)a * g.ntot + lin] : 0.0;
-    x[a] = ((double)idx[a] + d[a]) * g.h[a];
+    x[a] = ((double)(idx[a] + g.off[a]) + d[a]) * g.h[a];
   }
   vel.init(x);
   if (integrator == SL_RK4) {
