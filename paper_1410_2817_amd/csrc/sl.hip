@@ -38,8 +38,8 @@
 namespace sl {
 
 __global__ void zero_kernel(unsigned long long* p, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = 0ull;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    p[i] = 0ull;
 }
 
 }  // namespace sl
@@ -52,7 +52,7 @@ __global__ void zero_kernel(unsigned long long* p, int n) {
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr size_t kStatsBytes = 256;
+constexpr size_t kStatsBytes = sizeof(unsigned long long) * sl::kStatWords;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -680,16 +680,17 @@ int sl_reconstruct(sl_grid* gr, void* workspace, const void* const* fields_in,
 int sl_sync(sl_grid* gr, void* workspace, void* stream, sl_stats* out) {
   if (!gr || !workspace) return SL_EINVAL;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  unsigned long long host[sl::ST_COUNT];
+  unsigned long long copies[sl::kStatWords], host[sl::ST_COUNT];
   auto* dev = reinterpret_cast<unsigned long long*>(static_cast<char*>(workspace) + gr->off_stats);
   clear_stale_error();
-  int rc = hip_status(hipMemcpyAsync(host, dev, sizeof(host), hipMemcpyDeviceToHost, s));
+  int rc = hip_status(hipMemcpyAsync(copies, dev, sizeof(copies), hipMemcpyDeviceToHost, s));
   if (rc != SL_OK) return rc;
-  sl::zero_kernel<<<1, 64, 0, s>>>(dev, sl::ST_COUNT);
+  sl::zero_kernel<<<4, 256, 0, s>>>(dev, sl::kStatWords);
   rc = hip_status(hipGetLastError());
   if (rc != SL_OK) return rc;
   rc = hip_status(hipStreamSynchronize(s));
   if (rc != SL_OK) return rc;
+  sl::stat_totals(copies, host);
   const int64_t recs = gr->reconstructs_launched;
   const int64_t nodes = recs * gr->ntot;
   if (out) {

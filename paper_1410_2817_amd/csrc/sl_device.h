@@ -72,6 +72,28 @@ enum StatSlot {
   ST_COUNT
 };
 
+// The counter block holds kStatCopies copies of the ST_COUNT counters, each
+// on a 128-byte line of its own.  A workgroup adds its sums into copy
+// blockIdx % kStatCopies: one copy per workgroup and counter would otherwise
+// queue every workgroup's atomics on one L2 line.  Consecutive workgroups go
+// to the 8 XCDs in turn, so each copy is only touched from one XCD.  The host
+// adds the copies up when it reads the counters.
+constexpr int kStatCopies = 64;
+constexpr int kStatStride = 16;  // counters per copy: one 128-byte line
+constexpr int kStatWords = kStatCopies * kStatStride;
+static_assert(ST_COUNT <= kStatStride, "counter copy overflows its line");
+
+__device__ __forceinline__ unsigned long long* stat_copy(unsigned long long* stats) {
+  return stats + (blockIdx.x % kStatCopies) * kStatStride;
+}
+
+// Host: the totals of the copies (copies: kStatWords words, out: ST_COUNT).
+inline void stat_totals(const unsigned long long* copies, unsigned long long* out) {
+  for (int k = 0; k < ST_COUNT; ++k) out[k] = 0ull;
+  for (int c = 0; c < kStatCopies; ++c)
+    for (int k = 0; k < ST_COUNT; ++k) out[k] += copies[c * kStatStride + k];
+}
+
 __device__ __forceinline__ int wrap_index(int i, int n) {
   int r = i % n;
   return r < 0 ? r + n : r;

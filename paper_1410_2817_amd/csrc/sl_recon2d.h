@@ -526,7 +526,7 @@ __device__ __forceinline__ void recon2d_tile(const GridArgs& g, const FieldPtrs&
   }
   __syncthreads();
   if (threadIdx.x < ST_COUNT && s_cnt[threadIdx.x])
-    atomicAdd(stats + threadIdx.x, (unsigned long long)s_cnt[threadIdx.x]);
+    atomicAdd(stat_copy(stats) + threadIdx.x, (unsigned long long)s_cnt[threadIdx.x]);
 }
 
 template <typename T, int NF>

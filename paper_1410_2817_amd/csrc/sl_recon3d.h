@@ -398,7 +398,7 @@ __global__ __launch_bounds__(kTileThreads, (Box3D<T, NF>::WAVES)) void recon3d_k
   }
   __syncthreads();
   if (threadIdx.x < ST_COUNT && s_cnt[threadIdx.x])
-    atomicAdd(stats + threadIdx.x, (unsigned long long)s_cnt[threadIdx.x]);
+    atomicAdd(stat_copy(stats) + threadIdx.x, (unsigned long long)s_cnt[threadIdx.x]);
 }
 
 }  // namespace sl

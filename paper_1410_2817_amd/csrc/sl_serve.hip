@@ -307,7 +307,7 @@ int sl_server_create(void* arena, size_t arena_bytes, int max_requests, int max_
       max_inflight < 1)
     return SL_EINVAL;
   const size_t table_bytes = align_up(sizeof(sl::ReqStatic) * (size_t)max_requests);
-  const size_t stats_bytes = align_up(sizeof(unsigned long long) * sl::ST_COUNT);
+  const size_t stats_bytes = align_up(sizeof(unsigned long long) * sl::kStatWords);
   if (arena_bytes < table_bytes + stats_bytes + kAlign) return SL_EINVAL;
   sl_server* s = new (std::nothrow) sl_server();
   if (!s) return SL_ENOMEM;
@@ -328,7 +328,7 @@ int sl_server_create(void* arena, size_t arena_bytes, int max_requests, int max_
   s->in_use = 0;
   // Counters start at zero.
   const int rc =
-      hipMemsetAsync(s->stats, 0, sizeof(unsigned long long) * sl::ST_COUNT, s->stream) ==
+      hipMemsetAsync(s->stats, 0, sizeof(unsigned long long) * sl::kStatWords, s->stream) ==
               hipSuccess
           ? SL_OK
           : SL_EHIP;
@@ -562,12 +562,13 @@ int sl_server_fetch(sl_server* s, int64_t id, void* const* fields_out) {
 
 int sl_server_sync(sl_server* s, sl_stats* out) {
   if (!s) return SL_EINVAL;
-  unsigned long long host[sl::ST_COUNT];
-  if (hipMemcpyAsync(host, s->stats, sizeof(host), hipMemcpyDeviceToHost, s->stream) !=
+  unsigned long long copies[sl::kStatWords], host[sl::ST_COUNT];
+  if (hipMemcpyAsync(copies, s->stats, sizeof(copies), hipMemcpyDeviceToHost, s->stream) !=
           hipSuccess ||
-      hipMemsetAsync(s->stats, 0, sizeof(host), s->stream) != hipSuccess ||
+      hipMemsetAsync(s->stats, 0, sizeof(copies), s->stream) != hipSuccess ||
       hipStreamSynchronize(s->stream) != hipSuccess)
     return SL_EHIP;
+  sl::stat_totals(copies, host);
   drain_events(s, true, 0);
   if (out) {
     memset(out, 0, sizeof(*out));

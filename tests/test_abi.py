@@ -57,7 +57,8 @@ def test_create_and_workspace_size(lib):
     n = 40 * 48
     # counters + FP64 displacement (2 components) + one flag byte per node
     assert ws >= 2 * 8 * n + n and ws % 256 == 0
-    assert lib.sl_displacement(h, C.c_void_p(1 << 20), 0) == (1 << 20) + 256
+    # the displacement follows the counter block (64 copies of 16 counters)
+    assert lib.sl_displacement(h, C.c_void_p(1 << 20), 0) == (1 << 20) + 64 * 16 * 8
     assert lib.sl_displacement(h, C.c_void_p(1 << 20), 2) is None
     assert lib.sl_destroy_grid(h) == B.SL_OK
     assert lib.sl_destroy_grid(None) == B.SL_OK
