@@ -31,18 +31,37 @@ struct GridArgs {
   int off[3];  // index of node 0 in the whole lattice (a shard); 0 otherwise
 };
 
-// Fourier mode q: theta/pi = c[0] x + c[1] y + c[2] z + phase/pi, and the mode
-// adds amp * cos(theta) to the velocity.
+// Fourier mode q adds amp * cos(theta) to the velocity, theta = pi k . y +
+// phase with y_a = 2 x_a / L_a.  Two encodings, one per grid
+// (VelArgs::small_k):
+//   gen: any wave vector; theta / pi = phase / pi + c . x (c_a = 2 k_a / L_a),
+//        one cospi per mode and point;
+//   ik:  2-D integer wave vectors with |k_a| <= kSmallK; e^{i theta} = e^{i phase}
+//        prod_a (e^{i pi y_a})^{k_a}, from e^{i pi y_a}, which all modes share
+//        (sum_a |k_a| complex products per mode instead of a cosine).
+constexpr int kSmallK = 4;
+
 struct Mode {
-  double c[3];
   double amp[3];
-  double phase_over_pi;
+  union {
+    struct {
+      double c[3];
+      double phase_over_pi;
+    } gen;
+    struct {
+      double cphi, sphi;  // cos and sin of the phase
+      int k[3];
+      int unused;
+    } ik;
+  };
   double pad;
 };
 
 struct VelArgs {
   int kind;
   int nmodes;
+  int small_k;        // SL_VEL_FOURIER: modes in the ik encoding
+  double kscale[3];   // SL_VEL_FOURIER: 2 / L_a (y_a = kscale_a x_a)
   double p[8];
   Mode mode[SL_MAX_MODES];
   // SL_VEL_GRIDDED: samples on the mesh (x first), mesh spacing and size,
@@ -136,6 +155,34 @@ __device__ __forceinline__ void wave_count(unsigned long long* ctr, bool pred) {
 template <typename T>
 __device__ __forceinline__ void zspline_weights(int m, T t, T* w);
 
+// Sum of the modes in the ik encoding at the point with sin/cos(pi y_a) =
+// sn[a] / cs[a]: e^{i theta} = e^{i phase} times |k_a| factors e^{+-i pi y_a}
+// per axis.  The wave vectors are wave-uniform, so these are scalar loops
+// (a branch per power would be if-converted into selects over every power).
+template <int D>
+__device__ __forceinline__ void fourier_small_k(const VelArgs& v, const double* sn,
+                                                const double* cs, double* u) {
+#pragma unroll
+  for (int a = 0; a < D; ++a) u[a] = 0.0;
+  for (int q = 0; q < v.nmodes; ++q) {
+    const Mode& md = v.mode[q];
+    double zr = md.ik.cphi, zi = md.ik.sphi;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const int k = md.ik.k[a];
+      const double r = cs[a], s = k < 0 ? -sn[a] : sn[a];
+#pragma unroll 1
+      for (int j = k < 0 ? -k : k; j > 0; --j) {
+        const double t = zr * r - zi * s;
+        zi = zr * s + zi * r;
+        zr = t;
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < D; ++a) u[a] = fma(md.amp[a], zr, u[a]);
+  }
+}
+
 template <int VK, int D>
 __device__ __forceinline__ void velocity(const VelArgs& v, const double* x, double tf,
                                          double* u) {
@@ -165,11 +212,18 @@ __device__ __forceinline__ void velocity(const VelArgs& v, const double* x, doub
     u[1] = -s * s2x * sy * sy * s2z;
     u[2] = -s * s2x * s2y * sz * sz;
   } else if constexpr (VK == SL_VEL_FOURIER) {
+    if (v.small_k) {
+      double sn[D], cs[D];
+#pragma unroll
+      for (int a = 0; a < D; ++a) sincospi(x[a] * v.kscale[a], &sn[a], &cs[a]);
+      fourier_small_k<D>(v, sn, cs, u);
+      return;
+    }
     for (int a = 0; a < D; ++a) u[a] = 0.0;
     for (int q = 0; q < v.nmodes; ++q) {
       const Mode& md = v.mode[q];
-      double th = md.phase_over_pi;
-      for (int a = 0; a < D; ++a) th += md.c[a] * x[a];
+      double th = md.gen.phase_over_pi;
+      for (int a = 0; a < D; ++a) th += md.gen.c[a] * x[a];
       const double cs = cospi(th);
       for (int a = 0; a < D; ++a) u[a] += md.amp[a] * cs;
     }
@@ -258,11 +312,17 @@ template <int VK, int D>
 struct NodeVelocity {
   double s0[3], c0[3];
 
-  __device__ __forceinline__ void init(const double* x0) {
+  // SL_VEL_FOURIER in the ik encoding: s0/c0 hold sin/cos(pi y_a) at x0.
+  __device__ __forceinline__ void init(const VelArgs& v, const double* x0) {
     if constexpr (VK == SL_VEL_SWIRL2D || (VK == SL_VEL_DEFORM3D && D == 3)) {
       constexpr int NA = VK == SL_VEL_SWIRL2D ? 2 : 3;
 #pragma unroll
       for (int a = 0; a < NA; ++a) sincospi(x0[a], &s0[a], &c0[a]);
+    } else if constexpr (VK == SL_VEL_FOURIER) {
+      if (v.small_k) {
+#pragma unroll
+        for (int a = 0; a < D; ++a) sincospi(x0[a] * v.kscale[a], &s0[a], &c0[a]);
+      }
     }
   }
 
@@ -295,6 +355,22 @@ struct NodeVelocity {
         u[2] = -s * s2x * s2y * sn[2] * sn[2];
       }
     } else {
+      if constexpr (VK == SL_VEL_FOURIER) {
+        if (v.small_k) {
+          double sn[D], cs[D];
+#pragma unroll
+          for (int a = 0; a < D; ++a) {
+            if (delta) {
+              sincospi_shift(s0[a], c0[a], delta[a] * v.kscale[a], &sn[a], &cs[a]);
+            } else {
+              sn[a] = s0[a];
+              cs[a] = c0[a];
+            }
+          }
+          fourier_small_k<D>(v, sn, cs, u);
+          return;
+        }
+      }
       double x[D];
 #pragma unroll
       for (int a = 0; a < D; ++a) x[a] = delta ? x0[a] + delta[a] : x0[a];

@@ -59,7 +59,7 @@ __device__ __forceinline__ void traj_node_with(const GridArgs& g, const VelArgs&
     d[a] = accumulate ? disp[(size_t)a * g.ntot + lin] : 0.0;
     x[a] = ((double)(idx[a] + g.off[a]) + d[a]) * g.h[a];
   }
-  vel.init(x);
+  vel.init(v, x);
   if (integrator == SL_RK4) {
     double k1[D], k2[D], k3[D], k4[D], o[D];
     vel.eval(v, x, nullptr, st.tf[0], k1);
@@ -117,7 +117,7 @@ struct GriddedBox2D {
   const double* box;  // 2 planes of W x W samples
   int bx0, by0, W;
 
-  __device__ __forceinline__ void init(const double*) {}
+  __device__ __forceinline__ void init(const VelArgs&, const double*) {}
 
   __device__ __forceinline__ void eval(const VelArgs& v, const double* x0, const double* delta,
                                        double, double* u) const {

@@ -105,6 +105,14 @@ def _traj_cases():
     w2 = W.serving_request(W.rng(5), 0, 0.0, sides=(64,)).workload
     w2.value_prec = "f64"
     yield "fourier2d", w2
+    # Wave vectors outside the small-integer encoding (a component of 5 and a
+    # fractional one): the modes take one cosine each.
+    w3 = W.serving_request(W.rng(5), 0, 0.0, sides=(64,)).workload
+    w3.value_prec = "f64"
+    w3.velocity.modes = w3.velocity.modes.copy()
+    w3.velocity.modes[0, :2] = (5.0, -1.0)
+    w3.velocity.modes[1, :2] = (0.5, 2.0)
+    yield "fourier2d_large_k", w3
     # Velocity given on the mesh (Z-spline interpolation of the samples).
     yield "gridded_swirl_z2", W.gridded(W.swirl_three_fields(40, value_prec="f64"), 2, t=0.4)
     yield "gridded_swirl_z0", W.gridded(W.swirl_three_fields(36, value_prec="f64"), 0, t=0.4)
