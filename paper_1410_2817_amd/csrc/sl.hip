@@ -495,6 +495,14 @@ int sl_create_grid(const sl_grid_desc* desc, sl_grid** out) {
     gr->off_src_qh = align_up(gr->off_src_qx + 2 * plane);
     gr->ws_bytes = align_up(gr->off_src_qh + 3 * plane);
   }
+  gr->off_trig = gr->trig_bytes = 0;
+  if (sl::uses_trig_table(v, D) && desc->source == SL_SRC_NONE) {
+    size_t axes = 0;
+    for (int a = 0; a < D; ++a) axes += (size_t)desc->n[a];
+    gr->off_trig = gr->ws_bytes;
+    gr->trig_bytes = 2 * sizeof(double) * axes;
+    gr->ws_bytes = align_up(gr->off_trig + gr->trig_bytes);
+  }
   // 2-D grids evaluate the limiter flags inside the reconstruction tiles
   // (the values are staged there anyway) unless the grid is large, where a
   // separate order-word pass costs less than the tiles' redundant flag work.
@@ -786,6 +794,21 @@ int sl_advance(sl_grid* gr, void* workspace, void* const* fields_a, void* const*
       e = gr->desc.dim == 2 ? launch_traj<2>(gr, dbuf[0], t0, dt, 0, s, ps.start, ps.stop)
                             : launch_traj<3>(gr, dbuf[0], t0, dt, 0, s, ps.start, ps.stop);
     prof_end(gr, ps, 0, e);
+    // The fused trajectories start from sin/cos(pi x) at the mesh nodes: one
+    // table per call, n_x + n_y (+ n_z) entries.
+    const double* trig = nullptr;
+    if (e == hipSuccess && gr->trig_bytes && nsteps > 1) {
+      double* tb = reinterpret_cast<double*>(ws + gr->off_trig);
+      int axes = 0;
+      for (int a = 0; a < gr->desc.dim; ++a) axes += gr->g.n[a];
+      const dim3 blocks((axes + sl::kBlock - 1) / sl::kBlock), threads(sl::kBlock);
+      if (gr->desc.dim == 2)
+        sl::trig_table_kernel<2><<<blocks, threads, 0, s>>>(gr->g, gr->v, tb);
+      else
+        sl::trig_table_kernel<3><<<blocks, threads, 0, s>>>(gr->g, gr->v, tb);
+      e = hipGetLastError();
+      trig = tb;
+    }
     for (int k = 0; k < nsteps && e == hipSuccess; ++k) {
       gr->steps_launched++;
       sl::NextTraj nt{};
@@ -795,6 +818,7 @@ int sl_advance(sl_grid* gr, void* workspace, void* const* fields_a, void* const*
         nt.dt = dt;
         nt.integrator = gr->desc.integrator;
         nt.carried = carried ? 1 : 0;
+        nt.trig = carried ? nullptr : trig;
       }
       e = reconstruct_launches(gr, ws, (k & 1) ? ba : ab, dbuf[k & 1], nt, s);
       if (e == hipSuccess) gr->reconstructs_launched++;

@@ -312,6 +312,23 @@ template <int VK, int D>
 struct NodeVelocity {
   double s0[3], c0[3];
 
+  // From the per-axis table of trig_table_kernel (sl_traj.h) instead: the
+  // same values at a lattice node that sits on its mesh node (x0 = idx h).
+  __device__ __forceinline__ void init_table(const double* __restrict__ trig, const GridArgs& g,
+                                             const int* idx) {
+    if constexpr (VK == SL_VEL_SWIRL2D || (VK == SL_VEL_DEFORM3D && D == 3) ||
+                  VK == SL_VEL_FOURIER) {
+      constexpr int NA = VK == SL_VEL_SWIRL2D ? 2 : D;
+      int base = 0;
+#pragma unroll
+      for (int a = 0; a < NA; ++a) {
+        s0[a] = trig[base + idx[a]];
+        c0[a] = trig[base + g.n[a] + idx[a]];
+        base += 2 * g.n[a];
+      }
+    }
+  }
+
   // SL_VEL_FOURIER in the ik encoding: s0/c0 hold sin/cos(pi y_a) at x0.
   __device__ __forceinline__ void init(const VelArgs& v, const double* x0) {
     if constexpr (VK == SL_VEL_SWIRL2D || (VK == SL_VEL_DEFORM3D && D == 3)) {

@@ -25,6 +25,9 @@ struct sl_grid {
   // precision each) and the RK registers of positions (2 FP64 planes) and
   // values (3), all per node.
   size_t off_src_h, off_src_g, off_src_qx, off_src_qh;
+  // Per-axis sin/cos table of the fused trajectories (sl::trig_table_kernel);
+  // 0 when the velocity family does not use one.
+  size_t off_trig, trig_bytes;
   bool limiter_words;  // limiter order words from a separate pass
   int steps_since_reset;
   int64_t steps_launched, reconstructs_launched;

@@ -235,7 +235,7 @@ __device__ __forceinline__ void recon2d_tile(const GridArgs& g, const FieldPtrs&
       for (int k = 0; k < C::NPT; ++k) {
         const int idx[2] = {tx0 + lx, ty0 + ly0 + ROWS * k};
         if (idx[0] < g.n[0] && idx[1] < g.n[1])
-          traj_any<2>(g, v, nt.disp, nt.st, nt.dt, nt.integrator, idx);
+          traj_any<2>(g, v, nt.disp, nt.st, nt.dt, nt.integrator, idx, nt.trig);
       }
     }
   }

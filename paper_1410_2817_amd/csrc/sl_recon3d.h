@@ -213,7 +213,8 @@ __global__ __launch_bounds__(kTileThreads, (Box3D<T, NF>::WAVES)) void recon3d_k
 
   // The next step's trajectory of this work-item's lattice node (NextTraj);
   // it touches nothing the reconstruction below reads.
-  if (nt.disp && !nt.carried && act) traj_any<3>(g, v, nt.disp, nt.st, nt.dt, nt.integrator, tgt);
+  if (nt.disp && !nt.carried && act)
+    traj_any<3>(g, v, nt.disp, nt.st, nt.dt, nt.integrator, tgt, nt.trig);
 
   // 1. Own displacement and start cell.
   double d0[3] = {0.0, 0.0, 0.0};

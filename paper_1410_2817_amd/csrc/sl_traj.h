@@ -46,12 +46,15 @@ constexpr int kTrajBX = 64, kTrajBY = 4;
 // Trajectory of lattice node idx over one step (or one more step when
 // `accumulate` is set), with the velocity evaluator `vel` (init(x0), then
 // eval(v, x0, delta, tf, u) at x0 + delta).
+// `trig` (fresh lattice only): the per-axis sin/cos table of trig_table_kernel
+// for the velocity families whose evaluator starts from sin/cos at x0.
 template <int D, class Vel>
 __device__ __forceinline__ void traj_node_with(const GridArgs& g, const VelArgs& v, Vel vel,
                                                double* __restrict__ disp,
                                                const StageTimes& st, double dt,
                                                int accumulate, int integrator,
-                                               const int* idx) {
+                                               const int* idx,
+                                               const double* __restrict__ trig = nullptr) {
   const int lin = flatten<D>(g, idx);
   double d[D], x[D];
 #pragma unroll
@@ -59,7 +62,10 @@ __device__ __forceinline__ void traj_node_with(const GridArgs& g, const VelArgs&
     d[a] = accumulate ? disp[(size_t)a * g.ntot + lin] : 0.0;
     x[a] = ((double)(idx[a] + g.off[a]) + d[a]) * g.h[a];
   }
-  vel.init(v, x);
+  if (trig && !accumulate)
+    vel.init_table(trig, g, idx);
+  else
+    vel.init(v, x);
   if (integrator == SL_RK4) {
     double k1[D], k2[D], k3[D], k4[D], o[D];
     vel.eval(v, x, nullptr, st.tf[0], k1);
@@ -104,8 +110,41 @@ template <int D, int VK>
 __device__ __forceinline__ void traj_node(const GridArgs& g, const VelArgs& v,
                                           double* __restrict__ disp, const StageTimes& st,
                                           double dt, int accumulate, int integrator,
-                                          const int* idx) {
-  traj_node_with<D>(g, v, NodeVelocity<VK, D>{}, disp, st, dt, accumulate, integrator, idx);
+                                          const int* idx, const double* trig = nullptr) {
+  traj_node_with<D>(g, v, NodeVelocity<VK, D>{}, disp, st, dt, accumulate, integrator, idx,
+                    trig);
+}
+
+// Does the grid's velocity evaluator start from sin/cos(pi x0) per axis (so
+// that a fresh lattice can read them from the trig table)?
+__host__ __device__ inline bool uses_trig_table(const VelArgs& v, int dim) {
+  return (v.kind == SL_VEL_SWIRL2D && dim == 2) || (v.kind == SL_VEL_DEFORM3D && dim == 3) ||
+         (v.kind == SL_VEL_FOURIER && v.small_k);
+}
+
+// sin/cos of pi times the first-stage argument of the evaluator, per axis a
+// and mesh index i: x0 = (i + off_a) h_a (the Fourier ik encoding takes
+// x0 * kscale_a).  Layout: axis a holds sin at [base_a, base_a + n_a) and cos
+// at [base_a + n_a, base_a + 2 n_a), base_a = 2 sum_{b<a} n_b.  The values are
+// the ones NodeVelocity::init computes for a lattice node on its mesh node,
+// by the same expressions.
+template <int D>
+__global__ __launch_bounds__(kBlock) void trig_table_kernel(GridArgs g, VelArgs v,
+                                                            double* __restrict__ trig) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int a = 0, base = 0;
+  while (a < D && i >= g.n[a]) {
+    i -= g.n[a];
+    base += 2 * g.n[a];
+    ++a;
+  }
+  if (a >= D) return;
+  const double x0 = ((double)(i + g.off[a]) + 0.0) * g.h[a];
+  const double arg = v.kind == SL_VEL_FOURIER ? x0 * v.kscale[a] : x0;
+  double s, c;
+  sincospi(arg, &s, &c);
+  trig[base + i] = s;
+  trig[base + g.n[a] + i] = c;
 }
 
 // Gridded velocity in 2-D with the samples around a tile staged in LDS: the
@@ -118,6 +157,7 @@ struct GriddedBox2D {
   int bx0, by0, W;
 
   __device__ __forceinline__ void init(const VelArgs&, const double*) {}
+  __device__ __forceinline__ void init_table(const double*, const GridArgs&, const int*) {}
 
   __device__ __forceinline__ void eval(const VelArgs& v, const double* x0, const double* delta,
                                        double, double* u) const {
@@ -202,7 +242,8 @@ __global__ __launch_bounds__(256) void traj_gridded2d_kernel(GridArgs g, VelArgs
 template <int D>
 __device__ __forceinline__ void traj_any(const GridArgs& g, const VelArgs& v,
                                          double* __restrict__ disp, const StageTimes& st,
-                                         double dt, int integrator, const int* idx) {
+                                         double dt, int integrator, const int* idx,
+                                         const double* trig = nullptr) {
   switch (v.kind) {
     case SL_VEL_UNIFORM:
       traj_node<D, SL_VEL_UNIFORM>(g, v, disp, st, dt, 0, integrator, idx);
@@ -211,13 +252,14 @@ __device__ __forceinline__ void traj_any(const GridArgs& g, const VelArgs& v,
       traj_node<D, SL_VEL_SOLID_BODY>(g, v, disp, st, dt, 0, integrator, idx);
       break;
     case SL_VEL_SWIRL2D:
-      traj_node<D, SL_VEL_SWIRL2D>(g, v, disp, st, dt, 0, integrator, idx);
+      traj_node<D, SL_VEL_SWIRL2D>(g, v, disp, st, dt, 0, integrator, idx, trig);
       break;
     case SL_VEL_DEFORM3D:
-      traj_node<D, SL_VEL_DEFORM3D>(g, v, disp, st, dt, 0, integrator, idx);
+      traj_node<D, SL_VEL_DEFORM3D>(g, v, disp, st, dt, 0, integrator, idx, trig);
       break;
     default:
-      traj_node<D, SL_VEL_FOURIER>(g, v, disp, st, dt, 0, integrator, idx);
+      traj_node<D, SL_VEL_FOURIER>(g, v, disp, st, dt, 0, integrator, idx,
+                                   v.small_k ? trig : nullptr);
       break;
   }
 }
@@ -235,6 +277,7 @@ struct NextTraj {
   double dt;
   int integrator;
   int carried;
+  const double* trig;  // trig_table_kernel's table, or null
 };
 
 // Stand-in for the velocity argument of kernels that never integrate.

@@ -293,11 +293,13 @@ def test_jump_flags_at_ties_fp32(B, torch, orc, theta):
     ("swirl96_f32", W.swirl_three_fields(96, value_prec="f32")),
     ("fourier3d_28_f32", W.fourier3d_three_fields(28, value_prec="f32")),
     ("deform3d_24_f64", W.deform3d_slotted_sphere(24)),
+    ("fourier2d_96_f32", W.serving_request(W.rng(7), 0, 0.0, sides=(96,)).workload),
 ])
 def test_per_call_path_equals_advance(B, torch, name, wl):
     """sl_step / sl_reconstruct called one by one give the same bits as
     sl_advance (where each reconstruction also integrates the next step's
-    trajectories), and kernel events do not change results."""
+    trajectories, starting from the per-axis sin/cos table where the velocity
+    family has one), and kernel events do not change results."""
     a, _, _, _ = gpu_run(B, torch, wl, nsteps=4, t0=0.6)
     g = B.Grid.from_workload(wl)
     g.profile(True)
