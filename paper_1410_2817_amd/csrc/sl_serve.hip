@@ -47,6 +47,7 @@ struct ReqStatic {
   int traj_bx, traj_by;   // trajectory blocks (64 x 4 nodes each)
   int integrator;
   int pad;
+  const double* trig;  // per-axis sin/cos table (sl::trig_table_kernel), or null
 };
 
 // Per tick and request, passed in the kernel arguments.
@@ -91,7 +92,7 @@ __global__ __launch_bounds__(kBlock) void traj_batched_kernel(const ReqStatic* _
   st.tf[1] = rt.tf[1];
   st.tf[2] = rt.tf[2];
   st.tf[3] = rt.tf[2];
-  traj_node<2, VK>(rs.g, rs.v, rs.disp, st, rt.dt, 0, rs.integrator, idx);
+  traj_node<2, VK>(rs.g, rs.v, rs.disp, st, rt.dt, 0, rs.integrator, idx, rs.trig);
 }
 
 template <typename T, int NF>
@@ -118,6 +119,7 @@ void recon2d_batched_kernel(
     nt.st.tf[3] = rt.tf[2];
     nt.dt = rt.dt;
     nt.integrator = rs.integrator;
+    nt.trig = rs.trig;
   }
   recon2d_tile<T, NF>(rs.g, fp, rt.parity ? rs.disp2 : rs.disp, nullptr, rs.stats,
                       logical - rt.blk_begin, rs.tiles_x, smem, nt, rs.v);
@@ -206,9 +208,9 @@ size_t request_bytes(const sl_grid* gr) {
   const size_t field = align_up(vbytes * (size_t)gr->ntot);
   // The batched reconstruction evaluates the limiter flags in LDS, so the
   // request needs the workspace only up to the order-word arrays, plus the
-  // second displacement buffer.
+  // second displacement buffer and the trajectories' sin/cos table.
   return 2 * (size_t)gr->desc.nfields * field + align_up(gr->off_ord) +
-         align_up(sizeof(double) * 2 * (size_t)gr->ntot);
+         align_up(sizeof(double) * 2 * (size_t)gr->ntot) + align_up(gr->trig_bytes);
 }
 
 hipEvent_t take_event(sl_server* s) {
@@ -408,6 +410,11 @@ int sl_server_admit(sl_server* s, const sl_grid_desc* desc, const void* const* f
   }
   hs.disp = reinterpret_cast<double*>(ws + gr->off_disp);
   hs.disp2 = reinterpret_cast<double*>(ws + align_up(gr->off_ord));
+  double* trig = gr->trig_bytes ? reinterpret_cast<double*>(
+                                      ws + align_up(gr->off_ord) +
+                                      align_up(sizeof(double) * 2 * (size_t)gr->ntot))
+                                : nullptr;
+  hs.trig = trig;
   hs.stats = s->stats;
   using C = sl::Tile2D<float, 1>;
   hs.tiles_x = (gr->g.n[0] + C::TX - 1) / C::TX;
@@ -418,6 +425,12 @@ int sl_server_admit(sl_server* s, const sl_grid_desc* desc, const void* const* f
 
   hipError_t e = hipMemcpyAsync(s->table + r.entry, &hs, sizeof(hs), hipMemcpyHostToDevice,
                                 s->stream);
+  if (e == hipSuccess && trig) {
+    const int axes = gr->g.n[0] + gr->g.n[1];
+    sl::trig_table_kernel<2><<<(axes + sl::kBlock - 1) / sl::kBlock, sl::kBlock, 0, s->stream>>>(
+        gr->g, gr->v, trig);
+    e = hipGetLastError();
+  }
   for (int f = 0; f < desc->nfields && e == hipSuccess; ++f)
     e = hipMemcpyAsync(r.a[f], fields_in[f], vbytes * (size_t)gr->ntot,
                        hipMemcpyDeviceToDevice, s->stream);
