@@ -286,14 +286,22 @@ __device__ __forceinline__ void velocity(const VelArgs& v, const double* x, doub
 // addition with sin/cos(pi delta) from short Taylor series; `tf` is the time
 // factor cos(pi t / p0) of the stage, computed on the host.
 
+// Taylor coefficients of sin (z, z^3, ..., z^9: [4] .. [0]) and cos (1, z^2,
+// ..., z^10: [10] .. [5]).  Kept in constant memory, they reach the FMAs as
+// scalar operands; as literals each 64-bit constant took two VALU moves.  Not
+// static: with internal linkage the compiler folds them back into literals.
+__constant__ double kTaylorSinCos[11] = {
+    1.0 / 362880,   -1.0 / 5040,  1.0 / 120, -1.0 / 6, 1.0,  // sin
+    -1.0 / 3628800, 1.0 / 40320, -1.0 / 720, 1.0 / 24, -0.5, 1.0};  // cos
+
 // sin(pi d) and cos(pi d): Taylor series to z^9 / z^10 (z = pi d) for
 // |d| <= 1/32, where the truncation error is below 2e-19; sincospi beyond.
 __device__ __forceinline__ void sincospi_near0(double d, double* s, double* c) {
   if (fabs(d) <= 0.03125) {
     const double z = 3.141592653589793 * d, z2 = z * z;
-    *s = z * (1.0 + z2 * (-1.0 / 6 + z2 * (1.0 / 120 + z2 * (-1.0 / 5040 + z2 * (1.0 / 362880)))));
-    *c = 1.0 + z2 * (-0.5 + z2 * (1.0 / 24 + z2 * (-1.0 / 720 + z2 * (1.0 / 40320 +
-                                                                    z2 * (-1.0 / 3628800)))));
+    const double* k = kTaylorSinCos;
+    *s = z * (k[4] + z2 * (k[3] + z2 * (k[2] + z2 * (k[1] + z2 * k[0]))));
+    *c = k[10] + z2 * (k[9] + z2 * (k[8] + z2 * (k[7] + z2 * (k[6] + z2 * k[5]))));
   } else {
     sincospi(d, s, c);
   }
