@@ -155,6 +155,32 @@ __device__ __forceinline__ void wave_count(unsigned long long* ctr, bool pred) {
 template <typename T>
 __device__ __forceinline__ void zspline_weights(int m, T t, T* w);
 
+// cos(pi x) for the general Fourier encoding.  With n the integer nearest x
+// and t = x - n (both exact), cos(pi x) = (-1)^n cos(pi t), |t| <= 1/2, and
+// cos(pi t) is its Taylor series in z = pi t up to z^22 (remainder below
+// 1e-19 for |z| <= pi/2; absolute error a few 1e-16 in all).  The library
+// cospi's general argument handling cost about twice the instructions per mode.
+// Coefficients (-1)^k / (2k)! in constant memory, so that the FMAs take them
+// as scalar operands (not static: with internal linkage the compiler folds
+// them back into literals, two VALU moves each).
+__constant__ double kCosTaylor[12] = {
+    1.0,           -1.0 / 2,          1.0 / 24,           -1.0 / 720,
+    1.0 / 40320,   -1.0 / 3628800,    1.0 / 479001600,    -1.0 / 87178291200.0,
+    1.0 / 20922789888000.0, -1.0 / 6402373705728000.0, 1.0 / 2432902008176640000.0,
+    -1.0 / 1124000727777607680000.0};
+
+__device__ __forceinline__ double cospi_taylor(double x) {
+  const double n = rint(x);
+  const double t = x - n;
+  const double z = 3.141592653589793 * t, z2 = z * z;
+  const double* k = kCosTaylor;
+  double p = k[11];
+#pragma unroll
+  for (int i = 10; i >= 0; --i) p = fma(p, z2, k[i]);
+  const double h = 0.5 * n;
+  return h != rint(h) ? -p : p;
+}
+
 // Sum of the modes in the ik encoding at the point with sin/cos(pi y_a) =
 // sn[a] / cs[a]: e^{i theta} = e^{i phase} times |k_a| factors e^{+-i pi y_a}
 // per axis.  The wave vectors are wave-uniform, so these are scalar loops
@@ -224,7 +250,7 @@ __device__ __forceinline__ void velocity(const VelArgs& v, const double* x, doub
       const Mode& md = v.mode[q];
       double th = md.gen.phase_over_pi;
       for (int a = 0; a < D; ++a) th += md.gen.c[a] * x[a];
-      const double cs = cospi(th);
+      const double cs = cospi_taylor(th);
       for (int a = 0; a < D; ++a) u[a] += md.amp[a] * cs;
     }
   } else if constexpr (VK == SL_VEL_GRIDDED) {
