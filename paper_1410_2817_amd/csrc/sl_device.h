@@ -152,7 +152,9 @@ __device__ __forceinline__ void wave_count(unsigned long long* ctr, bool pred) {
 // Prescribed velocity u(x, t) (physical units).  `tf` is the time factor
 // cos(pi t / p0) of the periodic families, evaluated once per stage.
 
-template <typename T>
+// Tab (FP64 only): Z2 coefficients from constant memory (kZ2Coef) rather
+// than literals.
+template <typename T, bool Tab = true>
 __device__ __forceinline__ void zspline_weights(int m, T t, T* w);
 
 // cos(pi x) for the general Fourier encoding.  With n the integer nearest x
@@ -160,23 +162,25 @@ __device__ __forceinline__ void zspline_weights(int m, T t, T* w);
 // cos(pi t) is its Taylor series in z = pi t up to z^22 (remainder below
 // 1e-19 for |z| <= pi/2; absolute error a few 1e-16 in all).  The library
 // cospi's general argument handling cost about twice the instructions per mode.
-// Coefficients (-1)^k / (2k)! in constant memory, so that the FMAs take them
-// as scalar operands (not static: with internal linkage the compiler folds
-// them back into literals, two VALU moves each).
-__constant__ double kCosTaylor[12] = {
-    1.0,           -1.0 / 2,          1.0 / 24,           -1.0 / 720,
-    1.0 / 40320,   -1.0 / 3628800,    1.0 / 479001600,    -1.0 / 87178291200.0,
-    1.0 / 20922789888000.0, -1.0 / 6402373705728000.0, 1.0 / 2432902008176640000.0,
-    -1.0 / 1124000727777607680000.0};
-
+// Coefficients (-1)^k / (2k)! as literals: the mode loop keeps them in
+// registers across iterations (from constant memory they took scalar
+// registers that kernels embedding every velocity family then had to spill).
 __device__ __forceinline__ double cospi_taylor(double x) {
   const double n = rint(x);
   const double t = x - n;
   const double z = 3.141592653589793 * t, z2 = z * z;
-  const double* k = kCosTaylor;
-  double p = k[11];
-#pragma unroll
-  for (int i = 10; i >= 0; --i) p = fma(p, z2, k[i]);
+  double p = -1.0 / 1124000727777607680000.0;
+  p = fma(p, z2, 1.0 / 2432902008176640000.0);
+  p = fma(p, z2, -1.0 / 6402373705728000.0);
+  p = fma(p, z2, 1.0 / 20922789888000.0);
+  p = fma(p, z2, -1.0 / 87178291200.0);
+  p = fma(p, z2, 1.0 / 479001600.0);
+  p = fma(p, z2, -1.0 / 3628800.0);
+  p = fma(p, z2, 1.0 / 40320.0);
+  p = fma(p, z2, -1.0 / 720.0);
+  p = fma(p, z2, 1.0 / 24.0);
+  p = fma(p, z2, -0.5);
+  p = fma(p, z2, 1.0);
   const double h = 0.5 * n;
   return h != rint(h) ? -p : p;
 }
@@ -435,13 +439,40 @@ struct NodeVelocity {
 // holds the weight Z_m(t - k) of node r + k, k = -2..3; slots outside the
 // order-m stencil are zero.
 
-template <typename T>
+// The Z2 coefficients below as FP64, in the order they appear there.  The
+// FP64 weights read them from constant memory so that the FMAs take them as
+// scalar operands (as FP64 literals each took two VALU moves; FP32 literals
+// fit the instructions).  Not static, for the reason given at kTaylorSinCos.
+// The 2-D reconstruction kernels keep the literals (Tab = false): there the
+// scalar registers the table takes are spilled.
+__constant__ double kZ2Coef[28] = {
+    1.0 / 12,  -1.0 / 24,  -3.0 / 8,   13.0 / 24,  -5.0 / 24,   // w0
+    -2.0 / 3,  2.0 / 3,    13.0 / 8,   -8.0 / 3,   25.0 / 24,   // w1
+    -5.0 / 4,  -35.0 / 12, 21.0 / 4,   -25.0 / 12,              // w2
+    2.0 / 3,   2.0 / 3,    11.0 / 4,   -31.0 / 6,  25.0 / 12,   // w3
+    -1.0 / 12, -1.0 / 24,  -11.0 / 8,  61.0 / 24,  -25.0 / 24,  // w4
+    7.0 / 24,  -1.0 / 2,   5.0 / 24,   0.0};                    // w5
+
+template <typename T, bool Tab>
 __device__ __forceinline__ void zspline_weights(int m, T t, T* w) {
   // Each weight is its degree-(2m+1) polynomial in t in Horner form, with the
   // Appendix's rational coefficients; every weight but the node's own has no
   // constant term, so t = 0 gives exactly the unit weight on slot 2.
   const T one = T(1);
   const T t2 = t * t;
+  if constexpr (sizeof(T) == 8 && Tab) {
+    if (m == 2) {
+      // The same polynomials as below, coefficients from kZ2Coef.
+      const double* k = kZ2Coef;
+      w[0] = t * (k[0] + t * (k[1] + t * (k[2] + t * (k[3] + t * k[4]))));
+      w[1] = t * (k[5] + t * (k[6] + t * (k[7] + t * (k[8] + t * k[9]))));
+      w[2] = one + t2 * (k[10] + t * (k[11] + t * (k[12] + t * k[13])));
+      w[3] = t * (k[14] + t * (k[15] + t * (k[16] + t * (k[17] + t * k[18]))));
+      w[4] = t * (k[19] + t * (k[20] + t * (k[21] + t * (k[22] + t * k[23]))));
+      w[5] = t2 * t * (k[24] + t * (k[25] + t * k[26]));
+      return;
+    }
+  }
   if (m == 2) {
     // Z2(t + 2) = -t (t-1)^3 (5t + 2) / 24
     w[0] = t * (T(1.0 / 12) + t * (T(-1.0 / 24) + t * (T(-3.0 / 8) + t * (T(13.0 / 24) + t * T(-5.0 / 24)))));

@@ -454,8 +454,8 @@ __device__ __forceinline__ void recon2d_tile(const GridArgs& g, const FieldPtrs&
     // only run when some lane of the wave needs them (a wave-uniform branch).
     const T tx = (T)xi[0], ty = (T)xi[1];
     T w2x[6], w2y[6];
-    zspline_weights<T>(g.order_max, tx, w2x);
-    zspline_weights<T>(g.order_max, ty, w2y);
+    zspline_weights<T, false>(g.order_max, tx, w2x);
+    zspline_weights<T, false>(g.order_max, ty, w2y);
     const unsigned fmask = nf >= 32 ? 0xffffffffu : ((1u << nf) - 1u);
     const bool low = lim && (((or6 | or4) & fmask) != 0u);
     auto field_value = [&](int f, const T* wx, const T* wy) {
@@ -493,10 +493,10 @@ __device__ __forceinline__ void recon2d_tile(const GridArgs& g, const FieldPtrs&
           continue;
         }
         T w1x[6], w1y[6], w0x[6], w0y[6];
-        zspline_weights<T>(g.order_max > 1 ? 1 : 0, tx, w1x);
-        zspline_weights<T>(g.order_max > 1 ? 1 : 0, ty, w1y);
-        zspline_weights<T>(0, tx, w0x);
-        zspline_weights<T>(0, ty, w0y);
+        zspline_weights<T, false>(g.order_max > 1 ? 1 : 0, tx, w1x);
+        zspline_weights<T, false>(g.order_max > 1 ? 1 : 0, ty, w1y);
+        zspline_weights<T, false>(0, tx, w0x);
+        zspline_weights<T, false>(0, ty, w0y);
         const int drop = g.order_max - m;  // 0, 1 or 2 orders below the top
         T wx[6], wy[6];
 #pragma unroll
