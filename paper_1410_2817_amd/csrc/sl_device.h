@@ -162,25 +162,42 @@ __device__ __forceinline__ void zspline_weights(int m, T t, T* w);
 // cos(pi t) is its Taylor series in z = pi t up to z^22 (remainder below
 // 1e-19 for |z| <= pi/2; absolute error a few 1e-16 in all).  The library
 // cospi's general argument handling cost about twice the instructions per mode.
-// Coefficients (-1)^k / (2k)! as literals: the mode loop keeps them in
-// registers across iterations (from constant memory they took scalar
-// registers that kernels embedding every velocity family then had to spill).
+// Coefficients (-1)^k / (2k)!.  Tab: from constant memory (scalar operands of
+// the FMAs); otherwise literals, which the mode loop keeps in vector
+// registers.  The 2-D kernels embed every velocity family and spill the
+// scalar registers the table takes, so only 3-D grids use it.  Not static,
+// for the reason given at kTaylorSinCos.
+__constant__ double kCosTaylor[12] = {
+    1.0,           -1.0 / 2,          1.0 / 24,           -1.0 / 720,
+    1.0 / 40320,   -1.0 / 3628800,    1.0 / 479001600,    -1.0 / 87178291200.0,
+    1.0 / 20922789888000.0, -1.0 / 6402373705728000.0, 1.0 / 2432902008176640000.0,
+    -1.0 / 1124000727777607680000.0};
+
+template <bool Tab>
 __device__ __forceinline__ double cospi_taylor(double x) {
   const double n = rint(x);
   const double t = x - n;
   const double z = 3.141592653589793 * t, z2 = z * z;
-  double p = -1.0 / 1124000727777607680000.0;
-  p = fma(p, z2, 1.0 / 2432902008176640000.0);
-  p = fma(p, z2, -1.0 / 6402373705728000.0);
-  p = fma(p, z2, 1.0 / 20922789888000.0);
-  p = fma(p, z2, -1.0 / 87178291200.0);
-  p = fma(p, z2, 1.0 / 479001600.0);
-  p = fma(p, z2, -1.0 / 3628800.0);
-  p = fma(p, z2, 1.0 / 40320.0);
-  p = fma(p, z2, -1.0 / 720.0);
-  p = fma(p, z2, 1.0 / 24.0);
-  p = fma(p, z2, -0.5);
-  p = fma(p, z2, 1.0);
+  double p;
+  if constexpr (Tab) {
+    const double* k = kCosTaylor;
+    p = k[11];
+#pragma unroll
+    for (int i = 10; i >= 0; --i) p = fma(p, z2, k[i]);
+  } else {
+    p = -1.0 / 1124000727777607680000.0;
+    p = fma(p, z2, 1.0 / 2432902008176640000.0);
+    p = fma(p, z2, -1.0 / 6402373705728000.0);
+    p = fma(p, z2, 1.0 / 20922789888000.0);
+    p = fma(p, z2, -1.0 / 87178291200.0);
+    p = fma(p, z2, 1.0 / 479001600.0);
+    p = fma(p, z2, -1.0 / 3628800.0);
+    p = fma(p, z2, 1.0 / 40320.0);
+    p = fma(p, z2, -1.0 / 720.0);
+    p = fma(p, z2, 1.0 / 24.0);
+    p = fma(p, z2, -0.5);
+    p = fma(p, z2, 1.0);
+  }
   const double h = 0.5 * n;
   return h != rint(h) ? -p : p;
 }
@@ -254,7 +271,7 @@ __device__ __forceinline__ void velocity(const VelArgs& v, const double* x, doub
       const Mode& md = v.mode[q];
       double th = md.gen.phase_over_pi;
       for (int a = 0; a < D; ++a) th += md.gen.c[a] * x[a];
-      const double cs = cospi_taylor(th);
+      const double cs = cospi_taylor<D == 3>(th);
       for (int a = 0; a < D; ++a) u[a] += md.amp[a] * cs;
     }
   } else if constexpr (VK == SL_VEL_GRIDDED) {

@@ -78,9 +78,12 @@ __device__ __forceinline__ void traj_node_with(const GridArgs& g, const VelArgs&
 #pragma unroll
     for (int a = 0; a < D; ++a) o[a] = dt * k3[a];
     vel.eval(v, x, o, st.tf[2], k4);
+    // One division per axis: dt (k1 + 2 k2 + 2 k3 + k4) / (6 h).  6 h is exact
+    // for power-of-two spacings, so uniform translations by whole cells stay
+    // exact.
 #pragma unroll
     for (int a = 0; a < D; ++a)
-      d[a] += dt * (k1[a] + 2.0 * k2[a] + 2.0 * k3[a] + k4[a]) / 6.0 / g.h[a];
+      d[a] += dt * (k1[a] + 2.0 * k2[a] + 2.0 * k3[a] + k4[a]) / (6.0 * g.h[a]);
   } else {
     // Williamson (1980) 2N-storage RK3: q = A_s q + dt u(x + dx, t + c_s dt),
     // dx += B_s q with A = (0, -5/9, -153/128), B = (1/3, 15/16, 8/15),
