@@ -203,8 +203,10 @@ int sl_create_grid(const sl_grid_desc *desc, sl_grid **out);
 int sl_destroy_grid(sl_grid *grid);
 
 /* Device bytes the caller must provide as `workspace` to the calls below
- * (lattice displacements and device counters); 0 for a NULL handle. The
- * workspace must be 256-byte aligned and zero-filled before its first use. */
+ * (lattice displacements, device counters, limiter order words and, for the
+ * periodic velocity families, a per-axis sin/cos table that sl_advance fills
+ * at each call); 0 for a NULL handle. The workspace must be 256-byte aligned
+ * and zero-filled before its first use. */
 size_t sl_workspace_bytes(const sl_grid *grid);
 
 /* SL_VEL_GRIDDED: the velocity samples for later sl_step / sl_advance calls.
