@@ -109,6 +109,31 @@ struct NearDisp2D {
   }
 };
 
+// Element solve in cell r with the global accessor: the four vertex indices
+// from one wrap per axis.  Same values and arithmetic as element_solve<2>.
+__device__ __forceinline__ int element_solve_near(const GridArgs& g, const NearDisp2D& acc,
+                                                  const int* tgt, const int* r, double* xi) {
+  const int x0 = wrap_near(r[0], g.n[0]), y0 = wrap_near(r[1], g.n[1]);
+  const int x1 = x0 + 1 == g.n[0] ? 0 : x0 + 1, y1 = y0 + 1 == g.n[1] ? 0 : y0 + 1;
+  const int row0 = g.n[0] * y0, row1 = g.n[0] * y1;
+  const int lin[4] = {x0 + row0, x1 + row0, x0 + row1, x1 + row1};
+  const double* __restrict__ gy = acc.gdisp + (size_t)g.ntot;
+  double V[4][2];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    V[e][0] = (double)(r[0] + (e & 1) - tgt[0]) + acc.gdisp[lin[e]];
+    V[e][1] = (double)(r[1] + (e >> 1) - tgt[1]) + gy[lin[e]];
+  }
+  Element<2> el;
+  el.set(V);
+  return el.solve(g, xi);
+}
+
+__device__ __forceinline__ int element_solve_near(const GridArgs& g, const BoxDisp2D& acc,
+                                                  const int* tgt, const int* r, double* xi) {
+  return element_solve<2>(g, acc, tgt, r, xi);
+}
+
 __device__ __forceinline__ BoxDisp2D make_disp_accessor(std::true_type, const double* ldx,
                                                         const double* ldy, int bx0, int by0,
                                                         int BX, int BY, const double* gdisp,
@@ -399,7 +424,7 @@ __device__ __forceinline__ void recon2d_tile(const GridArgs& g, const FieldPtrs&
     int walked = 0;
     int loc = LOC_OK;
     const auto solve = [&](const int* rr, double* x) {
-      return element_solve<2>(g, acc, tgt, rr, x);
+      return element_solve_near(g, acc, tgt, rr, x);
     };
     const int rc0 = solve(r, xi);
     if (rc0 != 1 || !in_cube<2>(g, xi)) {
