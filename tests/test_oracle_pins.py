@@ -522,8 +522,8 @@ def test_swirl_returns_after_one_period(orc):
 
 # --------------------------------------------------------------------------
 # Gridded velocity (velocity given on the reference mesh, interpolated with
-# the Z-spline of eq. "multiZ"; the paper's velocity "given ... or as part of
-# the transported quantities", Sec. 2)
+# the Z-spline of eq. "multiZ"; Sec. 2 lets the velocity be prescribed or be
+# one of the transported fields)
 
 def _gridded_problem(orc, shape, ugrid, m, length=None):
     return orc.Problem(shape, 1, length, vel_kind=orc.VEL_GRIDDED, vp=[float(m)], ugrid=ugrid)
