@@ -174,7 +174,16 @@ typedef struct sl_grid_desc {
                            * of the shard's edges (a halo of at least the largest
                            * displacement plus 4 nodes) match the whole grid.  Not
                            * with SL_VEL_GRIDDED or a source term; |offset| < 2^30. */
+  int limiter_pass;       /* where a 2-D grid evaluates the jump flags (Sec. 2.3):
+                           * SL_LIMITER_AUTO (default: inside the reconstruction
+                           * tiles below 2^22 nodes, a separate order-word pass
+                           * from there up), SL_LIMITER_IN_TILES or
+                           * SL_LIMITER_ORDER_WORDS.  Both give the same orders
+                           * and results; 3-D grids always take the separate
+                           * pass. */
 } sl_grid_desc;
+
+enum { SL_LIMITER_AUTO = 0, SL_LIMITER_IN_TILES = 1, SL_LIMITER_ORDER_WORDS = 2 };
 
 /* Counters accumulated on the device since the last sl_sync. */
 typedef struct sl_stats {

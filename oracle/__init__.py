@@ -106,6 +106,8 @@ def _load():
         lib.orc_run.argtypes = [P, C.c_double, C.c_double, C.c_int, C.c_int,
                                 C.POINTER(dp), C.POINTER(_Stats)]
         lib.orc_run.restype = C.c_int
+        lib.orc_run_f32store.argtypes = lib.orc_run.argtypes
+        lib.orc_run_f32store.restype = C.c_int
         lib.orc_fd_weights.argtypes = [C.c_int, C.c_int, dp]
         lib.orc_fd_weights.restype = C.c_int
         lib.orc_source_mesh.argtypes = [P, C.POINTER(dp), C.POINTER(dp)]
@@ -347,13 +349,19 @@ def step_sampled(prob: Problem, t: float, dt: float, fields, nodes,
     return rc, out, st.as_dict()
 
 
-def run(prob: Problem, t0: float, dt: float, nsteps: int, fields, kevery: int = 1):
-    """nsteps steps from t0; returns (status, fields, accumulated stats)."""
+def run(prob: Problem, t0: float, dt: float, nsteps: int, fields, kevery: int = 1,
+        store: str = "f64"):
+    """nsteps steps from t0; returns (status, fields, accumulated stats).
+
+    store="f32" rounds the fields to FP32 after every reconstruction (the
+    values a run with FP32 field storage carries between steps); the
+    arithmetic stays FP64."""
     fs = [f.copy() for f in _as_fields(prob, fields)]
     st = _Stats()
     p = prob._c()
-    rc = _load().orc_run(C.byref(p), float(t0), float(dt), int(nsteps), int(kevery),
-                         _fields_ptrs(fs), C.byref(st))
+    fn = _load().orc_run_f32store if store == "f32" else _load().orc_run
+    rc = fn(C.byref(p), float(t0), float(dt), int(nsteps), int(kevery),
+            _fields_ptrs(fs), C.byref(st))
     return rc, fs, st.as_dict()
 
 

@@ -824,8 +824,26 @@ static void accumulate_stats(orc_stats *tot, const orc_stats *st) {
  * fields on the mesh (Sec. 2: the lattice moves for a number of steps and is
  * then interpolated back and reset).  Step s covers [t0+s dt, t0+(s+1) dt];
  * nsteps must be a multiple of kevery.                                       */
+static int run_cycles(const orc_problem *P, double t0, double dt, int nsteps, int kevery,
+                      int store_f32, double *const *fields, orc_stats *stats);
+
 int orc_run(const orc_problem *P, double t0, double dt, int nsteps, int kevery,
             double *const *fields, orc_stats *stats) {
+  return run_cycles(P, t0, dt, nsteps, kevery, 0, fields, stats);
+}
+
+/* As orc_run, but every reconstructed value is rounded to the nearest FP32
+ * number before the next cycle uses it: the values a run that stores its
+ * fields in single precision carries from step to step (the FP32-value form,
+ * whose positions, search and Newton stay FP64).  All arithmetic within a
+ * step is still FP64.                                                        */
+int orc_run_f32store(const orc_problem *P, double t0, double dt, int nsteps, int kevery,
+                     double *const *fields, orc_stats *stats) {
+  return run_cycles(P, t0, dt, nsteps, kevery, 1, fields, stats);
+}
+
+static int run_cycles(const orc_problem *P, double t0, double dt, int nsteps, int kevery,
+                      int store_f32, double *const *fields, orc_stats *stats) {
   if (check_problem(P) != ORC_OK || kevery < 1 || nsteps % kevery != 0)
     return ORC_EINVAL;
   int64_t N = total_nodes(P);
@@ -852,6 +870,9 @@ int orc_run(const orc_problem *P, double t0, double dt, int nsteps, int kevery,
     orc_stats st;
     rc = orc_reconstruct(P, disp, (const double *const *)fields, outp, &st, NULL);
     for (int f = 0; f < nf; ++f) memcpy(fields[f], outp[f], sizeof(double) * (size_t)N);
+    if (store_f32)
+      for (int f = 0; f < nf; ++f)
+        for (int64_t i = 0; i < N; ++i) fields[f][i] = (double)(float)fields[f][i];
     accumulate_stats(&tot, &st);
   }
   free(disp);

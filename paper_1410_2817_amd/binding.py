@@ -21,6 +21,7 @@ SL_OK, SL_EINVAL, SL_ENOMEM, SL_EHIP, SL_ESEARCH, SL_ENEWTON, SL_ENONFINITE, \
 SL_FP64, SL_FP32 = 0, 1
 SL_RK4, SL_RK3_WILLIAMSON = 0, 1
 SL_SRC_NONE, SL_SRC_SHALLOW_WATER = 0, 1
+SL_LIMITER_AUTO, SL_LIMITER_IN_TILES, SL_LIMITER_ORDER_WORDS = 0, 1, 2
 SL_MAX_FIELDS = 8
 SL_MAX_MODES = 32
 
@@ -39,7 +40,7 @@ class SlGridDesc(C.Structure):
         ("newton_max_iter", C.c_int), ("newton_tol", C.c_double),
         ("walk_max", C.c_int), ("scan_radius", C.c_int), ("eps_inside", C.c_double),
         ("source", C.c_int), ("source_p", C.c_double * 4),
-        ("offset", C.c_int64 * 3),
+        ("offset", C.c_int64 * 3), ("limiter_pass", C.c_int),
     ]
 
 
@@ -156,7 +157,8 @@ def make_desc(shape: Sequence[int], nfields: int, *, length=None, value_prec="f6
               order_max=2, limiter=False, theta=0.25, integrator=SL_RK4,
               reconstruct_every=1, vel_kind=0, vel_params=None, modes=None,
               newton_max_iter=20, newton_tol=1e-14, walk_max=32, scan_radius=4,
-              eps_inside=1e-12, source=SL_SRC_NONE, source_p=None, offset=None):
+              eps_inside=1e-12, source=SL_SRC_NONE, source_p=None, offset=None,
+              limiter_pass=SL_LIMITER_AUTO):
     """Descriptor for a grid whose arrays have `shape` (array order, x last)."""
     d = SlGridDesc()
     load().sl_grid_desc_init(C.byref(d))
@@ -190,6 +192,7 @@ def make_desc(shape: Sequence[int], nfields: int, *, length=None, value_prec="f6
     if offset is not None:  # array order, like shape
         for a in range(dim):
             d.offset[a] = int(offset[dim - 1 - a])
+    d.limiter_pass = int(limiter_pass)
     d.source = int(source)
     sp = list(source_p or []) + [0.0] * 4
     for i in range(4):

@@ -130,6 +130,8 @@ int check_desc(const sl_grid_desc* d) {
   if (d->walk_max < 0 || d->walk_max > 4096) return SL_EINVAL;
   if (d->scan_radius < 0 || d->scan_radius > 16) return SL_EINVAL;
   if (d->limiter != 0 && d->limiter != 1) return SL_EINVAL;
+  if (d->limiter_pass < SL_LIMITER_AUTO || d->limiter_pass > SL_LIMITER_ORDER_WORDS)
+    return SL_EINVAL;
   if (d->limiter && !(d->limiter_theta >= 0.0)) return SL_EINVAL;
   int64_t tot = 1;
   for (int a = 0; a < d->dim; ++a) {
@@ -505,12 +507,10 @@ int sl_create_grid(const sl_grid_desc* desc, sl_grid** out) {
   }
   // 2-D grids evaluate the limiter flags inside the reconstruction tiles
   // (the values are staged there anyway) unless the grid is large, where a
-  // separate order-word pass costs less than the tiles' redundant flag work.
-  // SL_LIMITER_WORDS=0/1 in the environment forces the choice in 2-D.
-  {
-    const char* ev = getenv("SL_LIMITER_WORDS");
-    gr->limiter_words = D == 3 || (ev && *ev ? atoi(ev) != 0 : gr->ntot >= kWordsMinNodes);
-  }
+  // separate order-word pass costs less than the tiles' redundant flag work;
+  // the descriptor may force either choice.
+  gr->limiter_words = D == 3 || desc->limiter_pass == SL_LIMITER_ORDER_WORDS ||
+                      (desc->limiter_pass == SL_LIMITER_AUTO && gr->ntot >= kWordsMinNodes);
   gr->steps_since_reset = 0;
   *out = gr;
   return SL_OK;

@@ -73,7 +73,7 @@ def test_create_and_workspace_size(lib):
     dict(vel_kind=3, vel_params=[3.0, 1.0]),  # 3-D family on a 2-D grid
     dict(vel_kind=4),  # Fourier without modes
     dict(newton_max_iter=0), dict(newton_tol=0.0), dict(scan_radius=99),
-    dict(length=(1.0, 0.0)), dict(vel_params=[float("nan")]),
+    dict(length=(1.0, 0.0)), dict(vel_params=[float("nan")]), dict(limiter_pass=3),
 ])
 def test_create_rejects_bad_descriptors(lib, bad):
     kw = dict(bad)

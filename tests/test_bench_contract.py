@@ -30,11 +30,23 @@ def test_algorithmic_bytes_per_node():
     assert bench.recon_bytes_per_node(2, 3, 8) == 64
 
 
-def test_traffic_record_matches_the_headline_kernel():
-    t = bench.recorded_traffic()
-    assert t is not None, "profiles/ traffic record is stale: re-take it with rocprofv3"
-    # within a few percent of the 56 B x 1024^2 algorithmic bytes
-    assert 0.9 < t / (56 * 1024 * 1024) < 1.5
+@pytest.mark.parametrize("key,alg", [
+    # 64 B x 512^3 (FP64 value, 3-D displacement read and next one written)
+    (("deform3d", 512, "f64"), 64 * 512 ** 3),
+    # 56 B x 1024^2 (three FP32 values, 2-D displacements)
+    (("swirl", 1024, "f32"), 56 * 1024 ** 2),
+])
+def test_traffic_records_match_the_kernels(key, alg):
+    t = bench.recorded_traffic(key)
+    assert t is not None, "profiles/ traffic record of %s is stale: re-take it" % (key,)
+    # within a few percent of the algorithmic bytes (the limiter's order
+    # words add 2 B per node)
+    assert 0.9 < t / alg < 1.5
+
+
+def test_headline_is_the_largest_single_gpu_configuration():
+    assert bench.HEADLINE == ("deform3d", 512, "f64")
+    assert bench.HEADLINE in bench.TRAFFIC
 
 
 @pytest.mark.parametrize("key", [

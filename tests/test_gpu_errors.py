@@ -1,0 +1,177 @@
+"""Error paths and resumption, through the C ABI on the GPU:
+
+  - a non-finite input value is carried into the outputs whose stencils hold
+    it, counted, and reported by sl_sync as SL_ENONFINITE (the same nodes as
+    the oracle's);
+  - an element whose Newton iteration does not converge (Sec. 2.2) is
+    reported as SL_ENEWTON with the oracle's count of failed nodes: the
+    lattice is written through sl_displacement into the caller's workspace;
+  - a run stopped after k steps, saved to a file, loaded into fresh buffers
+    and a fresh grid, and continued for N - k steps ends bitwise where the
+    uninterrupted N-step run ends.
+No test here makes the GPU fault: every failure is a reported status."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1410_2817_amd import workloads as W
+from tests.util import oracle_problem, stored_values
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as T
+    if not T.cuda.is_available():
+        pytest.fail("no GPU visible")
+    return T
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_1410_2817_amd import binding
+    binding.load()
+    return binding
+
+
+@pytest.mark.parametrize("dim,prec", [(2, "f64"), (2, "f32"), (3, "f64"), (3, "f32")])
+def test_nonfinite_input_is_reported(B, torch, orc, dim, prec):
+    if dim == 2:
+        wl = W.swirl_three_fields(64, value_prec=prec)
+        bad = (40, 17)
+        t0 = 0.4
+    else:
+        wl = W.deform3d_slotted_sphere(24, value_prec=prec)
+        wl.fields = wl.fields + [W.gaussian(wl.shape, (0.5, 0.5, 0.5), 0.2)]
+        bad = (11, 9, 14)
+        t0 = 0.3
+    wl.limiter = False  # a NaN fires no flag; keep every stencil full-width
+    fields = stored_values(wl)
+    fields[0][bad] = np.nan
+    say("nonfinite", dim, prec, bad)
+    g = B.Grid.from_workload(wl)
+    out = g.advance(g.new_fields(fields), t0, wl.dt, 1)
+    rc, st = g.sync()
+    got = [f.double().cpu().numpy() for f in out]
+    nan_gpu = [~np.isfinite(f) for f in got]
+    count = int(sum(m.sum() for m in nan_gpu))
+    say("  rc", rc, "nonfinite", st["nonfinite"], "outputs", count)
+    assert rc == B.SL_ENONFINITE
+    assert st["nonfinite"] == count > 0
+    assert st["search_fail"] == 0 and st["newton_fail"] == 0
+    orc_rc, want, _ = orc.step(oracle_problem(orc, wl), t0, wl.dt, fields)
+    assert orc_rc == 0
+    for f in range(wl.nfields):
+        assert np.array_equal(nan_gpu[f], ~np.isfinite(want[f])), f
+    # Only field 0 held the NaN; the other fields are finite and correct.
+    for f in range(1, wl.nfields):
+        assert not nan_gpu[f].any()
+        e = np.abs(got[f] - want[f]).sum() / np.abs(want[f]).sum()
+        assert e <= (1e-5 if prec == "f32" else 1e-12)
+    # The counters were cleared: a clean step reports nothing.
+    out = g.advance(g.new_fields(stored_values(wl)), t0, wl.dt, 1)
+    rc, st = g.sync()
+    assert rc == 0 and st["nonfinite"] == 0
+
+
+def _curved_lattice(shape, block):
+    """Uniform displacement of half a cell, plus a checkerboard of +-1/16
+    cell on the nodes of a block: cells touching the block are curved (their
+    multilinear map has a non-zero mixed term), all others are exact
+    parallelograms.  Displacements are dyadic, so every parallelogram's
+    element solve is exact on both sides.  Returns (dim, *shape) in cell
+    units, component 0 along x (the last array axis)."""
+    dim = len(shape)
+    d = np.full((dim, *shape), 0.5)
+    idx = np.indices(shape).sum(axis=0)
+    sign = np.where(idx % 2 == 0, 1.0, -1.0)
+    sl = tuple(slice(b0, b1) for b0, b1 in block)
+    for a in range(dim):
+        d[a][sl] += 0.0625 * sign[sl]
+    return d
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_newton_failure_is_reported(B, torch, orc, dim):
+    """With a single Newton iteration and a tolerance no non-zero step meets,
+    an element solve converges only where its first step is exactly zero (the
+    parallelograms); in the curved cells the search ends on a cell whose
+    linear root is inside but whose Newton iteration did not converge:
+    SL_ENEWTON, on the same number of nodes as the oracle, with NaN outputs
+    there."""
+    if dim == 2:
+        shape, block = (24, 32), ((8, 13), (10, 16))
+    else:
+        shape, block = (12, 14, 16), ((4, 7), (5, 8), (6, 10))
+    g0 = np.random.Generator(np.random.PCG64(3))
+    fields = [g0.uniform(0.0, 1.0, shape)]
+    disp = _curved_lattice(shape, block)
+    say("newton failure", dim)
+    over = dict(newton_max_iter=1, newton_tol=1e-300)
+    g = B.Grid(shape, 1, vel_kind=W.VEL_UNIFORM, vel_params=[0.0] * 3, **over)
+    x = g.new_fields(fields)
+    y = g.new_fields()
+    g.step(0.0, 0.1)  # zero velocity: the lattice sits on the mesh
+    dview = g.displacement()
+    torch.cuda.synchronize()
+    dview.copy_(torch.as_tensor(disp, device=g.device))
+    g.reconstruct(x, y)
+    rc, st = g.sync()
+    got = y[0].double().cpu().numpy()
+    prob = orc.Problem(shape, 1, newton_max_iter=1, newton_tol=1e-300)
+    orc_rc, want, ost = orc.reconstruct(prob, disp, fields)
+    say("  gpu", rc, st["newton_fail"], st["search_fail"], "oracle", orc_rc,
+        ost["newton_fail"], ost["search_fail"])
+    assert orc_rc == orc.ENEWTON and ost["search_fail"] == 0 and ost["newton_fail"] > 0
+    assert rc == B.SL_ENEWTON
+    assert st["newton_fail"] == ost["newton_fail"] and st["search_fail"] == 0
+    assert np.array_equal(np.isnan(got), np.isnan(want[0]))
+    ok = ~np.isnan(want[0])
+    assert np.abs(got[ok] - want[0][ok]).max() <= 1e-12
+    # The same lattice with the default Newton settings locates every node.
+    prob2 = orc.Problem(shape, 1)
+    orc_rc2, want2, ost2 = orc.reconstruct(prob2, disp, fields)
+    assert orc_rc2 == 0 and ost2["newton_fail"] == 0
+
+
+@pytest.mark.parametrize("name,wl,n_total,k", [
+    ("swirl256_f32", W.swirl_three_fields(256, value_prec="f32"), 40, 17),
+    ("swirl256_f64", W.swirl_three_fields(256, value_prec="f64"), 40, 23),
+    ("deform3d64_f64", W.deform3d_slotted_sphere(64), 12, 5),
+    ("deform3d64_f32", W.deform3d_slotted_sphere(64, value_prec="f32"), 12, 7),
+])
+def test_checkpoint_resume_is_bitwise(B, torch, tmp_path, name, wl, n_total, k):
+    """The state at a reconstruction boundary is the fields and the time (the
+    lattice is reset), so N steps equal k steps, a save and load, and N - k
+    more steps.  The time steps of these workloads are dyadic, so the resumed
+    run's step times t0 + k dt + j dt are the uninterrupted run's exactly."""
+    say("checkpoint", name, n_total, k)
+    t0 = 0.0
+    g = B.Grid.from_workload(wl)
+    full = g.advance(g.new_fields(stored_values(wl)), t0, wl.dt, n_total)
+    rc, _ = g.sync()
+    assert rc == 0
+    full = [f.cpu().numpy() for f in full]
+    part = g.advance(g.new_fields(stored_values(wl)), t0, wl.dt, k)
+    rc, _ = g.sync()
+    assert rc == 0
+    path = os.path.join(tmp_path, "state.npz")
+    np.savez(path, t=t0 + k * wl.dt, **{"f%d" % f: x.cpu().numpy() for f, x in enumerate(part)})
+    del g, part
+    ck = np.load(path, allow_pickle=False)
+    g2 = B.Grid.from_workload(wl)
+    x = [torch.as_tensor(ck["f%d" % f], device=g2.device).contiguous()
+         for f in range(wl.nfields)]
+    out = g2.advance(x, float(ck["t"]), wl.dt, n_total - k)
+    rc, _ = g2.sync()
+    assert rc == 0
+    for a, b in zip(out, full):
+        assert np.array_equal(a.cpu().numpy(), b)

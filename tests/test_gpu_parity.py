@@ -382,15 +382,14 @@ def test_full_size_3d_sampled(B, torch, orc, which):
     ("swirl96_f64", W.swirl_three_fields(96, value_prec="f64")),
     ("swirl70_f64", W.swirl_three_fields(70, value_prec="f64")),
 ])
-def test_2d_limiter_paths_agree_bitwise(B, torch, name, wl, monkeypatch):
+def test_2d_limiter_paths_agree_bitwise(B, torch, name, wl):
     """2-D grids take the limiter flags either inside the reconstruction
     tiles or from the separate order-word pass (quad kernels when rows are a
     multiple of 4, scalar ones otherwise); both give the same orders, so the
     results are bitwise equal."""
     outs = []
-    for words in ("0", "1"):
-        monkeypatch.setenv("SL_LIMITER_WORDS", words)
-        out, st, rc, _ = gpu_run(B, torch, wl, nsteps=3, t0=1.1)
+    for where in (B.SL_LIMITER_IN_TILES, B.SL_LIMITER_ORDER_WORDS):
+        out, st, rc, _ = gpu_run(B, torch, wl, nsteps=3, t0=1.1, limiter_pass=where)
         assert rc == 0
         outs.append((out, st["order_hist"]))
     (a, ha), (b, hb) = outs

@@ -146,3 +146,129 @@ def test_stream_driver_completes(torch, S):
     say(rep)
     assert rep["status"] == 0 and rep["requests"] == 24
     assert rep["latency_p99_ms"] >= rep["latency_p50_ms"] > 0
+
+
+# --------------------------------------------------------------------------
+# Served requests against the oracle at the serving mix's sizes.
+
+def _golden():
+    import importlib.util
+    import os
+    here = os.path.dirname(os.path.abspath(__file__))
+    spec = importlib.util.spec_from_file_location(
+        "make_oracle_runs", os.path.join(here, "golden", "make_oracle_runs.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod, os.path.join(here, "golden")
+
+
+def _serve_all(torch, S, reqs, prec, budget=3 << 30):
+    """Admit every (request, nsteps) pair into one server, half of them after
+    two ticks, run to completion; returns {index: fields as FP64 numpy}."""
+    from paper_1410_2817_amd import binding as B
+    dt_ = torch.float32 if prec == "f32" else torch.float64
+    srv = S.Server(budget, max_requests=len(reqs) + 1, max_inflight=2)
+    dev = srv.device
+    ids, got = {}, {}
+
+    def admit(i):
+        req, nsteps = reqs[i]
+        desc, _ = B.make_desc(req.shape, req.nfields, value_prec=prec, order_max=2,
+                              limiter=True, vel_kind=W.VEL_FOURIER, vel_params=[1.0],
+                              modes=req.modes)
+        f = [torch.as_tensor(x, device=dev).to(dt_).contiguous() for x in req.fields()]
+        sid = srv.admit(desc, f, req.dt, nsteps)
+        assert sid is not None, ("no room", i)
+        ids[sid] = i
+
+    half = (len(reqs) + 1) // 2
+    for i in range(half):
+        admit(i)
+    srv.tick()
+    srv.tick()
+    for i in range(half, len(reqs)):
+        admit(i)
+    while len(got) < len(reqs):
+        srv.tick()
+        for sid in srv.poll():
+            i = ids[sid]
+            req = reqs[i][0]
+            out = [torch.empty(req.shape, dtype=dt_, device=dev) for _ in range(req.nfields)]
+            srv.fetch(sid, out)
+            torch.cuda.synchronize()
+            got[i] = [o.double().cpu().numpy() for o in out]
+    rc, st = srv.sync()
+    assert rc == 0 and st["search_fail"] == 0 and st["newton_fail"] == 0, (rc, st)
+    srv.close()
+    return got
+
+
+SERVED = ["serve_mix128", "serve_mix256", "serve_mix512", "serve_mix1024",
+          "serve_mix2048", "serve2048_50"]
+
+
+def test_served_fp64_runs_match_stored_oracle_runs(torch, S):
+    """FP64 requests of every side of the serving mix (and a 2048^2 one for
+    50 steps), served together with staggered admission, against the
+    oracle's runs of the same requests (tests/golden/oracle_serve_*.npz) at
+    the stored sample of nodes and by each field's whole-grid L1 norm."""
+    mod, gold = _golden()
+    import os
+    reqs = [(mod.served_request(n), mod.SERVED[n][2]) for n in SERVED]
+    say("served fp64", [(r.n, r.nfields, k) for r, k in reqs])
+    got = _serve_all(torch, S, reqs, "f64")
+    for i, name in enumerate(SERVED):
+        ref = np.load(os.path.join(gold, "oracle_%s.npz" % name), allow_pickle=False)
+        assert int(ref["steps"]) == reqs[i][1]
+        nodes, want = ref["nodes"], ref["values"]
+        num = den = 0.0
+        for f, fld in enumerate(got[i]):
+            a = fld.ravel()[nodes]
+            num += float(np.abs(a - want[:, f]).sum())
+            den += float(np.abs(want[:, f]).sum())
+            norm = abs(np.abs(fld).sum() - ref["l1"][f]) / ref["l1"][f]
+            assert norm <= 1e-12, (name, f, norm)
+        say("  ", name, "rel L1 %.3e" % (num / den))
+        assert num / den <= 1e-12, (name, num / den)
+
+
+def test_served_fp32_steps_match_oracle_steps(torch, S, orc):
+    """FP32 requests of every side: each is served twice in the same mix,
+    for n - 1 and for n steps; one oracle step from the (n - 1)-step result
+    must give the n-step result within the FP32 tolerance (whole grids up to
+    512^2, sampled nodes above)."""
+    mod, _ = _golden()
+    base = [(mod.served_request(n), mod.SERVED[n][2]) for n in SERVED]
+    reqs = []
+    for r, k in base:
+        reqs += [(r, k - 1), (r, k)]
+    say("served fp32 pairs", [(r.n, k) for r, k in reqs])
+    got = _serve_all(torch, S, reqs, "f32")
+    rng = np.random.Generator(np.random.PCG64(23))
+    for j, (r, k) in enumerate(base):
+        prev, last = got[2 * j], got[2 * j + 1]
+        wl = r.workload
+        wl.fields = prev
+        prob = oracle_problem(orc, wl)
+        t = (k - 1) * r.dt
+        if r.n <= 512:
+            rc, want, _ = orc.step(prob, t, r.dt, prev)
+            assert rc == 0
+            pairs = [(a.ravel(), b.ravel()) for a, b in zip(last, want)]
+        else:
+            f0 = prev[0].ravel()
+            edge = np.nonzero(np.abs(np.diff(f0, append=f0[:1])) > 0.1 * np.abs(f0).max())[0]
+            nodes = np.unique(np.concatenate([
+                rng.integers(0, r.nodes, 3000),
+                rng.choice(edge, min(1500, edge.size), replace=False)])).astype(np.int64)
+            rc, vals, _ = orc.step_sampled(prob, t, r.dt, prev, nodes)
+            assert rc == 0
+            pairs = [(a.ravel()[nodes], vals[:, f]) for f, a in enumerate(last)]
+        num = den = 0.0
+        for f, (a, b) in enumerate(pairs):
+            d = np.abs(a - b)
+            assert d.max() <= 1e-5 * np.abs(b).max(), (r.n, f, float(d.max()))
+            num += float(d.sum())
+            den += float(np.abs(b).sum())
+        say("  side", r.n, "step", k - 1, "->", k, "rel L1 %.3e" % (num / den))
+        assert num / den <= 1e-5

@@ -274,3 +274,26 @@ def test_sampled_step_equals_the_step(orc, case):
     assert rc3 == 0 and np.array_equal(part, got[::7])
     # the run moved things: not an identity
     assert any(not np.array_equal(want[f], fields[f]) for f in range(wl.nfields))
+
+
+# --------------------------------------------------------------------------
+# FP32 storage between steps (the values the FP32-value form carries).
+
+def test_f32_storage_run_is_steps_with_rounding_between(orc):
+    wl = W.swirl_three_fields(40, value_prec="f32")
+    prob = _problem(orc, wl)
+    f0 = [np.asarray(f, np.float32).astype(np.float64) for f in wl.fields]
+    rc, got, _ = orc.run(prob, 0.3, wl.dt, 5, f0, store="f32")
+    assert rc == 0
+    cur = [f.copy() for f in f0]
+    for s in range(5):
+        rc, cur, _ = orc.run(prob, 0.3 + s * wl.dt, wl.dt, 1, cur)
+        assert rc == 0
+        cur = [np.asarray(f, np.float32).astype(np.float64) for f in cur]
+    for a, b in zip(got, cur):
+        assert np.array_equal(a, b)
+        assert np.array_equal(a, a.astype(np.float32).astype(np.float64))
+    # without rounding the values are not all FP32 numbers
+    rc, plain, _ = orc.run(prob, 0.3, wl.dt, 5, f0)
+    assert any(not np.array_equal(p, p.astype(np.float32).astype(np.float64)) for p in plain)
+    assert max(np.abs(p - q).max() for p, q in zip(plain, got)) < 1e-5
