@@ -755,22 +755,40 @@ def gpu_vs_oracle(wl, stored, steps, ofields):
             "linf": [float(np.abs(g - o).max()) for g, o in zip(got, ofields)]}
 
 
+SERVING_MODES = (("queued", 4), ("queued", 1), ("batched", 1))
+
+
 def run_serving(count: int, budget_gib: float):
     """Serving mix: `count` seeded requests (2-D periodic grids with sides in
     {128, ..., 2048}, 1-4 fields, 10-50 steps of a 16-mode Fourier flow, FP32
     values / FP64 positions) through the continuous-batching server with an
     HBM budget of `budget_gib`.  First all requests arrive at once (capacity),
-    then with Poisson arrivals at 0.7 x that capacity (latency)."""
+    then with Poisson arrivals at 0.7 x that capacity (latency).  Each launch
+    mode of the server is measured (SERVING_MODES: queued launches of 4 and 1
+    steps from device-side tile queues, and one batched launch per tick); the
+    first is reported at the top level, all under "modes"."""
+    res = None
+    modes = {}
+    for mode, window in SERVING_MODES:
+        r = _serving_mode(count, budget_gib, mode, window)
+        modes["%s_w%d" % (mode, window)] = r
+        if res is None:
+            res = dict(r)
+    res["modes"] = modes
+    return res
+
+
+def _serving_mode(count, budget_gib, mode, window):
     from paper_1410_2817_amd import serving as S
     from paper_1410_2817_amd import workloads as W
     budget = int(budget_gib * (1 << 30))
     burst = W.serving_stream(seed=0, count=count, rate=1e9)
     for r in burst:
         r.arrival = 0.0
-    cap = S.run_stream(burst, budget, max_requests=256)
+    cap = S.run_stream(burst, budget, max_requests=256, mode=mode, window=window)
     rate = 0.7 * count / cap["makespan_s"]
     rep = S.run_stream(W.serving_stream(seed=0, count=count, rate=rate), budget,
-                       max_requests=256)
+                       max_requests=256, mode=mode, window=window)
     keep = ("latency_p50_ms", "latency_p99_ms", "latency_mean_ms", "queue_wait_p50_ms",
             "queue_wait_p99_ms", "node_updates_per_s", "makespan_s", "ticks", "status")
     # Whole-job effective HBM rate of the capacity run: the algorithmic bytes of
@@ -780,7 +798,7 @@ def run_serving(count: int, budget_gib: float):
     alg = sum(r.nodes * r.nsteps * (recon_bytes_per_node(2, r.nfields, 4) + traj_bytes_per_node(2))
               for r in burst)
     eff = alg / cap["makespan_s"] / 1e9
-    return {"requests": count, "budget_gib": budget_gib,
+    return {"mode": mode, "window": window, "requests": count, "budget_gib": budget_gib,
             "capacity_node_updates_per_s": cap["node_updates_per_s"],
             "capacity_requests_per_s": count / cap["makespan_s"],
             "capacity_effective_hbm_gbs": eff, "capacity_effective_hbm_frac": eff / HBM_PEAK_GBS,

@@ -340,8 +340,9 @@ int sl_server_admit(sl_server *server, const sl_grid_desc *desc,
                     const void *const *fields_in, double t0, double dt, int nsteps,
                     int64_t *id);
 
-/* Advance every active request by one step; *active (may be NULL) receives
- * the number still stepping afterwards.  Errors: SL_EINVAL, SL_EHIP. */
+/* Advance every active request by one step (up to `window` steps in
+ * SL_SERVE_QUEUED mode, see sl_server_set_mode); *active (may be NULL)
+ * receives the number still stepping afterwards.  Errors: SL_EINVAL, SL_EHIP. */
 int sl_server_tick(sl_server *server, int *active);
 
 /* Report up to max_ids requests whose last step has completed on the device
@@ -353,9 +354,27 @@ int sl_server_poll(sl_server *server, int64_t *done_ids, int max_ids, int *ndone
  * or unfinished id. */
 int sl_server_fetch(sl_server *server, int64_t id, void *const *fields_out);
 
-/* Wait for the stream; report and clear the device counters accumulated by
- * all requests since the last call (status as for sl_sync). */
+/* Wait for the stream; report and clear the counters accumulated by all
+ * requests since the last call (nodes and steps count request steps; status
+ * as for sl_sync, and SL_EHIP if a queued launch gave up waiting). */
 int sl_server_sync(sl_server *server, sl_stats *stats);
+
+/* How sl_server_tick launches the work of a tick.
+ *   SL_SERVE_BATCHED  one batched reconstruction launch per value precision
+ *                     and field count, every request one step per tick
+ *                     (window must be 1).  The default.
+ *   SL_SERVE_QUEUED   one launch per value precision and field count runs
+ *                     `window` (1..16) steps of every request of the group:
+ *                     the tiles of all those steps sit in device-side queues
+ *                     (one per XCD, in step order), each workgroup takes the
+ *                     next tile of the queue of the XCD it runs on, and a
+ *                     request's step starts once every tile of its previous
+ *                     step is done (device-side counts, no host round trip).
+ *                     Requests with more than 4 fields keep batched
+ *                     launches, one step per tick.
+ * Results are bitwise the same in both modes.  Errors: SL_EINVAL. */
+enum { SL_SERVE_BATCHED = 0, SL_SERVE_QUEUED = 1 };
+int sl_server_set_mode(sl_server *server, int mode, int window);
 
 /* Occupancy of the server. */
 int sl_server_info(const sl_server *server, sl_server_status *out);

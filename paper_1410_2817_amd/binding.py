@@ -22,6 +22,7 @@ SL_FP64, SL_FP32 = 0, 1
 SL_RK4, SL_RK3_WILLIAMSON = 0, 1
 SL_SRC_NONE, SL_SRC_SHALLOW_WATER = 0, 1
 SL_LIMITER_AUTO, SL_LIMITER_IN_TILES, SL_LIMITER_ORDER_WORDS = 0, 1, 2
+SL_SERVE_BATCHED, SL_SERVE_QUEUED = 0, 1
 SL_MAX_FIELDS = 8
 SL_MAX_MODES = 32
 
@@ -103,6 +104,7 @@ SIGNATURES = {
     "sl_server_fetch": (C.c_int, [_VP, C.c_int64, C.POINTER(_VP)]),
     "sl_server_sync": (C.c_int, [_VP, C.POINTER(SlStats)]),
     "sl_server_info": (C.c_int, [_VP, C.POINTER(SlServerStatus)]),
+    "sl_server_set_mode": (C.c_int, [_VP, C.c_int, C.c_int]),
     "sl_error_detail": (C.c_char_p, []),
 }
 
@@ -332,3 +334,4 @@ class Grid:
                                 C.c_void_p(_stream_handle(stream)), C.byref(in_b)),
               "sl_advance")
         return b if in_b.value else a
+

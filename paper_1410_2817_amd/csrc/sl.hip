@@ -44,6 +44,8 @@ __global__ void zero_kernel(unsigned long long* p, int n) {
 
 }  // namespace sl
 
+
+
 // ===========================================================================
 // Host side: descriptors, validation, launches.
 
@@ -726,8 +728,7 @@ int sl_sync(sl_grid* gr, void* workspace, void* stream, sl_stats* out) {
     out->nonfinite = (int64_t)host[sl::ST_NONFINITE];
     out->order_hist[0] = (int64_t)host[sl::ST_ORDER0];
     out->order_hist[1] = (int64_t)host[sl::ST_ORDER1];
-    const int64_t located = nodes - out->search_fail - out->newton_fail;
-    out->order_hist[2] = located * gr->desc.nfields - out->order_hist[0] - out->order_hist[1];
+    out->order_hist[2] = (int64_t)host[sl::ST_ORDER2];
     out->walked = (int64_t)host[sl::ST_WALKED];
     out->scanned = (int64_t)host[sl::ST_SCANNED];
     out->steps = gr->steps_launched;

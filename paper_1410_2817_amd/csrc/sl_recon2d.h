@@ -3,8 +3,11 @@
 // A workgroup of 256 work-items owns a TX x TY tile of mesh nodes.  It reads
 // the displacement of its own nodes (the start guesses of the element walk),
 // reduces their departure cells to a bounding box, and stages into LDS the
-// lattice displacements of that box (plus a margin for the walk) and the field
-// values of the box grown by one node (the jump criterion needs neighbours).
+// field values of that box (plus a margin for the walk) grown by one node
+// (the jump criterion needs neighbours).  The element solves read the
+// vertex displacements through the caches: staging them in LDS as well
+// measured slower (51.4 -> 54.5 us per 1024^2 launch, 0.608 -> 0.639 ms at
+// 4096^2), the loads being few and the L1/L2 hit rate high.
 // The jump flags of the box are computed once from the staged values and
 // OR-reduced over the quintic and cubic stencil windows by separable passes,
 // so each node reads its order mask with two LDS loads.  Every node then runs
@@ -28,12 +31,6 @@ namespace sl {
 constexpr int kTileThreads = 256;
 constexpr int kWalkMargin = 1;   // extra cells staged around the start cells
 constexpr int kNumXcd = 8;
-#ifndef SL_STAGE_DISP
-#define SL_STAGE_DISP 0
-#endif
-// Stage the departure box's displacements in LDS (1) or let the element
-// solves read them through the caches (0).
-constexpr bool kStageDisp = SL_STAGE_DISP;
 
 // 16 x 16 tiles, one mesh node per work-item: small LDS boxes and few live
 // registers keep four workgroups resident per CU, which hides the latency of
@@ -48,8 +45,7 @@ struct Tile2D {
   // start cells); larger boxes take the global path.  Keeping the allocation
   // tight lets many workgroups share a CU's 160 KB.
   static constexpr int BOX = TX + 5 + 2 * kWalkMargin + 3;
-  static constexpr int RAW = (kStageDisp ? BOX * BOX * 16 : 0) +
-                             (BOX + 2) * (BOX + 2) * NF * (int)sizeof(T) + NF * BOX * 4 + 64;
+  static constexpr int RAW = (BOX + 2) * (BOX + 2) * NF * (int)sizeof(T) + NF * BOX * 4 + 64;
   static constexpr int CAP = 60 * 1024;  // stay under the 64 KB workgroup limit
   static constexpr int LDS_BYTES = (RAW + 255) / 256 * 256 < CAP ? (RAW + 255) / 256 * 256 : CAP;
 };
@@ -68,27 +64,6 @@ __device__ __forceinline__ int xcd_tile(int b, int nblocks) {
   const int q = nblocks / kNumXcd, rem = nblocks % kNumXcd;
   return xcd * q + (xcd < rem ? xcd : rem) + local;
 }
-
-// Displacement accessor: LDS box first, global memory outside it.
-struct BoxDisp2D {
-  const double* __restrict__ ldx;
-  const double* __restrict__ ldy;
-  int bx0, by0, BX, BY;
-  const double* __restrict__ gdisp;
-  GridArgs g;
-  __device__ __forceinline__ void operator()(const int* v, double* d) const {
-    const int lx = v[0] - bx0, ly = v[1] - by0;
-    if ((unsigned)lx < (unsigned)BX && (unsigned)ly < (unsigned)BY) {
-      const int i = lx + BX * ly;
-      d[0] = ldx[i];
-      d[1] = ldy[i];
-    } else {
-      const int lin = wrap_index(v[0], g.n[0]) + g.n[0] * wrap_index(v[1], g.n[1]);
-      d[0] = gdisp[lin];
-      d[1] = gdisp[(size_t)g.ntot + lin];
-    }
-  }
-};
 
 // Wrap an index known to lie near [0, n) without integer division; far
 // indices (only from pathological walks) take the general path.
@@ -127,24 +102,6 @@ __device__ __forceinline__ int element_solve_near(const GridArgs& g, const NearD
   Element<2> el;
   el.set(V);
   return el.solve(g, xi);
-}
-
-__device__ __forceinline__ int element_solve_near(const GridArgs& g, const BoxDisp2D& acc,
-                                                  const int* tgt, const int* r, double* xi) {
-  return element_solve<2>(g, acc, tgt, r, xi);
-}
-
-__device__ __forceinline__ BoxDisp2D make_disp_accessor(std::true_type, const double* ldx,
-                                                        const double* ldy, int bx0, int by0,
-                                                        int BX, int BY, const double* gdisp,
-                                                        const GridArgs& g) {
-  return BoxDisp2D{ldx, ldy, bx0, by0, BX, BY, gdisp, g};
-}
-
-__device__ __forceinline__ NearDisp2D make_disp_accessor(std::false_type, const double*,
-                                                         const double*, int, int, int, int,
-                                                         const double* gdisp, const GridArgs& g) {
-  return NearDisp2D{gdisp, g};
 }
 
 // Jump-flag bits (all fields) of the lattice node at wrapped (x, y), from
@@ -319,24 +276,21 @@ __device__ __forceinline__ void recon2d_tile(const GridArgs& g, const FieldPtrs&
   const int BX = sane ? (int)ex : 0;
   const int BY = sane ? (int)ey : 0;
   const int VX = BX + 2, VY = BY + 2;
-  const int nbox = BX * BY, nval = VX * VY;
+  const int nval = VX * VY;
   constexpr int nf = NF;
-  // LDS layout: disp x | disp y | values (nf planes) | flags | row-OR | OR
-  const size_t off_dy = kStageDisp ? (size_t)nbox * 8 : 0;
-  const size_t off_val = kStageDisp ? off_dy + (size_t)nbox * 8 : 0;
+  // LDS layout: values (nf planes) | flag row words
+  const size_t off_val = 0;
   // Jump flags are kept as one 32-bit word per field and box row (bit x set
   // when node (x, row) is flagged), so the box may be at most 32 wide.
   const size_t off_bits = off_val + (((size_t)nf * nval * sizeof(T) + 15) & ~(size_t)15);
   const size_t need = off_bits + (size_t)nf * BY * 4;
   const bool staged = sane && BX <= 32 && need <= (size_t)C::LDS_BYTES;
 
-  double* ldx = reinterpret_cast<double*>(smem);
-  double* ldy = reinterpret_cast<double*>(smem + off_dy);
   T* lval = reinterpret_cast<T*>(smem + off_val);
   unsigned* lbits = reinterpret_cast<unsigned*>(smem + off_bits);  // [f][row]
 
   if (staged) {
-    // 2. Stage displacements and values.  Work-items cover the box as rows of
+    // 2. Stage the values.  Work-items cover the box as rows of
     // 32 (one wave = two rows), so no integer division is needed; wrapped
     // coordinates are advanced incrementally from the box origin.
     const int sx_lane = threadIdx.x % 32, sy_lane = threadIdx.x / 32;
@@ -364,13 +318,6 @@ __device__ __forceinline__ void recon2d_tile(const GridArgs& g, const FieldPtrs&
 #pragma unroll
         for (int f = 0; f < nf; ++f)
           lval[(size_t)f * nval + vi] = static_cast<const T*>(fp.in[f])[lin];
-        // The displacement box is the value box without its one-node rim.
-        const int bx = vx - 1, by = vy - 1;
-        if (kStageDisp && bx >= 0 && by >= 0 && bx < BX && by < BY) {
-          const int i = bx + BX * by;
-          ldx[i] = gdisp[lin];
-          ldy[i] = gdisp[(size_t)g.ntot + lin];
-        }
       }
     }
     __syncthreads();
@@ -407,9 +354,8 @@ __device__ __forceinline__ void recon2d_tile(const GridArgs& g, const FieldPtrs&
     __syncthreads();
   }
 
-  const auto acc = make_disp_accessor(std::integral_constant<bool, kStageDisp>{}, ldx, ldy, bx0,
-                                      by0, staged ? BX : 0, staged ? BY : 0, gdisp, g);
-  int walked_any = 0, scanned_any = 0, sfail = 0, nfail = 0, c0 = 0, c1 = 0, bad = 0;
+  const NearDisp2D acc{gdisp, g};
+  int walked_any = 0, scanned_any = 0, sfail = 0, nfail = 0, c0 = 0, c1 = 0, c2 = 0, bad = 0;
 
 #pragma unroll 1
   for (int k = 0; k < C::NPT; ++k) {
@@ -501,6 +447,7 @@ __device__ __forceinline__ void recon2d_tile(const GridArgs& g, const FieldPtrs&
     if (__ballot(low) == 0ull) {
       c0 += g.order_max == 0 ? nf : 0;
       c1 += g.order_max == 1 ? nf : 0;
+      c2 += g.order_max == 2 ? nf : 0;
 #pragma unroll
       for (int f = 0; f < nf; ++f) field_value(f, w2x, w2y);
     } else {
@@ -513,6 +460,7 @@ __device__ __forceinline__ void recon2d_tile(const GridArgs& g, const FieldPtrs&
         const int m = pick_order(g.order_max, or6, or4, f);
         c0 += m == 0;
         c1 += m == 1;
+        c2 += m == 2;
         if (__ballot(m != g.order_max) == 0ull) {
           field_value(f, w2x, w2y);
           continue;
@@ -538,15 +486,17 @@ __device__ __forceinline__ void recon2d_tile(const GridArgs& g, const FieldPtrs&
   // is at most 64 * 8), then one LDS atomic per wave.
   const unsigned p0 = wave_sum((unsigned)walked_any | ((unsigned)scanned_any << 16));
   const unsigned p1 = wave_sum((unsigned)sfail | ((unsigned)nfail << 16));
-  const unsigned p2 = wave_sum((unsigned)c0 | ((unsigned)c1 << 16));
+  // Order counts per wave fit 10 bits each (at most 64 lanes x 8 fields).
+  const unsigned p2 = wave_sum((unsigned)c0 | ((unsigned)c1 << 10) | ((unsigned)c2 << 20));
   const unsigned p3 = wave_sum((unsigned)bad);
   if (__lane_id() == 0) {
     if (p0 & 0xffffu) atomicAdd(&s_cnt[ST_WALKED], p0 & 0xffffu);
     if (p0 >> 16) atomicAdd(&s_cnt[ST_SCANNED], p0 >> 16);
     if (p1 & 0xffffu) atomicAdd(&s_cnt[ST_SEARCH_FAIL], p1 & 0xffffu);
     if (p1 >> 16) atomicAdd(&s_cnt[ST_NEWTON_FAIL], p1 >> 16);
-    if (p2 & 0xffffu) atomicAdd(&s_cnt[ST_ORDER0], p2 & 0xffffu);
-    if (p2 >> 16) atomicAdd(&s_cnt[ST_ORDER1], p2 >> 16);
+    if (p2 & 0x3ffu) atomicAdd(&s_cnt[ST_ORDER0], p2 & 0x3ffu);
+    if ((p2 >> 10) & 0x3ffu) atomicAdd(&s_cnt[ST_ORDER1], (p2 >> 10) & 0x3ffu);
+    if (p2 >> 20) atomicAdd(&s_cnt[ST_ORDER2], p2 >> 20);
     if (p3) atomicAdd(&s_cnt[ST_NONFINITE], p3);
   }
   __syncthreads();

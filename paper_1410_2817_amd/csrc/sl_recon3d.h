@@ -112,14 +112,13 @@ __device__ __forceinline__ T zsum3d_linear(const T* wx, const T* wy, const T* wz
   return acc;
 }
 
-#ifndef SL_STAGE3D
-#define SL_STAGE3D 1
-#endif
-
 // LDS box of field values for one tile: the tile, the quintic stencil (5),
 // one cell of walk margin on each side and one of spread in the start cells.
 // Boxes of more than 48 KB (many fields, or FP64 with more than one field)
-// are not staged; their taps are read through the caches.
+// are not staged; their taps are read through the caches.  Reading every tap
+// through the caches measured 2x slower on the deformational flow (8.3 ->
+// 16.5 ms per 512^3 launch) and 3x on the Fourier flow (2.0 -> 6.0 ms per
+// 256^3 launch).
 template <typename T, int NF>
 struct Box3D {
   static constexpr int BX = Tile3D::TX + 8;
@@ -133,7 +132,7 @@ struct Box3D {
   // pitch (occupancy matters more there than the bank conflicts).
   static constexpr int PX = bytes(BX + 8) <= 40 * 1024 ? BX + 8 : BX;
   static constexpr int NB = PX * BY * BZ;  // elements per field
-  static constexpr bool STAGE = SL_STAGE3D && bytes(PX) <= 48 * 1024;
+  static constexpr bool STAGE = bytes(PX) <= 48 * 1024;
   // Waves per SIMD the register budget targets: four workgroups per CU when
   // their boxes fit 160 KB of LDS, three otherwise.
   static constexpr int WAVES = STAGE && bytes(PX) <= 40 * 1024 ? 4 : 3;
@@ -256,7 +255,7 @@ __global__ __launch_bounds__(kTileThreads, (Box3D<T, NF>::WAVES)) void recon3d_k
     __syncthreads();
   }
 
-  int walked_any = 0, scanned_any = 0, sfail = 0, nfail = 0, c0 = 0, c1 = 0, bad = 0;
+  int walked_any = 0, scanned_any = 0, sfail = 0, nfail = 0, c0 = 0, c1 = 0, c2 = 0, bad = 0;
   if (act) {
     const NearDisp3D acc{gdisp, g};
     double xi[3];
@@ -357,6 +356,7 @@ __global__ __launch_bounds__(kTileThreads, (Box3D<T, NF>::WAVES)) void recon3d_k
       if (__ballot(low) == 0ull) {
         c0 += g.order_max == 0 ? nf : 0;
         c1 += g.order_max == 1 ? nf : 0;
+        c2 += g.order_max == 2 ? nf : 0;
         T w[3][6];
 #pragma unroll
         for (int a = 0; a < 3; ++a) zspline_weights<T>(g.order_max, t[a], w[a]);
@@ -371,6 +371,7 @@ __global__ __launch_bounds__(kTileThreads, (Box3D<T, NF>::WAVES)) void recon3d_k
           const int m = pick_order(g.order_max, or6, or4, f);
           c0 += m == 0;
           c1 += m == 1;
+          c2 += m == 2;
           T w[3][6];
 #pragma unroll
           for (int a = 0; a < 3; ++a) zspline_weights<T>(m, t[a], w[a]);
@@ -386,15 +387,17 @@ __global__ __launch_bounds__(kTileThreads, (Box3D<T, NF>::WAVES)) void recon3d_k
   // one LDS atomic per wave, one global atomic per workgroup and counter.
   const unsigned p0 = wave_sum((unsigned)walked_any | ((unsigned)scanned_any << 16));
   const unsigned p1 = wave_sum((unsigned)sfail | ((unsigned)nfail << 16));
-  const unsigned p2 = wave_sum((unsigned)c0 | ((unsigned)c1 << 16));
+  // Order counts per wave fit 10 bits each (at most 64 lanes x 8 fields).
+  const unsigned p2 = wave_sum((unsigned)c0 | ((unsigned)c1 << 10) | ((unsigned)c2 << 20));
   const unsigned p3 = wave_sum((unsigned)bad);
   if (__lane_id() == 0) {
     if (p0 & 0xffffu) atomicAdd(&s_cnt[ST_WALKED], p0 & 0xffffu);
     if (p0 >> 16) atomicAdd(&s_cnt[ST_SCANNED], p0 >> 16);
     if (p1 & 0xffffu) atomicAdd(&s_cnt[ST_SEARCH_FAIL], p1 & 0xffffu);
     if (p1 >> 16) atomicAdd(&s_cnt[ST_NEWTON_FAIL], p1 >> 16);
-    if (p2 & 0xffffu) atomicAdd(&s_cnt[ST_ORDER0], p2 & 0xffffu);
-    if (p2 >> 16) atomicAdd(&s_cnt[ST_ORDER1], p2 >> 16);
+    if (p2 & 0x3ffu) atomicAdd(&s_cnt[ST_ORDER0], p2 & 0x3ffu);
+    if ((p2 >> 10) & 0x3ffu) atomicAdd(&s_cnt[ST_ORDER1], (p2 >> 10) & 0x3ffu);
+    if (p2 >> 20) atomicAdd(&s_cnt[ST_ORDER2], p2 >> 20);
     if (p3) atomicAdd(&s_cnt[ST_NONFINITE], p3);
   }
   __syncthreads();

@@ -125,6 +125,159 @@ void recon2d_batched_kernel(
                       logical - rt.blk_begin, rs.tiles_x, smem, nt, rs.v);
 }
 
+// ---------------------------------------------------------------------------
+// Multi-step serving kernel with a device-side work queue.
+//
+// One launch covers `window` ticks of every resident request whose values are
+// of type T and that has NF fields (NF <= kServeMaxNF; a kernel per field
+// count keeps each one's registers those of the batched kernel).  Its work is
+// a list of segments, one per (request, step), in tick order; the tiles of
+// each segment are split into 8 contiguous chunks, one per XCD, and each XCD
+// has its own queue: the concatenation of its chunks over the segments.  The
+// launch has one workgroup per tile of the whole window.  A workgroup reads
+// the XCD it runs on and takes the next tile of that XCD's queue through one
+// atomic counter (the next non-empty queue once its own is empty), so a
+// request's neighbouring tiles meet in one L2, and tiles are handed out in
+// tick order whatever order the workgroups start in.
+//
+// Steps of one request depend on each other: step s reads the fields and the
+// displacement that step s - 1 wrote, and writes into buffers step s - 1 read
+// from.  Within a launch, a request's segments after its first wait for every
+// tile of its previous segment: each finished tile of a segment that a later
+// one waits for is published with an agent-scope release (its writes reach
+// the memory all XCDs share) and a count in `done`; the waiting workgroup
+// acquires once the count has reached the segment's `need`.  A request's
+// first segment of a launch needs no wait (the launch boundary orders it
+// after the previous launch), so a one-tick launch has neither waits nor
+// fences.  Every queue hands out its tiles in tick order and a tile only
+// waits for tiles of earlier segments, which were handed to workgroups that
+// are already running, so the waits always end.  A wait that still exceeds
+// kServeSpinLimit polls (a failure elsewhere) sets `abort`; every workgroup
+// that sees it leaves, and the host reports SL_EHIP.
+//
+// (A fixed grid of workgroups that loop over the queue was tried first: with
+// the tile code inside a loop the compiler could no longer keep the
+// request's parameters in scalar registers and spilled about 60 VGPRs per
+// lane, so each workgroup takes one tile.)
+
+constexpr int kServeMaxNF = 4;  // field counts the window kernels take
+constexpr unsigned kServeSpinLimit = 1u << 23;
+
+struct ServeSeg {
+  int entry;   // table index
+  int parity;  // 0: A -> B from disp, 1: B -> A from disp2
+  int next;    // also integrate the next step's trajectories
+  int ntiles;
+  unsigned need;  // published tiles of the request before this segment starts
+  int wait;       // 1: wait for `need` (not the request's first segment here)
+  int publish;    // 1: a later segment of this launch waits for these tiles
+  double dt;
+  double tf[3];  // stage time factors of the next step's trajectories
+};
+
+__device__ __forceinline__ int xcc_id() {
+  // HW_REG_XCC_ID (register 20), bits [3:0]: the XCD this wave runs on.
+  return (int)(__builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & (kNumXcd - 1));
+}
+
+template <typename T, int NF>
+__device__ __forceinline__ void serve_tile(const ReqStatic& rs, const ServeSeg& sg, int tile,
+                                           unsigned char* smem) {
+  FieldPtrs fp;
+#pragma unroll
+  for (int f = 0; f < SL_MAX_FIELDS; ++f) {
+    fp.in[f] = sg.parity ? rs.ab.out[f] : rs.ab.in[f];
+    fp.out[f] = sg.parity ? const_cast<void*>(rs.ab.in[f]) : rs.ab.out[f];
+  }
+  NextTraj nt{};
+  if (sg.next) {
+    nt.disp = sg.parity ? rs.disp : rs.disp2;
+    nt.st.tf[0] = sg.tf[0];
+    nt.st.tf[1] = sg.tf[1];
+    nt.st.tf[2] = sg.tf[2];
+    nt.st.tf[3] = sg.tf[2];
+    nt.dt = sg.dt;
+    nt.integrator = rs.integrator;
+    nt.trig = rs.trig;
+  }
+  recon2d_tile<T, NF>(rs.g, fp, sg.parity ? rs.disp2 : rs.disp, nullptr, rs.stats, tile,
+                      rs.tiles_x, smem, nt, rs.v);
+}
+
+template <typename T, int NF>
+__global__ __launch_bounds__(kTileThreads, (tile2d_waves<T, NF>()))
+void serve_window_kernel(const ReqStatic* __restrict__ table,
+                         const ServeSeg* __restrict__ segs,
+                         const int* __restrict__ prefix,  // kNumXcd x (nseg + 1)
+                         int nseg, unsigned* __restrict__ qctr,
+                         unsigned* __restrict__ done, int* __restrict__ abort_flag) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int s_item, s_seg, s_x;
+  if (threadIdx.x == 0) {
+    const int home = xcc_id();
+    int it = 0, k = -1, x = home;
+    if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+      for (int q = 0; q < kNumXcd && k < 0; ++q) {
+        x = (home + q) & (kNumXcd - 1);
+        const int* __restrict__ pre = prefix + x * (nseg + 1);
+        if (__hip_atomic_load(&qctr[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >=
+            (unsigned)pre[nseg])
+          continue;  // drained
+        it = (int)atomicAdd(&qctr[x], 1u);
+        if (it >= pre[nseg]) continue;
+        int lo = 0, hi = nseg - 1;  // last k with pre[k] <= it
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (pre[mid] <= it) lo = mid;
+          else hi = mid - 1;
+        }
+        k = lo;
+      }
+    }
+    if (k >= 0 && segs[k].wait) {
+      const ServeSeg& sg = segs[k];
+      unsigned spins = 0;
+      while (__hip_atomic_load(&done[sg.entry], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+             sg.need) {
+        if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
+            ++spins > kServeSpinLimit) {
+          __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          k = -1;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(4);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    s_item = it;
+    s_seg = k;
+    s_x = x;
+  }
+  __syncthreads();
+  // Uniform across the workgroup: keep them (and what is loaded through
+  // them) in scalar registers.
+  const int k = __builtin_amdgcn_readfirstlane(s_seg);
+  if (k < 0) return;
+  const int it = __builtin_amdgcn_readfirstlane(s_item);
+  const int x = __builtin_amdgcn_readfirstlane(s_x);
+  const ServeSeg& sg = segs[k];
+  const ReqStatic& rs = table[sg.entry];
+  const int tile = sg.ntiles * x / kNumXcd + (it - prefix[x * (nseg + 1) + k]);
+  serve_tile<T, NF>(rs, sg, tile, smem);
+  if (sg.publish) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __hip_atomic_fetch_add(&done[sg.entry], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
+__global__ void serve_zero_kernel(unsigned* p, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
 }  // namespace sl
 
 namespace {
@@ -141,8 +294,20 @@ struct Request {
   double t0, dt;
   int64_t finish_tick;
   bool reported;
+  unsigned published;  // tiles counted in the device's done[entry] (window launches)
   void* a[SL_MAX_FIELDS];
   void* b[SL_MAX_FIELDS];
+};
+
+constexpr int kServeMaxWindow = 16;  // ticks per window launch
+// Window kernels: one per value precision and field count 1..kServeMaxNF;
+// group = precision * kServeMaxNF + nf - 1.
+constexpr int kServeGroups = 2 * sl::kServeMaxNF;
+
+// Host staging of one window launch's segment table (pinned memory).
+struct SegStage {
+  sl::ServeSeg* segs;
+  int* prefix;
 };
 
 }  // namespace
@@ -166,6 +331,24 @@ struct sl_server {
   std::vector<hipEvent_t> ev_pool;
   int64_t completed_tick;
   size_t in_use;
+  // Launch mode of sl_server_tick (sl_server_set_mode).
+  int mode;
+  int window;
+  // Window launches: the device segment table of a tick (the groups of
+  // one value precision and field count one after another) and its per-XCD
+  // prefix sums, per-group queue counters, per-entry published-tile counts
+  // and the abort flag, all in the arena header; pinned host staging, one
+  // slot per tick in flight.
+  sl::ServeSeg* dev_segs;
+  int* dev_prefix;
+  unsigned* qctr;  // kServeGroups x kNumXcd
+  unsigned* done;  // max_requests
+  int* abort_flag;
+  int max_segs;
+  std::vector<SegStage> stage;
+  void* stage_mem;
+  // Host totals since the last sl_server_sync.
+  int64_t stat_nodes, stat_steps;
 };
 
 namespace {
@@ -279,6 +462,43 @@ hipError_t launch_traj_group(sl_server* s, int vk, const sl::TickArgs& ta) {
   }
 }
 
+// The window kernel of group `grp` (value precision * kServeMaxNF + field
+// count - 1) and its dynamic LDS bytes.
+struct WindowKernel {
+  const void* fn;
+  uint32_t lds;
+};
+
+template <typename T, int NF>
+WindowKernel window_kernel_of() {
+  return {reinterpret_cast<const void*>(sl::serve_window_kernel<T, NF>),
+          (uint32_t)sl::Tile2D<T, NF>::LDS_BYTES};
+}
+
+WindowKernel window_kernel(int grp) {
+  static_assert(sl::kServeMaxNF == 4, "one case per field count");
+  switch (grp) {
+    case 0: return window_kernel_of<double, 1>();
+    case 1: return window_kernel_of<double, 2>();
+    case 2: return window_kernel_of<double, 3>();
+    case 3: return window_kernel_of<double, 4>();
+    case 4: return window_kernel_of<float, 1>();
+    case 5: return window_kernel_of<float, 2>();
+    case 6: return window_kernel_of<float, 3>();
+    default: return window_kernel_of<float, 4>();
+  }
+}
+
+// Group `grp`'s window kernel over `tiles` tiles (one workgroup each).
+hipError_t launch_window(sl_server* s, int grp, const sl::ServeSeg* segs, const int* prefix,
+                         int nseg, int tiles, unsigned* qctr) {
+  const WindowKernel wk = window_kernel(grp);
+  const sl::ReqStatic* table = s->table;
+  void* args[] = {&table, &segs, &prefix, &nseg, &qctr, &s->done, &s->abort_flag};
+  return hipExtLaunchKernel(wk.fn, dim3((unsigned)tiles), dim3(sl::kTileThreads), args, wk.lds,
+                            s->stream, nullptr, nullptr, 0);
+}
+
 // Stage time factors of step `k` of request r.
 void stage_times(const Request& r, int k, double tf[3]) {
   const sl_grid* gr = r.grid;
@@ -310,7 +530,14 @@ int sl_server_create(void* arena, size_t arena_bytes, int max_requests, int max_
     return SL_EINVAL;
   const size_t table_bytes = align_up(sizeof(sl::ReqStatic) * (size_t)max_requests);
   const size_t stats_bytes = align_up(sizeof(unsigned long long) * sl::kStatWords);
-  if (arena_bytes < table_bytes + stats_bytes + kAlign) return SL_EINVAL;
+  const int max_segs = max_requests * kServeMaxWindow;
+  const size_t seg_bytes = align_up(sizeof(sl::ServeSeg) * (size_t)max_segs);
+  const size_t prefix_bytes =
+      align_up(sizeof(int) * sl::kNumXcd * (size_t)(max_segs + kServeGroups));
+  const size_t ctl_bytes = align_up(
+      sizeof(unsigned) * (kServeGroups * sl::kNumXcd + (size_t)max_requests) + sizeof(int));
+  const size_t persist_bytes = seg_bytes + prefix_bytes + ctl_bytes;
+  if (arena_bytes < table_bytes + stats_bytes + persist_bytes + kAlign) return SL_EINVAL;
   sl_server* s = new (std::nothrow) sl_server();
   if (!s) return SL_ENOMEM;
   s->arena = static_cast<char*>(arena);
@@ -321,20 +548,48 @@ int sl_server_create(void* arena, size_t arena_bytes, int max_requests, int max_
   s->table = reinterpret_cast<sl::ReqStatic*>(s->arena);
   s->stats = reinterpret_cast<unsigned long long*>(s->arena + table_bytes);
   s->host_table.resize(max_requests);
-  const size_t heap = table_bytes + stats_bytes;
+  char* ph = s->arena + table_bytes + stats_bytes;
+  s->dev_segs = reinterpret_cast<sl::ServeSeg*>(ph);
+  s->dev_prefix = reinterpret_cast<int*>(ph + seg_bytes);
+  s->qctr = reinterpret_cast<unsigned*>(ph + seg_bytes + prefix_bytes);
+  s->done = s->qctr + kServeGroups * sl::kNumXcd;
+  s->abort_flag = reinterpret_cast<int*>(s->done + max_requests);
+  s->max_segs = max_segs;
+  s->mode = SL_SERVE_BATCHED;
+  s->window = 1;
+  s->stage_mem = nullptr;
+  s->stat_nodes = s->stat_steps = 0;
+  const size_t heap = table_bytes + stats_bytes + persist_bytes;
   s->free_blocks[heap] = (arena_bytes - heap) / kAlign * kAlign;
   for (int e = max_requests - 1; e >= 0; --e) s->free_entries.push_back(e);
   s->next_id = 1;
   s->tick = 0;
   s->completed_tick = 0;
   s->in_use = 0;
-  // Counters start at zero.
-  const int rc =
-      hipMemsetAsync(s->stats, 0, sizeof(unsigned long long) * sl::kStatWords, s->stream) ==
-              hipSuccess
-          ? SL_OK
-          : SL_EHIP;
+  // Counters, queue counters, published counts and the abort flag start at
+  // zero.
+  int rc = SL_OK;
+  {
+    sl::serve_zero_kernel<<<8, 256, 0, s->stream>>>(reinterpret_cast<unsigned*>(s->stats),
+                                                   2 * sl::kStatWords);
+    const int nctl = (int)(ctl_bytes / sizeof(unsigned));
+    sl::serve_zero_kernel<<<(nctl + 255) / 256, 256, 0, s->stream>>>(s->qctr, nctl);
+    if (hipGetLastError() != hipSuccess) rc = SL_EHIP;
+  }
+  if (rc == SL_OK) {
+    const size_t slot = seg_bytes + prefix_bytes;
+    const int nslots = max_inflight + 1;
+    if (hipHostMalloc(&s->stage_mem, slot * (size_t)nslots, hipHostMallocDefault) != hipSuccess)
+      rc = SL_EHIP;
+    for (int k = 0; k < nslots && rc == SL_OK; ++k) {
+      char* base = static_cast<char*>(s->stage_mem) + slot * (size_t)k;
+      s->stage.push_back({reinterpret_cast<sl::ServeSeg*>(base),
+                          reinterpret_cast<int*>(base + seg_bytes)});
+    }
+  }
   if (rc != SL_OK) {
+    (void)hipStreamSynchronize(s->stream);
+    if (s->stage_mem) (void)hipHostFree(s->stage_mem);
     delete s;
     return rc;
   }
@@ -349,6 +604,7 @@ int sl_server_destroy(sl_server* s) {
   for (hipEvent_t e : s->ev_pool) (void)hipEventDestroy(e);
   for (auto& r : s->active) sl_destroy_grid(r.grid);
   for (auto& r : s->finished) sl_destroy_grid(r.grid);
+  if (s->stage_mem) (void)hipHostFree(s->stage_mem);
   delete s;
   return SL_OK;
 }
@@ -425,6 +681,11 @@ int sl_server_admit(sl_server* s, const sl_grid_desc* desc, const void* const* f
 
   hipError_t e = hipMemcpyAsync(s->table + r.entry, &hs, sizeof(hs), hipMemcpyHostToDevice,
                                 s->stream);
+  if (e == hipSuccess) {
+    // The entry's published-tile count restarts (window launches).
+    sl::serve_zero_kernel<<<1, 64, 0, s->stream>>>(s->done + r.entry, 1);
+    e = hipGetLastError();
+  }
   if (e == hipSuccess && trig) {
     const int axes = gr->g.n[0] + gr->g.n[1];
     sl::trig_table_kernel<2><<<(axes + sl::kBlock - 1) / sl::kBlock, sl::kBlock, 0, s->stream>>>(
@@ -480,9 +741,94 @@ int sl_server_tick(sl_server* s, int* active) {
     ta.total_blocks = blocks;
     err = launch_traj_group(s, vk, ta);
   }
-  // Reconstructions, batched per (value precision, field count).
-  order.resize(s->active.size());
-  for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+  // Steps of each request this tick: up to `window` for the requests the
+  // window kernels take, one for the others.
+  const bool windowed = s->mode == SL_SERVE_QUEUED;
+  auto in_window = [&](const Request& r) {
+    return windowed && r.grid->desc.nfields <= sl::kServeMaxNF;
+  };
+  std::vector<int> nstep(s->active.size(), 1);
+  for (size_t i = 0; i < s->active.size(); ++i) {
+    const Request& r = s->active[i];
+    if (in_window(r)) nstep[i] = std::min(s->window, r.nsteps - r.done);
+  }
+  // Window launches, one per (value precision, field count) group; the
+  // tick's segment table holds the groups one after another.
+  if (windowed && err == hipSuccess) {
+    SegStage& st = s->stage[(size_t)(s->tick % (int64_t)s->stage.size())];
+    int seg0[kServeGroups + 1], pre0[kServeGroups + 1], tiles[kServeGroups];
+    int nseg = 0, npre = 0;
+    for (int grp = 0; grp < kServeGroups; ++grp) {
+      const int prec = grp / sl::kServeMaxNF, nf = grp % sl::kServeMaxNF + 1;
+      auto member = [&](const Request& r) {
+        return in_window(r) && r.grid->desc.value_prec == prec &&
+               r.grid->desc.nfields == nf;
+      };
+      seg0[grp] = nseg;
+      pre0[grp] = npre;
+      int maxw = 0;
+      for (size_t i = 0; i < s->active.size(); ++i)
+        if (member(s->active[i])) maxw = std::max(maxw, nstep[i]);
+      // Tick-major order: every queue hands out a request's steps in order.
+      for (int j = 0; j < maxw; ++j)
+        for (size_t i = 0; i < s->active.size(); ++i) {
+          const Request& r = s->active[i];
+          if (!member(r) || j >= nstep[i]) continue;
+          const sl::ReqStatic& hs = s->host_table[r.entry];
+          sl::ServeSeg& sg = st.segs[nseg++];
+          const int step = r.done + j;
+          sg.entry = r.entry;
+          sg.parity = step & 1;
+          sg.next = step + 1 < r.nsteps;
+          sg.ntiles = hs.ntiles;
+          sg.wait = j > 0;
+          sg.need = r.published + (unsigned)j * (unsigned)hs.ntiles;
+          sg.publish = j + 1 < nstep[i];
+          sg.dt = r.dt;
+          sg.tf[0] = sg.tf[1] = sg.tf[2] = 1.0;
+          if (sg.next) stage_times(r, step + 1, sg.tf);
+        }
+      const int n = nseg - seg0[grp];
+      tiles[grp] = 0;
+      for (int k = seg0[grp]; k < nseg; ++k) tiles[grp] += st.segs[k].ntiles;
+      if (n > 0) {
+        // Per-XCD prefix sums of the segments' chunk sizes.
+        for (int x = 0; x < sl::kNumXcd; ++x) {
+          int* pre = st.prefix + npre + x * (n + 1);
+          pre[0] = 0;
+          for (int k = 0; k < n; ++k) {
+            const int t = st.segs[seg0[grp] + k].ntiles;
+            pre[k + 1] = pre[k] + (t * (x + 1) / sl::kNumXcd - t * x / sl::kNumXcd);
+          }
+        }
+        npre += sl::kNumXcd * (n + 1);
+      }
+    }
+    seg0[kServeGroups] = nseg;
+    pre0[kServeGroups] = npre;
+    if (nseg > 0) {
+      err = hipMemcpyAsync(s->dev_segs, st.segs, sizeof(sl::ServeSeg) * (size_t)nseg,
+                           hipMemcpyHostToDevice, s->stream);
+      if (err == hipSuccess)
+        err = hipMemcpyAsync(s->dev_prefix, st.prefix, sizeof(int) * (size_t)npre,
+                             hipMemcpyHostToDevice, s->stream);
+      if (err == hipSuccess) {
+        sl::serve_zero_kernel<<<1, 64, 0, s->stream>>>(s->qctr, kServeGroups * sl::kNumXcd);
+        err = hipGetLastError();
+      }
+      for (int grp = 0; grp < kServeGroups && err == hipSuccess; ++grp) {
+        const int n = seg0[grp + 1] - seg0[grp];
+        if (n > 0)
+          err = launch_window(s, grp, s->dev_segs + seg0[grp], s->dev_prefix + pre0[grp], n,
+                              tiles[grp], s->qctr + grp * sl::kNumXcd);
+      }
+    }
+  }
+  // The other requests: one batched reconstruction launch per (value
+  // precision, field count).
+  order.clear();
+  for (size_t i = 0; i < s->active.size(); ++i)
+    if (!in_window(s->active[i])) order.push_back((int)i);
   auto key_of = [&](int i) {
     const sl_grid* g = s->active[i].grid;
     return g->desc.value_prec * 16 + g->desc.nfields;
@@ -519,8 +865,13 @@ int sl_server_tick(sl_server* s, int* active) {
   // Advance the step counters; move completed requests out of the batch.
   std::vector<Request> still;
   still.reserve(s->active.size());
-  for (Request& r : s->active) {
-    ++r.done;
+  for (size_t i = 0; i < s->active.size(); ++i) {
+    Request& r = s->active[i];
+    const int n = nstep[i];
+    if (in_window(r)) r.published += (unsigned)(n - 1) * (unsigned)s->host_table[r.entry].ntiles;
+    r.done += n;
+    s->stat_nodes += (int64_t)n * r.grid->ntot;
+    s->stat_steps += n;
     if (r.done >= r.nsteps) {
       r.finish_tick = s->tick;
       s->finished.push_back(r);
@@ -530,6 +881,15 @@ int sl_server_tick(sl_server* s, int* active) {
   }
   s->active.swap(still);
   if (active) *active = (int)s->active.size();
+  return SL_OK;
+}
+
+int sl_server_set_mode(sl_server* s, int mode, int window) {
+  if (!s || (mode != SL_SERVE_BATCHED && mode != SL_SERVE_QUEUED) || window < 1 ||
+      window > kServeMaxWindow || (mode == SL_SERVE_BATCHED && window != 1))
+    return SL_EINVAL;
+  s->mode = mode;
+  s->window = window;
   return SL_OK;
 }
 
@@ -576,23 +936,34 @@ int sl_server_fetch(sl_server* s, int64_t id, void* const* fields_out) {
 int sl_server_sync(sl_server* s, sl_stats* out) {
   if (!s) return SL_EINVAL;
   unsigned long long copies[sl::kStatWords], host[sl::ST_COUNT];
+  int aborted = 0;
   if (hipMemcpyAsync(copies, s->stats, sizeof(copies), hipMemcpyDeviceToHost, s->stream) !=
           hipSuccess ||
-      hipMemsetAsync(s->stats, 0, sizeof(copies), s->stream) != hipSuccess ||
-      hipStreamSynchronize(s->stream) != hipSuccess)
+      hipMemcpyAsync(&aborted, s->abort_flag, sizeof(int), hipMemcpyDeviceToHost, s->stream) !=
+          hipSuccess)
+    return SL_EHIP;
+  sl::serve_zero_kernel<<<8, 256, 0, s->stream>>>(reinterpret_cast<unsigned*>(s->stats),
+                                                 2 * sl::kStatWords);
+  if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s->stream) != hipSuccess)
     return SL_EHIP;
   sl::stat_totals(copies, host);
   drain_events(s, true, 0);
   if (out) {
     memset(out, 0, sizeof(*out));
+    out->nodes = s->stat_nodes;
     out->search_fail = (int64_t)host[sl::ST_SEARCH_FAIL];
     out->newton_fail = (int64_t)host[sl::ST_NEWTON_FAIL];
     out->nonfinite = (int64_t)host[sl::ST_NONFINITE];
     out->order_hist[0] = (int64_t)host[sl::ST_ORDER0];
     out->order_hist[1] = (int64_t)host[sl::ST_ORDER1];
+    out->order_hist[2] = (int64_t)host[sl::ST_ORDER2];
     out->walked = (int64_t)host[sl::ST_WALKED];
     out->scanned = (int64_t)host[sl::ST_SCANNED];
+    out->steps = s->stat_steps;
+    out->reconstructs = s->stat_steps;
   }
+  s->stat_nodes = s->stat_steps = 0;
+  if (aborted) return SL_EHIP;
   if (host[sl::ST_SEARCH_FAIL]) return SL_ESEARCH;
   if (host[sl::ST_NEWTON_FAIL]) return SL_ENEWTON;
   if (host[sl::ST_NONFINITE]) return SL_ENONFINITE;

@@ -32,7 +32,7 @@ class Server:
     """Server over a device arena of `budget_bytes` (the HBM budget)."""
 
     def __init__(self, budget_bytes: int, max_requests: int = 256, max_inflight: int = 2,
-                 device="cuda", stream=None):
+                 device="cuda", stream=None, mode: str = "batched", window: int = 1):
         import torch
         self.torch = torch
         self.device = torch.device(device)
@@ -45,6 +45,17 @@ class Server:
                 "sl_server_create")
         self._h = h
         self._inputs = {}
+        self.set_mode(mode, window)
+
+    def set_mode(self, mode: str = "batched", window: int = 1):
+        """"batched": one launch per (precision, field count) and tick, one
+        step per request; "queued": one launch per (precision, field count)
+        running `window` steps of every request from device-side tile queues
+        (sl_server_set_mode)."""
+        if mode not in ("batched", "queued"):
+            raise ValueError("mode must be 'batched' or 'queued'")
+        m = B.SL_SERVE_QUEUED if mode == "queued" else B.SL_SERVE_BATCHED
+        B.check(_lib().sl_server_set_mode(self._h, m, int(window)), "sl_server_set_mode")
 
     def close(self):
         if getattr(self, "_h", None):
@@ -102,7 +113,8 @@ class Server:
 
 
 def run_stream(requests, budget_bytes: int, max_requests: int = 256, max_inflight: int = 2,
-               keep_results: bool = False, device="cuda", time_scale: float = 1.0):
+               keep_results: bool = False, device="cuda", time_scale: float = 1.0,
+               mode: str = "batched", window: int = 1):
     """Replay `requests` (workloads.Request, with arrival times in seconds)
     against a fresh server.  Requests wait in a FIFO queue until the arena has
     room; every loop iteration admits what fits, runs one tick and collects
@@ -110,7 +122,7 @@ def run_stream(requests, budget_bytes: int, max_requests: int = 256, max_infligh
     completion seen by the host) and throughput."""
     import torch
     srv = Server(budget_bytes, max_requests=max_requests, max_inflight=max_inflight,
-                 device=device)
+                 device=device, mode=mode, window=window)
     dev = srv.device
     # Inputs are prepared before the clock starts (they are the clients'
     # data, already on the device when a request arrives).

@@ -60,8 +60,6 @@ def cases():
     # after every step.
     c = {
         "swirl1024_period": (lambda: W.swirl_three_fields(1024, value_prec="f32"), 1280, 0.0),
-        "swirl1024_period_f32store": (lambda: W.swirl_three_fields(1024, value_prec="f32"),
-                                      1280, 0.0, "f32"),
         "fourier3d256_50": (lambda: W.fourier3d_three_fields(256, value_prec="f32"), 50, 0.0),
         "deform3d512_10": (lambda: W.deform3d_slotted_sphere(512), 10, 0.0),
         # Shallow-water source terms (the oracle's run_source): the Kelvin

@@ -54,7 +54,7 @@ def test_nonfinite_input_is_reported(B, torch, orc, dim, prec):
         bad = (11, 9, 14)
         t0 = 0.3
     wl.limiter = False  # a NaN fires no flag; keep every stencil full-width
-    fields = stored_values(wl)
+    fields = [f.copy() for f in stored_values(wl)]
     fields[0][bad] = np.nan
     say("nonfinite", dim, prec, bad)
     g = B.Grid.from_workload(wl)

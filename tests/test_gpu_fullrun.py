@@ -3,11 +3,20 @@ runs of the same workloads (tests/golden/oracle_*.npz, written by
 tests/golden/make_oracle_runs.py from the oracle alone), compared at the
 stored sample of mesh nodes and by the whole-grid L1 norm of each field.
 
-The oracle runs in FP64 from the values as the split form stores them
-(FP32-rounded), so a plain-FP64 GPU run from the same values is the parity
-check proper (bound derived below); the FP32-value run of the same workload is
-compared with the same oracle result, which measures the split form's
-accumulated error."""
+Plain FP64 GPU runs are held to 1e-12 against the oracle's FP64 runs.
+
+The FP32-value form's parity with the oracle is per step (tests/
+test_gpu_restart.py: one oracle step from the GPU's own stored state, along
+whole runs).  Over a whole run its distance from the oracle grows: each
+step's FP32 weights and sums differ from FP64 ones by a few units of 2^-24
+(a single step measures ~4e-8 relative L1), and later steps carry that
+difference on.  Without the jump limiter the scheme is linear in the values
+and does not amplify it, so after N steps the FP32 form stays within
+N x 1e-7 of the oracle run that stores its values in FP32 between steps
+(checked here).  With the limiter, a criterion value within a rounding of
+the threshold can fall on the other side, which changes a node's order and
+that change is carried on; the benchmark then compares the FP32 form with
+plain FP64 at their L1 error against the exact solution."""
 import os
 import sys
 
@@ -35,14 +44,10 @@ WORKLOADS = {
 # the order of partial sums, the refined-reciprocal Newton), a few units of
 # 2^-53 per step; the 1e-12 tolerance of single steps holds over the whole
 # runs (1280 steps of the swirl measure below 1e-13).
-# FP32 values: each step stores its results rounded to 2^-24 relative, and a
-# rounding that crosses a limiter threshold lowers one node's order (a local
-# change of the interpolation error, up to ~1e-2 of the field's range); over
-# long runs this accumulates well above a single step's 1e-5 (a period of the
-# swirl: 1.2e-3 at samples concentrated on the slotted disc's edge, whose
-# own error against the exact solution is 0.6).  1e-2 is an envelope; the
-# test prints the measured values.
-TOL = {"f64": 1e-12, "f32": 1e-2}
+TOL = {"f64": 1e-12}
+# FP32 values against the oracle's FP32-storage run without the limiter: the
+# FP32 rounding of each step's weights and sums, accumulated linearly.
+F32_PER_STEP = 1e-7
 
 
 def say(*a):
@@ -66,12 +71,12 @@ def B():
 
 
 @pytest.mark.parametrize("case", list(WORKLOADS))
-@pytest.mark.parametrize("prec", ["f64", "f32"])
-def test_full_run_vs_oracle(B, torch, case, prec):
+def test_full_run_vs_oracle(B, torch, case):
+    prec = "f64"
     path = os.path.join(GOLDEN, "oracle_%s.npz" % case)
-    if not os.path.exists(path):
-        pytest.skip("oracle run not stored yet (tests/golden/make_oracle_runs.py %s)" % case)
     ref = np.load(path, allow_pickle=False)
+    store = str(ref["store"]) if "store" in ref.files else "f64"
+    assert store == prec, (case, store, prec)
     wl = WORKLOADS[case]()
     steps, t0 = int(ref["steps"]), float(ref["t0"])
     assert abs(float(ref["dt"]) - wl.dt) < 1e-15
@@ -99,3 +104,32 @@ def test_full_run_vs_oracle(B, torch, case, prec):
             assert rel <= TOL[prec] and norm <= TOL[prec], (f, rel, norm)
     say("  all fields sampled rel L1 %.3e" % (num / total))
     assert num / total <= TOL[prec]
+
+
+def test_fp32_whole_period_without_limiter_vs_f32_storage_oracle(B, torch, orc):
+    """The 256^2 three-field swirl over one whole period (320 steps), FP32
+    values, limiter off: the GPU run against the oracle's run from the same
+    stored values that rounds its values to FP32 after every step, within
+    320 x 1e-7 relative L1."""
+    from tests.util import oracle_problem
+    wl = W.swirl_three_fields(256, value_prec="f32")
+    wl.limiter = False
+    say("fp32 whole period, limiter off", wl.shape, wl.nsteps)
+    g = B.Grid.from_workload(wl)
+    out = g.advance(g.new_fields(stored_values(wl)), 0.0, wl.dt, wl.nsteps)
+    rc, st = g.sync()
+    assert rc == 0
+    orc_rc, want, _ = orc.run(oracle_problem(orc, wl), 0.0, wl.dt, wl.nsteps,
+                              stored_values(wl), store="f32")
+    assert orc_rc == 0
+    bound = wl.nsteps * F32_PER_STEP
+    num = den = 0.0
+    for f, (a, b) in enumerate(zip(out, want)):
+        a = a.double().cpu().numpy()
+        d = np.abs(a - b)
+        rel = d.sum() / np.abs(b).sum()
+        say("  field", f, "rel L1 %.3e" % rel, "Linf %.3e" % d.max())
+        assert rel <= bound, (f, rel, bound)
+        num += d.sum()
+        den += np.abs(b).sum()
+    assert num / den <= bound

@@ -48,12 +48,20 @@ def _alone(torch, req):
     return [f.cpu().numpy() for f in out]
 
 
-def test_mix_equals_alone_bitwise(torch, S):
+MODES = [("batched", 1), ("queued", 1), ("queued", 3), ("queued", 16)]
+
+
+@pytest.mark.parametrize("mode,window", MODES)
+def test_mix_equals_alone_bitwise(torch, S, mode, window):
+    """Served in a mix (staggered admissions, several field counts and sides)
+    each request gives the bits of its run alone, in every launch mode: one
+    batched launch per tick, or queued launches of 1, 3 or 16 steps (in which
+    a request's later steps wait on the device for its earlier ones)."""
     reqs = _requests()
     say("alone")
     alone = {r.rid: _alone(torch, r) for r in reqs}
-    say("mix")
-    srv = S.Server(256 << 20, max_requests=8, max_inflight=2)
+    say("mix", mode, window)
+    srv = S.Server(256 << 20, max_requests=8, max_inflight=2, mode=mode, window=window)
     dev = srv.device
     ids, got = {}, {}
     # Staggered admissions: three now, the rest after two ticks.
@@ -139,10 +147,11 @@ def test_served_request_matches_oracle(torch, S, orc):
     srv.close()
 
 
-def test_stream_driver_completes(torch, S):
+@pytest.mark.parametrize("mode,window", [("batched", 1), ("queued", 4)])
+def test_stream_driver_completes(torch, S, mode, window):
     reqs = W.serving_stream(seed=2, count=24, rate=400.0, sides=(64, 128, 256),
                             steps_range=(5, 12))
-    rep = S.run_stream(reqs, 64 << 20, max_requests=16)
+    rep = S.run_stream(reqs, 64 << 20, max_requests=16, mode=mode, window=window)
     say(rep)
     assert rep["status"] == 0 and rep["requests"] == 24
     assert rep["latency_p99_ms"] >= rep["latency_p50_ms"] > 0
@@ -162,12 +171,13 @@ def _golden():
     return mod, os.path.join(here, "golden")
 
 
-def _serve_all(torch, S, reqs, prec, budget=3 << 30):
+def _serve_all(torch, S, reqs, prec, budget=3 << 30, mode="batched", window=1):
     """Admit every (request, nsteps) pair into one server, half of them after
     two ticks, run to completion; returns {index: fields as FP64 numpy}."""
     from paper_1410_2817_amd import binding as B
     dt_ = torch.float32 if prec == "f32" else torch.float64
-    srv = S.Server(budget, max_requests=len(reqs) + 1, max_inflight=2)
+    srv = S.Server(budget, max_requests=len(reqs) + 1, max_inflight=2, mode=mode,
+                   window=window)
     dev = srv.device
     ids, got = {}, {}
 
@@ -207,7 +217,8 @@ SERVED = ["serve_mix128", "serve_mix256", "serve_mix512", "serve_mix1024",
           "serve_mix2048", "serve2048_50"]
 
 
-def test_served_fp64_runs_match_stored_oracle_runs(torch, S):
+@pytest.mark.parametrize("mode,window", [("batched", 1), ("queued", 4)])
+def test_served_fp64_runs_match_stored_oracle_runs(torch, S, mode, window):
     """FP64 requests of every side of the serving mix (and a 2048^2 one for
     50 steps), served together with staggered admission, against the
     oracle's runs of the same requests (tests/golden/oracle_serve_*.npz) at
@@ -215,8 +226,8 @@ def test_served_fp64_runs_match_stored_oracle_runs(torch, S):
     mod, gold = _golden()
     import os
     reqs = [(mod.served_request(n), mod.SERVED[n][2]) for n in SERVED]
-    say("served fp64", [(r.n, r.nfields, k) for r, k in reqs])
-    got = _serve_all(torch, S, reqs, "f64")
+    say("served fp64", mode, window, [(r.n, r.nfields, k) for r, k in reqs])
+    got = _serve_all(torch, S, reqs, "f64", mode=mode, window=window)
     for i, name in enumerate(SERVED):
         ref = np.load(os.path.join(gold, "oracle_%s.npz" % name), allow_pickle=False)
         assert int(ref["steps"]) == reqs[i][1]
@@ -232,7 +243,8 @@ def test_served_fp64_runs_match_stored_oracle_runs(torch, S):
         assert num / den <= 1e-12, (name, num / den)
 
 
-def test_served_fp32_steps_match_oracle_steps(torch, S, orc):
+@pytest.mark.parametrize("mode,window", [("batched", 1), ("queued", 4)])
+def test_served_fp32_steps_match_oracle_steps(torch, S, orc, mode, window):
     """FP32 requests of every side: each is served twice in the same mix,
     for n - 1 and for n steps; one oracle step from the (n - 1)-step result
     must give the n-step result within the FP32 tolerance (whole grids up to
@@ -242,8 +254,8 @@ def test_served_fp32_steps_match_oracle_steps(torch, S, orc):
     reqs = []
     for r, k in base:
         reqs += [(r, k - 1), (r, k)]
-    say("served fp32 pairs", [(r.n, k) for r, k in reqs])
-    got = _serve_all(torch, S, reqs, "f32")
+    say("served fp32 pairs", mode, window, [(r.n, k) for r, k in reqs])
+    got = _serve_all(torch, S, reqs, "f32", mode=mode, window=window)
     rng = np.random.Generator(np.random.PCG64(23))
     for j, (r, k) in enumerate(base):
         prev, last = got[2 * j], got[2 * j + 1]
@@ -272,3 +284,23 @@ def test_served_fp32_steps_match_oracle_steps(torch, S, orc):
             den += float(np.abs(b).sum())
         say("  side", r.n, "step", k - 1, "->", k, "rel L1 %.3e" % (num / den))
         assert num / den <= 1e-5
+
+
+def test_server_counts_every_step(torch, S):
+    """sl_server_sync reports the request steps it ran: nodes, steps and
+    reconstructions, and the order histogram summing to the field-node
+    reconstructions."""
+    reqs = _requests(4, seed=8)
+    srv = S.Server(128 << 20, max_requests=4, mode="queued", window=2)
+    dev = srv.device
+    for r in reqs:
+        (desc, _), f = S.request_desc(r), r.fields_torch(dev, torch.float32)
+        assert srv.admit(desc, f, r.dt, r.nsteps) is not None
+    while srv.tick() > 0:
+        pass
+    rc, st = srv.sync()
+    assert rc == 0
+    assert st["steps"] == st["reconstructs"] == sum(r.nsteps for r in reqs)
+    assert st["nodes"] == sum(r.nodes * r.nsteps for r in reqs)
+    assert sum(st["order_hist"]) == sum(r.nodes * r.nsteps * r.nfields for r in reqs)
+    srv.close()
