@@ -69,7 +69,8 @@ typedef enum sl_status {
   SL_ENONFINITE = -6,  /* a reconstructed value is NaN or infinite */
   SL_EBUSY = -7,       /* no room (serving: HBM budget or slots exhausted) */
   SL_ESTATE = -8,      /* call out of order (e.g. reconstruct before step) */
-  SL_ENOTFOUND = -9    /* unknown request id */
+  SL_ENOTFOUND = -9,   /* unknown request id */
+  SL_ETOOBIG = -10     /* the grid needs more than the static scratch holds */
 } sl_status;
 
 enum { SL_FP64 = 0, SL_FP32 = 1 };
@@ -259,6 +260,33 @@ int sl_sync(sl_grid *grid, void *workspace, void *stream, sl_stats *stats);
 int sl_advance(sl_grid *grid, void *workspace, void *const *fields_a,
                void *const *fields_b, double t0, double dt, int nsteps,
                void *stream, int *result_in_b);
+
+/* sl_advance without a workspace argument, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  The lattice displacements, limiter words and device
+ * counters live in a scratch array of SL_STATIC_SCRATCH_BYTES that the
+ * library holds on each device it runs on until the process ends; the call
+ * allocates nothing, host or device (the caller still owns the two field
+ * sets, the stream and `counters`).
+ *   - Runs on the current device; `stream` must belong to it.
+ *   - Same arguments, semantics, kernels and results as sl_advance.
+ *   - The scratch's counters are cleared at the start of each call (by a fill
+ *     kernel on `stream`).  counters (device memory, may be NULL) receives
+ *     SL_STATIC_COUNTERS int64 values once the call's kernels have run:
+ *     search failures, Newton failures, non-finite values, field-node
+ *     reconstructions at order 0 and at order 1, walked nodes, scanned nodes,
+ *     and 0.  The grid's own counters (sl_sync) are not touched.
+ *   - Every call on one device shares that device's scratch and leaves its
+ *     contents there: calls that overlap on one device (on different streams,
+ *     or from different host threads) race and must be serialised by the
+ *     caller.
+ * Errors: SL_ETOOBIG when sl_workspace_bytes(grid) exceeds
+ * SL_STATIC_SCRATCH_BYTES, SL_EHIP, and those of sl_advance. */
+#define SL_STATIC_SCRATCH_BYTES ((size_t)128 << 20)
+#define SL_STATIC_COUNTERS 8
+int sl_advance_static(sl_grid *grid, void *const *fields_a, void *const *fields_b,
+                      double t0, double dt, int nsteps, void *stream, int *result_in_b,
+                      int64_t *counters);
 
 /* Kernel timing: when enabled, the timed launches of the grid carry HIP
  * events in their dispatch packets.  Kinds: trajectories (sl_step), the

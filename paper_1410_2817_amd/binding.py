@@ -17,7 +17,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsl.so")
 
 SL_OK, SL_EINVAL, SL_ENOMEM, SL_EHIP, SL_ESEARCH, SL_ENEWTON, SL_ENONFINITE, \
-    SL_EBUSY, SL_ESTATE, SL_ENOTFOUND = 0, -1, -2, -3, -4, -5, -6, -7, -8, -9
+    SL_EBUSY, SL_ESTATE, SL_ENOTFOUND, SL_ETOOBIG = 0, -1, -2, -3, -4, -5, -6, -7, -8, -9, -10
+SL_STATIC_SCRATCH_BYTES = 128 << 20
+SL_STATIC_COUNTERS = 8
 SL_FP64, SL_FP32 = 0, 1
 SL_RK4, SL_RK3_WILLIAMSON = 0, 1
 SL_SRC_NONE, SL_SRC_SHALLOW_WATER = 0, 1
@@ -89,6 +91,9 @@ SIGNATURES = {
     "sl_sync": (C.c_int, [_VP, _VP, _VP, C.POINTER(SlStats)]),
     "sl_advance": (C.c_int, [_VP, _VP, C.POINTER(_VP), C.POINTER(_VP), C.c_double,
                              C.c_double, C.c_int, _VP, C.POINTER(C.c_int)]),
+    "sl_advance_static": (C.c_int, [_VP, C.POINTER(_VP), C.POINTER(_VP), C.c_double,
+                                    C.c_double, C.c_int, _VP, C.POINTER(C.c_int),
+                                    C.POINTER(C.c_int64)]),
     "sl_profile_enable": (C.c_int, [_VP, C.c_int]),
     "sl_profile_read": (C.c_int, [_VP, C.POINTER(SlProfile)]),
     "sl_displacement": (C.c_void_p, [_VP, _VP, C.c_int]),
@@ -335,3 +340,26 @@ class Grid:
               "sl_advance")
         return b if in_b.value else a
 
+    def advance_static(self, fields, t0: float, dt: float, nsteps: int, out=None,
+                       counters=None, stream=None):
+        """As advance, through sl_advance_static: the library's static scratch
+        on the current device stands in for the workspace (no allocation in the
+        call).  `counters`, when given, is a device int64 tensor of at least
+        SL_STATIC_COUNTERS elements that receives the call's counters.  Raises
+        SlError (SL_ETOOBIG for grids whose workspace exceeds the scratch)."""
+        a = list(fields)
+        b = list(out) if out is not None else self.new_fields()
+        self._check_fields(a)
+        self._check_fields(b)
+        pa = (_VP * self.nfields)(*[f.data_ptr() for f in a])
+        pb = (_VP * self.nfields)(*[f.data_ptr() for f in b])
+        in_b = C.c_int(0)
+        cp = None
+        if counters is not None:
+            if counters.numel() < SL_STATIC_COUNTERS or counters.element_size() != 8:
+                raise ValueError("counters must hold %d int64 values" % SL_STATIC_COUNTERS)
+            cp = C.cast(C.c_void_p(counters.data_ptr()), C.POINTER(C.c_int64))
+        check(load().sl_advance_static(self._h, pa, pb, float(t0), float(dt), int(nsteps),
+                                       C.c_void_p(_stream_handle(stream)), C.byref(in_b), cp),
+              "sl_advance_static")
+        return b if in_b.value else a

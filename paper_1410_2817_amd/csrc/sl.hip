@@ -21,6 +21,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <tuple>
 #include <utility>
@@ -42,9 +43,27 @@ __global__ void zero_kernel(unsigned long long* p, int n) {
     p[i] = 0ull;
 }
 
+// Totals of the counter copies into the caller's array of sl_advance_static
+// (one work-item per counter).
+__global__ void static_counters_kernel(const unsigned long long* __restrict__ copies,
+                                       int64_t* __restrict__ out) {
+  const int slots[SL_STATIC_COUNTERS - 1] = {ST_SEARCH_FAIL, ST_NEWTON_FAIL, ST_NONFINITE,
+                                             ST_ORDER0,      ST_ORDER1,      ST_WALKED,
+                                             ST_SCANNED};
+  const int k = threadIdx.x;
+  if (k >= SL_STATIC_COUNTERS) return;
+  unsigned long long sum = 0ull;
+  if (k < SL_STATIC_COUNTERS - 1)
+    for (int c = 0; c < kStatCopies; ++c) sum += copies[c * kStatStride + slots[k]];
+  out[k] = (int64_t)sum;
+}
+
 }  // namespace sl
 
-
+// Scratch of sl_advance_static: the workspace of callers that cannot
+// allocate.  Each device holds its own copy; host code reaches it only
+// through the address hipGetSymbolAddress returns on that device.
+static __device__ __align__(256) unsigned char scratch[SL_STATIC_SCRATCH_BYTES];
 
 // ===========================================================================
 // Host side: descriptors, validation, launches.
@@ -866,6 +885,69 @@ int sl_advance(sl_grid* gr, void* workspace, void* const* fields_a, void* const*
   return SL_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per
+// device (with that device current).
+int static_scratch(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_status(e);
+  if (dev < 0 || dev >= kMaxDevices) return SL_EINVAL;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_status(e);
+    if (!p) return SL_EHIP;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return SL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sl_advance_static(sl_grid* gr, void* const* fields_a, void* const* fields_b, double t0,
+                      double dt, int nsteps, void* stream, int* result_in_b,
+                      int64_t* counters) {
+  if (!gr) return SL_EINVAL;
+  if (gr->ws_bytes > SL_STATIC_SCRATCH_BYTES) {
+    snprintf(g_detail, sizeof(g_detail),
+             "grid needs %zu workspace bytes; the static scratch holds %zu", gr->ws_bytes,
+             (size_t)SL_STATIC_SCRATCH_BYTES);
+    return SL_ETOOBIG;
+  }
+  void* ws = nullptr;
+  int rc = static_scratch(&ws);
+  if (rc != SL_OK) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  auto* stats = reinterpret_cast<unsigned long long*>(static_cast<char*>(ws) + gr->off_stats);
+  clear_stale_error();
+  sl::zero_kernel<<<4, 256, 0, s>>>(stats, sl::kStatWords);
+  rc = hip_status(hipGetLastError());
+  if (rc != SL_OK) return rc;
+  // The grid's counters of launched steps belong to sl_sync's workspace.
+  const int64_t steps0 = gr->steps_launched, recs0 = gr->reconstructs_launched;
+  rc = sl_advance(gr, ws, fields_a, fields_b, t0, dt, nsteps, stream, result_in_b);
+  gr->steps_launched = steps0;
+  gr->reconstructs_launched = recs0;
+  if (rc != SL_OK) return rc;
+  if (counters) {
+    sl::static_counters_kernel<<<1, 64, 0, s>>>(stats, counters);
+    rc = hip_status(hipGetLastError());
+  }
+  return rc;
+}
+
 int sl_profile_enable(sl_grid* gr, int period) {
   if (!gr) return SL_EINVAL;
   gr->prof_period = period > 0 ? period : 0;
@@ -911,6 +993,7 @@ const char* sl_strerror(int code) {
     case SL_EBUSY: return "resources exhausted";
     case SL_ESTATE: return "call out of order";
     case SL_ENOTFOUND: return "unknown request";
+    case SL_ETOOBIG: return "grid larger than the static scratch";
     default: return "unknown status";
   }
 }
