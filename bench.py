@@ -755,7 +755,7 @@ def gpu_vs_oracle(wl, stored, steps, ofields):
             "linf": [float(np.abs(g - o).max()) for g, o in zip(got, ofields)]}
 
 
-SERVING_MODES = (("queued", 4), ("queued", 1), ("batched", 1))
+SERVING_MODES = (("batched", 1), ("queued", 1), ("queued", 4))
 
 
 def run_serving(count: int, budget_gib: float):
@@ -764,9 +764,9 @@ def run_serving(count: int, budget_gib: float):
     values / FP64 positions) through the continuous-batching server with an
     HBM budget of `budget_gib`.  First all requests arrive at once (capacity),
     then with Poisson arrivals at 0.7 x that capacity (latency).  Each launch
-    mode of the server is measured (SERVING_MODES: queued launches of 4 and 1
-    steps from device-side tile queues, and one batched launch per tick); the
-    first is reported at the top level, all under "modes"."""
+    mode of the server is measured (SERVING_MODES: one batched launch per
+    tick, and queued launches of 1 and 4 steps from device-side tile queues);
+    the first is reported at the top level, all under "modes"."""
     res = None
     modes = {}
     for mode, window in SERVING_MODES:

@@ -343,6 +343,11 @@ typedef struct sl_server_status {
   int64_t completed_ticks; /* ticks known to have finished on the device */
 } sl_server_status;
 
+/* Arena bytes the server keeps for itself (request table, counters, the
+ * window kernels' queues) with room for max_requests requests (0 if
+ * invalid); the rest of the arena holds the requests. */
+size_t sl_server_arena_overhead(int max_requests);
+
 /* Arena bytes one request with this descriptor occupies (0 if invalid). */
 size_t sl_server_request_bytes(const sl_grid_desc *desc);
 

@@ -100,6 +100,7 @@ SIGNATURES = {
     "sl_strerror": (C.c_char_p, [C.c_int]),
     "sl_version": (C.c_int, []),
     "sl_server_request_bytes": (C.c_size_t, [C.POINTER(SlGridDesc)]),
+    "sl_server_arena_overhead": (C.c_size_t, [C.c_int]),
     "sl_server_create": (C.c_int, [_VP, C.c_size_t, C.c_int, C.c_int, _VP, C.POINTER(_VP)]),
     "sl_server_destroy": (C.c_int, [_VP]),
     "sl_server_admit": (C.c_int, [_VP, C.POINTER(SlGridDesc), C.POINTER(_VP), C.c_double,

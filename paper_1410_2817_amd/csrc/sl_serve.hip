@@ -136,7 +136,8 @@ void recon2d_batched_kernel(
 // has its own queue: the concatenation of its chunks over the segments.  The
 // launch has one workgroup per tile of the whole window.  A workgroup reads
 // the XCD it runs on and takes the next tile of that XCD's queue through one
-// atomic counter (the next non-empty queue once its own is empty), so a
+// atomic counter (the next non-empty queue once its own is empty) and finds
+// its segment by a 64-way search of the queue's prefix sums, so a
 // request's neighbouring tiles meet in one L2, and tiles are handed out in
 // tick order whatever order the workgroups start in.
 //
@@ -162,6 +163,8 @@ void recon2d_batched_kernel(
 
 constexpr int kServeMaxNF = 4;  // field counts the window kernels take
 constexpr unsigned kServeSpinLimit = 1u << 23;
+// Queue counters sit 256 bytes apart: atomics on one line serialise.
+constexpr int kQueueStride = 64;
 
 struct ServeSeg {
   int entry;   // table index
@@ -213,28 +216,39 @@ void serve_window_kernel(const ReqStatic* __restrict__ table,
                          unsigned* __restrict__ done, int* __restrict__ abort_flag) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int s_item, s_seg, s_x;
-  if (threadIdx.x == 0) {
+  if (threadIdx.x < 64) {
+    // Wave 0 takes the workgroup's tile: lane 0 the atomic, all 64 lanes the
+    // search for its segment (a 64-way split of the prefix per round).
+    const int lane = threadIdx.x;
     const int home = xcc_id();
     int it = 0, k = -1, x = home;
     if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
       for (int q = 0; q < kNumXcd && k < 0; ++q) {
         x = (home + q) & (kNumXcd - 1);
         const int* __restrict__ pre = prefix + x * (nseg + 1);
-        if (__hip_atomic_load(&qctr[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >=
-            (unsigned)pre[nseg])
-          continue;  // drained
-        it = (int)atomicAdd(&qctr[x], 1u);
-        if (it >= pre[nseg]) continue;
-        int lo = 0, hi = nseg - 1;  // last k with pre[k] <= it
-        while (lo < hi) {
-          const int mid = (lo + hi + 1) >> 1;
-          if (pre[mid] <= it) lo = mid;
-          else hi = mid - 1;
+        const int total = pre[nseg];
+        unsigned* ctr = qctr + x * kQueueStride;
+        int got = total;
+        if (lane == 0 &&
+            __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < (unsigned)total)
+          got = (int)atomicAdd(ctr, 1u);
+        it = __builtin_amdgcn_readfirstlane(got);
+        if (it >= total) continue;  // drained
+        int lo = 0, hi = nseg;  // pre[lo] <= it < pre[hi]
+        while (hi - lo > 1) {
+          const int step = (hi - lo + 63) >> 6;
+          const int idx = min(lo + lane * step, hi - 1);
+          const unsigned long long below = __ballot(pre[idx] <= it);
+          const int top = 63 - __builtin_clzll(below);  // lane 0 always qualifies
+          const int nlo = min(lo + top * step, hi - 1);
+          const int nhi = top < 63 ? min(lo + (top + 1) * step, hi) : hi;
+          lo = nlo;
+          hi = nhi;
         }
         k = lo;
       }
     }
-    if (k >= 0 && segs[k].wait) {
+    if (lane == 0 && k >= 0 && segs[k].wait) {
       const ServeSeg& sg = segs[k];
       unsigned spins = 0;
       while (__hip_atomic_load(&done[sg.entry], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
@@ -249,9 +263,11 @@ void serve_window_kernel(const ReqStatic* __restrict__ table,
       }
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
-    s_item = it;
-    s_seg = k;
-    s_x = x;
+    if (lane == 0) {
+      s_item = it;
+      s_seg = k;
+      s_x = x;
+    }
   }
   __syncthreads();
   // Uniform across the workgroup: keep them (and what is loaded through
@@ -304,10 +320,21 @@ constexpr int kServeMaxWindow = 16;  // ticks per window launch
 // group = precision * kServeMaxNF + nf - 1.
 constexpr int kServeGroups = 2 * sl::kServeMaxNF;
 
+// Bytes of a tick's upload for the window kernels: the queue counters of
+// every group (zeros, kQueueStride apart), the segments, the per-XCD prefix
+// sums.
+constexpr size_t kQueueBytes =
+    sizeof(unsigned) * kServeGroups * sl::kNumXcd * sl::kQueueStride;
+
+inline size_t tick_area_bytes(int max_requests) {
+  const size_t max_segs = (size_t)max_requests * kServeMaxWindow;
+  return kQueueBytes + (sizeof(sl::ServeSeg) * max_segs + 255) / 256 * 256 +
+         (sizeof(int) * sl::kNumXcd * (max_segs + kServeGroups) + 255) / 256 * 256;
+}
+
 // Host staging of one window launch's segment table (pinned memory).
 struct SegStage {
-  sl::ServeSeg* segs;
-  int* prefix;
+  char* base;  // queue counters (zeros), then the segments, then the prefix sums
 };
 
 }  // namespace
@@ -339,14 +366,13 @@ struct sl_server {
   // prefix sums, per-group queue counters, per-entry published-tile counts
   // and the abort flag, all in the arena header; pinned host staging, one
   // slot per tick in flight.
-  sl::ServeSeg* dev_segs;
-  int* dev_prefix;
-  unsigned* qctr;  // kServeGroups x kNumXcd
+  char* dev_tick;   // a tick's queue counters, segments and prefix sums (one upload)
   unsigned* done;  // max_requests
   int* abort_flag;
-  int max_segs;
   std::vector<SegStage> stage;
   void* stage_mem;
+  std::vector<sl::ServeSeg> segs;  // host scratch of a tick's segments
+  std::vector<int> prefix;         // and of their per-XCD prefix sums
   // Host totals since the last sl_server_sync.
   int64_t stat_nodes, stat_steps;
 };
@@ -513,6 +539,13 @@ void stage_times(const Request& r, int k, double tf[3]) {
 
 extern "C" {
 
+size_t sl_server_arena_overhead(int max_requests) {
+  if (max_requests < 1 || max_requests > 4096) return 0;
+  return align_up(sizeof(sl::ReqStatic) * (size_t)max_requests) +
+         align_up(sizeof(unsigned long long) * sl::kStatWords) + tick_area_bytes(max_requests) +
+         align_up(sizeof(unsigned) * (size_t)max_requests + sizeof(int));
+}
+
 size_t sl_server_request_bytes(const sl_grid_desc* desc) {
   sl_grid* gr = nullptr;
   if (sl_create_grid(desc, &gr) != SL_OK) return 0;
@@ -530,14 +563,10 @@ int sl_server_create(void* arena, size_t arena_bytes, int max_requests, int max_
     return SL_EINVAL;
   const size_t table_bytes = align_up(sizeof(sl::ReqStatic) * (size_t)max_requests);
   const size_t stats_bytes = align_up(sizeof(unsigned long long) * sl::kStatWords);
-  const int max_segs = max_requests * kServeMaxWindow;
-  const size_t seg_bytes = align_up(sizeof(sl::ServeSeg) * (size_t)max_segs);
-  const size_t prefix_bytes =
-      align_up(sizeof(int) * sl::kNumXcd * (size_t)(max_segs + kServeGroups));
-  const size_t ctl_bytes = align_up(
-      sizeof(unsigned) * (kServeGroups * sl::kNumXcd + (size_t)max_requests) + sizeof(int));
-  const size_t persist_bytes = seg_bytes + prefix_bytes + ctl_bytes;
-  if (arena_bytes < table_bytes + stats_bytes + persist_bytes + kAlign) return SL_EINVAL;
+  const size_t tick_bytes = tick_area_bytes(max_requests);
+  const size_t ctl_bytes = align_up(sizeof(unsigned) * (size_t)max_requests + sizeof(int));
+  const size_t persist_bytes = tick_bytes + ctl_bytes;
+  if (arena_bytes < sl_server_arena_overhead(max_requests) + kAlign) return SL_EINVAL;
   sl_server* s = new (std::nothrow) sl_server();
   if (!s) return SL_ENOMEM;
   s->arena = static_cast<char*>(arena);
@@ -549,12 +578,9 @@ int sl_server_create(void* arena, size_t arena_bytes, int max_requests, int max_
   s->stats = reinterpret_cast<unsigned long long*>(s->arena + table_bytes);
   s->host_table.resize(max_requests);
   char* ph = s->arena + table_bytes + stats_bytes;
-  s->dev_segs = reinterpret_cast<sl::ServeSeg*>(ph);
-  s->dev_prefix = reinterpret_cast<int*>(ph + seg_bytes);
-  s->qctr = reinterpret_cast<unsigned*>(ph + seg_bytes + prefix_bytes);
-  s->done = s->qctr + kServeGroups * sl::kNumXcd;
+  s->dev_tick = ph;
+  s->done = reinterpret_cast<unsigned*>(ph + tick_bytes);
   s->abort_flag = reinterpret_cast<int*>(s->done + max_requests);
-  s->max_segs = max_segs;
   s->mode = SL_SERVE_BATCHED;
   s->window = 1;
   s->stage_mem = nullptr;
@@ -573,18 +599,16 @@ int sl_server_create(void* arena, size_t arena_bytes, int max_requests, int max_
     sl::serve_zero_kernel<<<8, 256, 0, s->stream>>>(reinterpret_cast<unsigned*>(s->stats),
                                                    2 * sl::kStatWords);
     const int nctl = (int)(ctl_bytes / sizeof(unsigned));
-    sl::serve_zero_kernel<<<(nctl + 255) / 256, 256, 0, s->stream>>>(s->qctr, nctl);
+    sl::serve_zero_kernel<<<(nctl + 255) / 256, 256, 0, s->stream>>>(s->done, nctl);
     if (hipGetLastError() != hipSuccess) rc = SL_EHIP;
   }
   if (rc == SL_OK) {
-    const size_t slot = seg_bytes + prefix_bytes;
+    const size_t slot = tick_bytes;
     const int nslots = max_inflight + 1;
     if (hipHostMalloc(&s->stage_mem, slot * (size_t)nslots, hipHostMallocDefault) != hipSuccess)
       rc = SL_EHIP;
     for (int k = 0; k < nslots && rc == SL_OK; ++k) {
-      char* base = static_cast<char*>(s->stage_mem) + slot * (size_t)k;
-      s->stage.push_back({reinterpret_cast<sl::ServeSeg*>(base),
-                          reinterpret_cast<int*>(base + seg_bytes)});
+      s->stage.push_back({static_cast<char*>(s->stage_mem) + slot * (size_t)k});
     }
   }
   if (rc != SL_OK) {
@@ -756,16 +780,19 @@ int sl_server_tick(sl_server* s, int* active) {
   // tick's segment table holds the groups one after another.
   if (windowed && err == hipSuccess) {
     SegStage& st = s->stage[(size_t)(s->tick % (int64_t)s->stage.size())];
+    std::vector<sl::ServeSeg>& segs = s->segs;
+    std::vector<int>& prefix = s->prefix;
+    segs.clear();
+    prefix.clear();
     int seg0[kServeGroups + 1], pre0[kServeGroups + 1], tiles[kServeGroups];
-    int nseg = 0, npre = 0;
     for (int grp = 0; grp < kServeGroups; ++grp) {
       const int prec = grp / sl::kServeMaxNF, nf = grp % sl::kServeMaxNF + 1;
       auto member = [&](const Request& r) {
         return in_window(r) && r.grid->desc.value_prec == prec &&
                r.grid->desc.nfields == nf;
       };
-      seg0[grp] = nseg;
-      pre0[grp] = npre;
+      seg0[grp] = (int)segs.size();
+      pre0[grp] = (int)prefix.size();
       int maxw = 0;
       for (size_t i = 0; i < s->active.size(); ++i)
         if (member(s->active[i])) maxw = std::max(maxw, nstep[i]);
@@ -775,7 +802,7 @@ int sl_server_tick(sl_server* s, int* active) {
           const Request& r = s->active[i];
           if (!member(r) || j >= nstep[i]) continue;
           const sl::ReqStatic& hs = s->host_table[r.entry];
-          sl::ServeSeg& sg = st.segs[nseg++];
+          sl::ServeSeg sg;
           const int step = r.done + j;
           sg.entry = r.entry;
           sg.parity = step & 1;
@@ -787,40 +814,40 @@ int sl_server_tick(sl_server* s, int* active) {
           sg.dt = r.dt;
           sg.tf[0] = sg.tf[1] = sg.tf[2] = 1.0;
           if (sg.next) stage_times(r, step + 1, sg.tf);
+          segs.push_back(sg);
         }
-      const int n = nseg - seg0[grp];
+      const int n = (int)segs.size() - seg0[grp];
       tiles[grp] = 0;
-      for (int k = seg0[grp]; k < nseg; ++k) tiles[grp] += st.segs[k].ntiles;
-      if (n > 0) {
-        // Per-XCD prefix sums of the segments' chunk sizes.
+      for (int k = seg0[grp]; k < (int)segs.size(); ++k) tiles[grp] += segs[k].ntiles;
+      // Per-XCD prefix sums of the segments' chunk sizes.
+      if (n > 0)
         for (int x = 0; x < sl::kNumXcd; ++x) {
-          int* pre = st.prefix + npre + x * (n + 1);
-          pre[0] = 0;
+          prefix.push_back(0);
           for (int k = 0; k < n; ++k) {
-            const int t = st.segs[seg0[grp] + k].ntiles;
-            pre[k + 1] = pre[k] + (t * (x + 1) / sl::kNumXcd - t * x / sl::kNumXcd);
+            const int t = segs[seg0[grp] + k].ntiles;
+            prefix.push_back(prefix.back() + (t * (x + 1) / sl::kNumXcd - t * x / sl::kNumXcd));
           }
         }
-        npre += sl::kNumXcd * (n + 1);
-      }
     }
-    seg0[kServeGroups] = nseg;
-    pre0[kServeGroups] = npre;
-    if (nseg > 0) {
-      err = hipMemcpyAsync(s->dev_segs, st.segs, sizeof(sl::ServeSeg) * (size_t)nseg,
-                           hipMemcpyHostToDevice, s->stream);
-      if (err == hipSuccess)
-        err = hipMemcpyAsync(s->dev_prefix, st.prefix, sizeof(int) * (size_t)npre,
-                             hipMemcpyHostToDevice, s->stream);
-      if (err == hipSuccess) {
-        sl::serve_zero_kernel<<<1, 64, 0, s->stream>>>(s->qctr, kServeGroups * sl::kNumXcd);
-        err = hipGetLastError();
-      }
+    seg0[kServeGroups] = (int)segs.size();
+    pre0[kServeGroups] = (int)prefix.size();
+    if (!segs.empty()) {
+      // One upload: zeroed queue counters, the segments, the prefix sums.
+      const size_t seg_off = kQueueBytes;
+      const size_t pre_off = align_up(seg_off + sizeof(sl::ServeSeg) * segs.size());
+      const size_t bytes = pre_off + sizeof(int) * prefix.size();
+      memset(st.base, 0, kQueueBytes);
+      memcpy(st.base + seg_off, segs.data(), sizeof(sl::ServeSeg) * segs.size());
+      memcpy(st.base + pre_off, prefix.data(), sizeof(int) * prefix.size());
+      err = hipMemcpyAsync(s->dev_tick, st.base, bytes, hipMemcpyHostToDevice, s->stream);
+      const auto* dsegs = reinterpret_cast<const sl::ServeSeg*>(s->dev_tick + seg_off);
+      const int* dpre = reinterpret_cast<const int*>(s->dev_tick + pre_off);
+      auto* dq = reinterpret_cast<unsigned*>(s->dev_tick);
       for (int grp = 0; grp < kServeGroups && err == hipSuccess; ++grp) {
         const int n = seg0[grp + 1] - seg0[grp];
         if (n > 0)
-          err = launch_window(s, grp, s->dev_segs + seg0[grp], s->dev_prefix + pre0[grp], n,
-                              tiles[grp], s->qctr + grp * sl::kNumXcd);
+          err = launch_window(s, grp, dsegs + seg0[grp], dpre + pre0[grp], n, tiles[grp],
+                              dq + grp * sl::kNumXcd * sl::kQueueStride);
       }
     }
   }

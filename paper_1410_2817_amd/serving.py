@@ -72,6 +72,11 @@ class Server:
     def request_bytes(desc) -> int:
         return int(_lib().sl_server_request_bytes(C.byref(desc)))
 
+    @staticmethod
+    def arena_overhead(max_requests: int) -> int:
+        """Arena bytes a server with max_requests slots keeps for itself."""
+        return int(_lib().sl_server_arena_overhead(int(max_requests)))
+
     def admit(self, desc, fields, dt: float, nsteps: int, t0: float = 0.0):
         """Admit one request (fields: device tensors); returns its id, or None
         when the arena or the request slots are full."""

@@ -196,3 +196,11 @@ def test_shallow_water_source_validation(lib):
         d, _ = _desc(**kw)
         rc, h = _create(d)
         assert rc == B.SL_EINVAL and not h.value, bad
+
+
+def test_server_arena_overhead(lib):
+    # The server's own share of the arena grows with its request slots and is
+    # 256-byte granular; invalid slot counts give 0.
+    a, b = lib.sl_server_arena_overhead(2), lib.sl_server_arena_overhead(256)
+    assert 0 < a < b and a % 256 == 0 and b % 256 == 0
+    assert lib.sl_server_arena_overhead(0) == 0 and lib.sl_server_arena_overhead(5000) == 0

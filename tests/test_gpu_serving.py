@@ -93,10 +93,8 @@ def test_admission_respects_budget(torch, S):
     reqs = _requests(3, seed=5)
     desc0, _ = S.request_desc(reqs[0])
     need = S.Server.request_bytes(desc0)
-    # Room for the descriptor table of two requests, the counters (64 copies
-    # of a 128-byte line) and exactly one request of this size (plus less
-    # than 12 KiB of slack).
-    srv = S.Server(16384 + 64 * 128 + need, max_requests=2, max_inflight=1)
+    # Room for the server's own data and exactly one request of this size.
+    srv = S.Server(S.Server.arena_overhead(2) + need, max_requests=2, max_inflight=1)
     dev = srv.device
     f0 = reqs[0].fields_torch(dev, torch.float32)
     a = srv.admit(desc0, f0, reqs[0].dt, reqs[0].nsteps)
