@@ -819,7 +819,7 @@ def sampled_cpu_baseline(wl, stored, seconds):
     t0 = time.perf_counter()
     rc, _, _ = oracle.step_sampled(prob, 0.0, wl.dt, fields, probe)
     per_node = (time.perf_counter() - t0) / probe.size
-    count = int(min(max(seconds / max(per_node, 1e-9), 2000), 4_000_000))
+    count = int(min(max(seconds / max(per_node, 1e-9), 2000), 32_000_000))
     nodes = np.unique(g.integers(0, wl.nodes, count)).astype(np.int64)
     t0 = time.perf_counter()
     rc, vals, _ = oracle.step_sampled(prob, 0.0, wl.dt, fields, nodes)

@@ -65,14 +65,6 @@ __device__ __forceinline__ int xcd_tile(int b, int nblocks) {
   return xcd * q + (xcd < rem ? xcd : rem) + local;
 }
 
-// Wrap an index known to lie near [0, n) without integer division; far
-// indices (only from pathological walks) take the general path.
-__device__ __forceinline__ int wrap_near(int v, int n) {
-  v = v < 0 ? v + n : v;
-  v = v >= n ? v - n : v;
-  return (unsigned)v < (unsigned)n ? v : wrap_index(v, n);
-}
-
 // Displacement accessor reading global memory (through L1/L2).
 struct NearDisp2D {
   const double* __restrict__ gdisp;
