@@ -242,9 +242,11 @@ sl::StageTimes stage_times(const sl_grid* gr, double t, double dt) {
   return st;
 }
 
+// `trig`: the grid's table (fresh lattice), or null.
 template <int D>
 hipError_t launch_traj(sl_grid* gr, double* disp, double t, double dt, int accumulate,
-                       hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+                       hipStream_t s, hipEvent_t e0, hipEvent_t e1,
+                       const double* trig = nullptr) {
   const sl::StageTimes st = stage_times(gr, t, dt);
   const dim3 blocks((unsigned)((gr->g.n[0] + sl::kTrajBX - 1) / sl::kTrajBX),
                     (unsigned)((gr->g.n[1] + sl::kTrajBY - 1) / sl::kTrajBY),
@@ -253,13 +255,13 @@ hipError_t launch_traj(sl_grid* gr, double* disp, double t, double dt, int accum
   const int integ = gr->desc.integrator;
   switch (gr->v.kind) {
     case SL_VEL_UNIFORM:
-      return launch(sl::traj_kernel<D, SL_VEL_UNIFORM>, blocks, threads, 0, s, e0, e1, gr->g, gr->v, disp, st, dt, accumulate, integ);
+      return launch(sl::traj_kernel<D, SL_VEL_UNIFORM>, blocks, threads, 0, s, e0, e1, gr->g, gr->v, disp, st, dt, accumulate, integ, trig);
     case SL_VEL_SOLID_BODY:
-      return launch(sl::traj_kernel<D, SL_VEL_SOLID_BODY>, blocks, threads, 0, s, e0, e1, gr->g, gr->v, disp, st, dt, accumulate, integ);
+      return launch(sl::traj_kernel<D, SL_VEL_SOLID_BODY>, blocks, threads, 0, s, e0, e1, gr->g, gr->v, disp, st, dt, accumulate, integ, trig);
     case SL_VEL_SWIRL2D:
-      return launch(sl::traj_kernel<D, SL_VEL_SWIRL2D>, blocks, threads, 0, s, e0, e1, gr->g, gr->v, disp, st, dt, accumulate, integ);
+      return launch(sl::traj_kernel<D, SL_VEL_SWIRL2D>, blocks, threads, 0, s, e0, e1, gr->g, gr->v, disp, st, dt, accumulate, integ, trig);
     case SL_VEL_DEFORM3D:
-      return launch(sl::traj_kernel<D, SL_VEL_DEFORM3D>, blocks, threads, 0, s, e0, e1, gr->g, gr->v, disp, st, dt, accumulate, integ);
+      return launch(sl::traj_kernel<D, SL_VEL_DEFORM3D>, blocks, threads, 0, s, e0, e1, gr->g, gr->v, disp, st, dt, accumulate, integ, trig);
     case SL_VEL_GRIDDED:
       if constexpr (D == 2) {
         // Tiles with their velocity samples staged in LDS.
@@ -268,9 +270,9 @@ hipError_t launch_traj(sl_grid* gr, double* disp, double t, double dt, int accum
         return launch(sl::traj_gridded2d_kernel<2>, dim3(tx * ty), dim3(256), 0, s, e0, e1, gr->g,
                       gr->v, disp, st, dt, accumulate, integ, tx);
       }
-      return launch(sl::traj_kernel<D, SL_VEL_GRIDDED>, blocks, threads, 0, s, e0, e1, gr->g, gr->v, disp, st, dt, accumulate, integ);
+      return launch(sl::traj_kernel<D, SL_VEL_GRIDDED>, blocks, threads, 0, s, e0, e1, gr->g, gr->v, disp, st, dt, accumulate, integ, trig);
     default:
-      return launch(sl::traj_kernel<D, SL_VEL_FOURIER>, blocks, threads, 0, s, e0, e1, gr->g, gr->v, disp, st, dt, accumulate, integ);
+      return launch(sl::traj_kernel<D, SL_VEL_FOURIER>, blocks, threads, 0, s, e0, e1, gr->g, gr->v, disp, st, dt, accumulate, integ, trig);
   }
 }
 
@@ -434,6 +436,8 @@ int sl_create_grid(const sl_grid_desc* desc, sl_grid** out) {
   for (int a = 0; a < 3; ++a) {
     g.n[a] = a < D ? (int)desc->n[a] : 1;
     g.h[a] = a < D ? desc->length[a] / (double)desc->n[a] : 1.0;
+    g.rh[a] = 1.0 / g.h[a];
+    g.r6h[a] = 1.0 / (6.0 * g.h[a]);
     g.off[a] = a < D ? (int)desc->offset[a] : 0;
     if (a < D) gr->ntot *= desc->n[a];
   }
@@ -500,6 +504,26 @@ int sl_create_grid(const sl_grid_desc* desc, sl_grid** out) {
       }
     }
   }
+  // Bound on the Runge-Kutta stage offsets per unit dt in the argument of the
+  // angle-shift evaluators: max |u_a| (times y_a / x_a for the Fourier ik
+  // encoding) times the integrator's factor.  RK4 evaluates at most dt u
+  // away; Williamson's RK3 at most dt max|u| (1/3 + 15/16 * 14/9) < 1.8.
+  {
+    double umax = HUGE_VAL;
+    if (v.kind == SL_VEL_SWIRL2D) {
+      umax = std::fabs(v.p[1]);  // |sin^2(pi x) sin(2 pi y)| <= 1
+    } else if (v.kind == SL_VEL_DEFORM3D) {
+      umax = 2.0 * std::fabs(v.p[1]);  // u_x carries the factor 2
+    } else if (v.kind == SL_VEL_FOURIER && v.small_k) {
+      umax = 0.0;
+      for (int a = 0; a < D; ++a) {
+        double sa = 0.0;
+        for (int q = 0; q < v.nmodes; ++q) sa += std::fabs(v.mode[q].amp[a]);
+        umax = std::max(umax, sa * v.kscale[a]);
+      }
+    }
+    v.shift_rate = umax * (desc->integrator == SL_RK4 ? 1.0 : 1.8);
+  }
   gr->off_stats = 0;
   gr->off_disp = align_up(kStatsBytes);
   gr->off_flags = align_up(gr->off_disp + sizeof(double) * (size_t)D * (size_t)gr->ntot);
@@ -520,10 +544,8 @@ int sl_create_grid(const sl_grid_desc* desc, sl_grid** out) {
   }
   gr->off_trig = gr->trig_bytes = 0;
   if (sl::uses_trig_table(v, D) && desc->source == SL_SRC_NONE) {
-    size_t axes = 0;
-    for (int a = 0; a < D; ++a) axes += (size_t)desc->n[a];
     gr->off_trig = gr->ws_bytes;
-    gr->trig_bytes = 2 * sizeof(double) * axes;
+    gr->trig_bytes = 2 * sizeof(double) * sl::trig_table_pairs(g, D);
     gr->ws_bytes = align_up(gr->off_trig + gr->trig_bytes);
   }
   // 2-D grids evaluate the limiter flags inside the reconstruction tiles
@@ -805,30 +827,25 @@ int sl_advance(sl_grid* gr, void* workspace, void* const* fields_a, void* const*
                        reinterpret_cast<double*>(ws + gr->off_disp2)};
     clear_stale_error();
     const bool carried = gr->v.kind == SL_VEL_CARRIED;
-    const ProfSlot ps = prof_begin(gr, 0);
-    hipError_t e;
-    if (carried)
-      e = gr->desc.dim == 2 ? launch_carried<2>(gr, ab, dbuf[0], dt, 0, s, ps.start, ps.stop)
-                            : launch_carried<3>(gr, ab, dbuf[0], dt, 0, s, ps.start, ps.stop);
-    else
-      e = gr->desc.dim == 2 ? launch_traj<2>(gr, dbuf[0], t0, dt, 0, s, ps.start, ps.stop)
-                            : launch_traj<3>(gr, dbuf[0], t0, dt, 0, s, ps.start, ps.stop);
-    prof_end(gr, ps, 0, e);
-    // The fused trajectories start from sin/cos(pi x) at the mesh nodes: one
-    // table per call, n_x + n_y (+ n_z) entries.
+    hipError_t e = hipSuccess;
+    // Every step's trajectories start from sin/cos(pi x) at the mesh nodes:
+    // one table per call, n_x + n_y (+ n_z) entries (sl::trig_table_kernel).
     const double* trig = nullptr;
-    if (e == hipSuccess && gr->trig_bytes && nsteps > 1) {
+    if (gr->trig_bytes && !carried) {
       double* tb = reinterpret_cast<double*>(ws + gr->off_trig);
-      int axes = 0;
-      for (int a = 0; a < gr->desc.dim; ++a) axes += gr->g.n[a];
-      const dim3 blocks((axes + sl::kBlock - 1) / sl::kBlock), threads(sl::kBlock);
-      if (gr->desc.dim == 2)
-        sl::trig_table_kernel<2><<<blocks, threads, 0, s>>>(gr->g, gr->v, tb);
-      else
-        sl::trig_table_kernel<3><<<blocks, threads, 0, s>>>(gr->g, gr->v, tb);
-      e = hipGetLastError();
+      e = gr->desc.dim == 2 ? sl::launch_trig_table<2>(gr->g, gr->v, tb, s)
+                            : sl::launch_trig_table<3>(gr->g, gr->v, tb, s);
       trig = tb;
     }
+    const ProfSlot ps = prof_begin(gr, 0);
+    if (e == hipSuccess && carried)
+      e = gr->desc.dim == 2 ? launch_carried<2>(gr, ab, dbuf[0], dt, 0, s, ps.start, ps.stop)
+                            : launch_carried<3>(gr, ab, dbuf[0], dt, 0, s, ps.start, ps.stop);
+    else if (e == hipSuccess)
+      e = gr->desc.dim == 2
+              ? launch_traj<2>(gr, dbuf[0], t0, dt, 0, s, ps.start, ps.stop, trig)
+              : launch_traj<3>(gr, dbuf[0], t0, dt, 0, s, ps.start, ps.stop, trig);
+    prof_end(gr, ps, 0, e);
     for (int k = 0; k < nsteps && e == hipSuccess; ++k) {
       gr->steps_launched++;
       sl::NextTraj nt{};

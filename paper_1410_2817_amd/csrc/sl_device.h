@@ -19,6 +19,8 @@ struct GridArgs {
   int n[3];
   int ntot;
   double h[3];
+  double rh[3];   // 1 / h_a, correctly rounded (host)
+  double r6h[3];  // 1 / (6 h_a), correctly rounded (host)
   int nfields;
   int order_max;
   int limiter;
@@ -62,6 +64,10 @@ struct VelArgs {
   int nmodes;
   int small_k;        // SL_VEL_FOURIER: modes in the ik encoding
   double kscale[3];   // SL_VEL_FOURIER: 2 / L_a (y_a = kscale_a x_a)
+  // Bound on |delta| / dt over the Runge-Kutta stage offsets delta that the
+  // angle-shift evaluators (NodeVelocity) take, in the units of their sincospi
+  // argument, for the grid's family and integrator; 0 if none is known.
+  double shift_rate;
   double p[8];
   Mode mode[SL_MAX_MODES];
   // SL_VEL_GRIDDED: samples on the mesh (x first), mesh spacing and size,
@@ -167,45 +173,43 @@ __device__ __forceinline__ void zspline_weights(int m, T t, T* w);
 
 // cos(pi x) for the general Fourier encoding.  With n the integer nearest x
 // and t = x - n (both exact), cos(pi x) = (-1)^n cos(pi t), |t| <= 1/2, and
-// cos(pi t) is its Taylor series in z = pi t up to z^22 (remainder below
-// 1e-19 for |z| <= pi/2; absolute error a few 1e-16 in all).  The library
-// cospi's general argument handling cost about twice the instructions per mode.
-// Coefficients (-1)^k / (2k)!.  Tab: from constant memory (scalar operands of
-// the FMAs); otherwise literals, which the mode loop keeps in vector
-// registers.  The 2-D kernels embed every velocity family and spill the
-// scalar registers the table takes, so only 3-D grids use it.  Not static,
-// for the reason given at kTaylorSinCos.
-__constant__ double kCosTaylor[12] = {
-    1.0,           -1.0 / 2,          1.0 / 24,           -1.0 / 720,
-    1.0 / 40320,   -1.0 / 3628800,    1.0 / 479001600,    -1.0 / 87178291200.0,
-    1.0 / 20922789888000.0, -1.0 / 6402373705728000.0, 1.0 / 2432902008176640000.0,
-    -1.0 / 1124000727777607680000.0};
+// cos(pi t) = 1 + s P(s), s = t^2, with P the degree-7 Chebyshev interpolant
+// of (cos(pi sqrt(s)) - 1) / s on [0, 1/4] (interpolation error below 1e-20;
+// absolute error of the evaluation about 2e-16).  Coefficients, constant term
+// first, from csrc/cospi_poly.py.  The library cospi's general argument
+// handling cost about twice the instructions per mode, and the Taylor series
+// in pi t it replaced took four more.  Tab: from constant memory (scalar
+// operands of the FMAs); otherwise literals, which the mode loop keeps in
+// vector registers.  The 2-D kernels embed every velocity family and spill
+// the scalar registers the table takes, so only 3-D grids use it.  Not
+// static, for the reason given at kTaylorSinCos.
+__constant__ double kCosPiPoly[8] = {
+    -4.934802200544679,    4.058712126416736,      -1.3352627688518803,
+    0.2353306302721577,    -0.02580689002587539,   0.001929562652479866,
+    -0.00010458286368326585, 4.166399462726949e-06};
 
 template <bool Tab>
-__device__ __forceinline__ double cospi_taylor(double x) {
+__device__ __forceinline__ double cospi_poly(double x) {
   const double n = rint(x);
   const double t = x - n;
-  const double z = 3.141592653589793 * t, z2 = z * z;
+  const double s = t * t;
   double p;
   if constexpr (Tab) {
-    const double* k = kCosTaylor;
-    p = k[11];
+    const double* k = kCosPiPoly;
+    p = k[7];
 #pragma unroll
-    for (int i = 10; i >= 0; --i) p = fma(p, z2, k[i]);
+    for (int i = 6; i >= 0; --i) p = fma(p, s, k[i]);
   } else {
-    p = -1.0 / 1124000727777607680000.0;
-    p = fma(p, z2, 1.0 / 2432902008176640000.0);
-    p = fma(p, z2, -1.0 / 6402373705728000.0);
-    p = fma(p, z2, 1.0 / 20922789888000.0);
-    p = fma(p, z2, -1.0 / 87178291200.0);
-    p = fma(p, z2, 1.0 / 479001600.0);
-    p = fma(p, z2, -1.0 / 3628800.0);
-    p = fma(p, z2, 1.0 / 40320.0);
-    p = fma(p, z2, -1.0 / 720.0);
-    p = fma(p, z2, 1.0 / 24.0);
-    p = fma(p, z2, -0.5);
-    p = fma(p, z2, 1.0);
+    p = 4.166399462726949e-06;
+    p = fma(p, s, -0.00010458286368326585);
+    p = fma(p, s, 0.001929562652479866);
+    p = fma(p, s, -0.02580689002587539);
+    p = fma(p, s, 0.2353306302721577);
+    p = fma(p, s, -1.3352627688518803);
+    p = fma(p, s, 4.058712126416736);
+    p = fma(p, s, -4.934802200544679);
   }
+  p = fma(p, s, 1.0);
   const double h = 0.5 * n;
   return h != rint(h) ? -p : p;
 }
@@ -279,7 +283,7 @@ __device__ __forceinline__ void velocity(const VelArgs& v, const double* x, doub
       const Mode& md = v.mode[q];
       double th = md.gen.phase_over_pi;
       for (int a = 0; a < D; ++a) th += md.gen.c[a] * x[a];
-      const double cs = cospi_taylor<D == 3>(th);
+      const double cs = cospi_poly<D == 3>(th);
       for (int a = 0; a < D; ++a) u[a] += md.amp[a] * cs;
     }
   } else if constexpr (VK == SL_VEL_GRIDDED) {
@@ -334,6 +338,17 @@ __device__ __forceinline__ void velocity(const VelArgs& v, const double* x, doub
   }
 }
 
+// a / b with y = RN(1 / b) given: q = RN(a y) corrected once by the exact
+// remainder a - b q (an FMA), q + (a - b q) y, which is Markstein's
+// correction step (P. Markstein, IBM J. Res. Dev. 34(1), 1990); for the
+// moderate magnitudes here it returns the correctly rounded quotient, so a
+// displacement of whole cells stays exact.  Three operations against the
+// ten of a general division.
+__device__ __forceinline__ double div_by(double a, double b, double y) {
+  const double q = a * y;
+  return fma(fma(-q, b, a), y, q);
+}
+
 // ---------------------------------------------------------------------------
 // Velocity at the Runge-Kutta stage points of one lattice node.  The stage
 // points are x0 + delta with delta a few cells at most, so the periodic
@@ -362,11 +377,25 @@ __device__ __forceinline__ void sincospi_near0(double d, double* s, double* c) {
   }
 }
 
-// sin/cos(pi (x0 + d)) from s0 = sin(pi x0), c0 = cos(pi x0).
-__device__ __forceinline__ void sincospi_shift(double s0, double c0, double d, double* s,
-                                               double* c) {
+// The same for |d| <= kSmallShift (z <= 0.0246), with the series to z^7 / z^6:
+// truncation below 1e-20 (sin) and 4e-18 (cos).
+constexpr double kSmallShift = 1.0 / 128;
+__device__ __forceinline__ void sincospi_small(double d, double* s, double* c) {
+  const double z = 3.141592653589793 * d, z2 = z * z;
+  const double* k = kTaylorSinCos;
+  *s = z * (k[4] + z2 * (k[3] + z2 * (k[2] + z2 * k[1])));
+  *c = k[10] + z2 * (k[9] + z2 * (k[8] + z2 * k[7]));
+}
+
+// sin/cos(pi (x0 + d)) from s0 = sin(pi x0), c0 = cos(pi x0).  `small`
+// (wave-uniform): |d| <= kSmallShift is known for every stage offset.
+__device__ __forceinline__ void sincospi_shift(double s0, double c0, double d, bool small,
+                                               double* s, double* c) {
   double sd, cd;
-  sincospi_near0(d, &sd, &cd);
+  if (small)
+    sincospi_small(d, &sd, &cd);
+  else
+    sincospi_near0(d, &sd, &cd);
   *s = s0 * cd + c0 * sd;
   *c = c0 * cd - s0 * sd;
 }
@@ -374,11 +403,13 @@ __device__ __forceinline__ void sincospi_shift(double s0, double c0, double d, d
 template <int VK, int D>
 struct NodeVelocity {
   double s0[3], c0[3];
+  bool small;  // every stage offset within kSmallShift (wave-uniform)
 
   // From the per-axis table of trig_table_kernel (sl_traj.h) instead: the
   // same values at a lattice node that sits on its mesh node (x0 = idx h).
   __device__ __forceinline__ void init_table(const double* __restrict__ trig, const GridArgs& g,
-                                             const int* idx) {
+                                             const int* idx, bool small_shift) {
+    small = small_shift;
     if constexpr (VK == SL_VEL_SWIRL2D || (VK == SL_VEL_DEFORM3D && D == 3) ||
                   VK == SL_VEL_FOURIER) {
       constexpr int NA = VK == SL_VEL_SWIRL2D ? 2 : D;
@@ -393,7 +424,8 @@ struct NodeVelocity {
   }
 
   // SL_VEL_FOURIER in the ik encoding: s0/c0 hold sin/cos(pi y_a) at x0.
-  __device__ __forceinline__ void init(const VelArgs& v, const double* x0) {
+  __device__ __forceinline__ void init(const VelArgs& v, const double* x0, bool small_shift) {
+    small = small_shift;
     if constexpr (VK == SL_VEL_SWIRL2D || (VK == SL_VEL_DEFORM3D && D == 3)) {
       constexpr int NA = VK == SL_VEL_SWIRL2D ? 2 : 3;
 #pragma unroll
@@ -415,7 +447,7 @@ struct NodeVelocity {
 #pragma unroll
       for (int a = 0; a < NA; ++a) {
         if (delta) {
-          sincospi_shift(s0[a], c0[a], delta[a], &sn[a], &cs[a]);
+          sincospi_shift(s0[a], c0[a], delta[a], small, &sn[a], &cs[a]);
         } else {
           sn[a] = s0[a];
           cs[a] = c0[a];
@@ -441,7 +473,7 @@ struct NodeVelocity {
 #pragma unroll
           for (int a = 0; a < D; ++a) {
             if (delta) {
-              sincospi_shift(s0[a], c0[a], delta[a] * v.kscale[a], &sn[a], &cs[a]);
+              sincospi_shift(s0[a], c0[a], delta[a] * v.kscale[a], small, &sn[a], &cs[a]);
             } else {
               sn[a] = s0[a];
               cs[a] = c0[a];

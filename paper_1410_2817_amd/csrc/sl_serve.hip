@@ -710,12 +710,7 @@ int sl_server_admit(sl_server* s, const sl_grid_desc* desc, const void* const* f
     sl::serve_zero_kernel<<<1, 64, 0, s->stream>>>(s->done + r.entry, 1);
     e = hipGetLastError();
   }
-  if (e == hipSuccess && trig) {
-    const int axes = gr->g.n[0] + gr->g.n[1];
-    sl::trig_table_kernel<2><<<(axes + sl::kBlock - 1) / sl::kBlock, sl::kBlock, 0, s->stream>>>(
-        gr->g, gr->v, trig);
-    e = hipGetLastError();
-  }
+  if (e == hipSuccess && trig) e = sl::launch_trig_table<2>(gr->g, gr->v, trig, s->stream);
   for (int f = 0; f < desc->nfields && e == hipSuccess; ++f)
     e = hipMemcpyAsync(r.a[f], fields_in[f], vbytes * (size_t)gr->ntot,
                        hipMemcpyDeviceToDevice, s->stream);

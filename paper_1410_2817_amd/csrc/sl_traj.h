@@ -62,10 +62,11 @@ __device__ __forceinline__ void traj_node_with(const GridArgs& g, const VelArgs&
     d[a] = accumulate ? disp[(size_t)a * g.ntot + lin] : 0.0;
     x[a] = ((double)(idx[a] + g.off[a]) + d[a]) * g.h[a];
   }
+  const bool small = dt * v.shift_rate <= kSmallShift;
   if (trig && !accumulate)
-    vel.init_table(trig, g, idx);
+    vel.init_table(trig, g, idx, small);
   else
-    vel.init(v, x);
+    vel.init(v, x, small);
   if (integrator == SL_RK4) {
     double k1[D], k2[D], k3[D], k4[D], o[D];
     vel.eval(v, x, nullptr, st.tf[0], k1);
@@ -78,12 +79,12 @@ __device__ __forceinline__ void traj_node_with(const GridArgs& g, const VelArgs&
 #pragma unroll
     for (int a = 0; a < D; ++a) o[a] = dt * k3[a];
     vel.eval(v, x, o, st.tf[2], k4);
-    // One division per axis: dt (k1 + 2 k2 + 2 k3 + k4) / (6 h).  6 h is exact
-    // for power-of-two spacings, so uniform translations by whole cells stay
-    // exact.
+    // One quotient per axis: dt (k1 + 2 k2 + 2 k3 + k4) / (6 h), correctly
+    // rounded (div_by); 6 h is exact for power-of-two spacings, so uniform
+    // translations by whole cells stay exact.
 #pragma unroll
     for (int a = 0; a < D; ++a)
-      d[a] += dt * (k1[a] + 2.0 * k2[a] + 2.0 * k3[a] + k4[a]) / (6.0 * g.h[a]);
+      d[a] += div_by(dt * (k1[a] + 2.0 * k2[a] + 2.0 * k3[a] + k4[a]), 6.0 * g.h[a], g.r6h[a]);
   } else {
     // Williamson (1980) 2N-storage RK3: q = A_s q + dt u(x + dx, t + c_s dt),
     // dx += B_s q with A = (0, -5/9, -153/128), B = (1/3, 15/16, 8/15),
@@ -103,7 +104,7 @@ __device__ __forceinline__ void traj_node_with(const GridArgs& g, const VelArgs&
       }
     }
 #pragma unroll
-    for (int a = 0; a < D; ++a) d[a] += dx[a] / g.h[a];
+    for (int a = 0; a < D; ++a) d[a] += div_by(dx[a], g.h[a], g.rh[a]);
   }
 #pragma unroll
   for (int a = 0; a < D; ++a) disp[(size_t)a * g.ntot + lin] = d[a];
@@ -119,10 +120,20 @@ __device__ __forceinline__ void traj_node(const GridArgs& g, const VelArgs& v,
 }
 
 // Does the grid's velocity evaluator start from sin/cos(pi x0) per axis (so
-// that a fresh lattice can read them from the trig table)?
+// that a fresh lattice can read them from trig_table_kernel's table)?  (A
+// table of the general Fourier encoding's per-mode phase factors e^{i pi c x0}
+// was tried for the 3-D Fourier flow: its 16 x 3 loads per node cost more
+// than the cosines they replace, 1.99 -> 2.05 ms per 256^3 launch.)
 __host__ __device__ inline bool uses_trig_table(const VelArgs& v, int dim) {
   return (v.kind == SL_VEL_SWIRL2D && dim == 2) || (v.kind == SL_VEL_DEFORM3D && dim == 3) ||
          (v.kind == SL_VEL_FOURIER && v.small_k);
+}
+
+// Entries (double pairs) of the table: n_x + n_y (+ n_z).
+__host__ __device__ inline size_t trig_table_pairs(const GridArgs& g, int dim) {
+  size_t axes = 0;
+  for (int a = 0; a < dim; ++a) axes += (size_t)g.n[a];
+  return axes;
 }
 
 // sin/cos of pi times the first-stage argument of the evaluator, per axis a
@@ -150,6 +161,15 @@ __global__ __launch_bounds__(kBlock) void trig_table_kernel(GridArgs g, VelArgs 
   trig[base + g.n[a] + i] = c;
 }
 
+// Fills the grid's table (host side; `tab` holds trig_table_pairs pairs).
+template <int D>
+inline hipError_t launch_trig_table(const GridArgs& g, const VelArgs& v, double* tab,
+                                    hipStream_t s) {
+  const size_t n = trig_table_pairs(g, D);
+  trig_table_kernel<D><<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, s>>>(g, v, tab);
+  return hipGetLastError();
+}
+
 // Gridded velocity in 2-D with the samples around a tile staged in LDS: the
 // same Z-spline sum as velocity<SL_VEL_GRIDDED> (same weights, same order of
 // taps), read from the box [bx0, bx0 + W) x [by0, by0 + W) of mesh nodes
@@ -159,8 +179,8 @@ struct GriddedBox2D {
   const double* box;  // 2 planes of W x W samples
   int bx0, by0, W;
 
-  __device__ __forceinline__ void init(const VelArgs&, const double*) {}
-  __device__ __forceinline__ void init_table(const double*, const GridArgs&, const int*) {}
+  __device__ __forceinline__ void init(const VelArgs&, const double*, bool) {}
+  __device__ __forceinline__ void init_table(const double*, const GridArgs&, const int*, bool) {}
 
   __device__ __forceinline__ void eval(const VelArgs& v, const double* x0, const double* delta,
                                        double, double* u) const {
@@ -307,17 +327,19 @@ __global__ __launch_bounds__(kBlock) void carried_traj_kernel(GridArgs g, FieldP
   }
 }
 
+// `trig`: trig_table_kernel's table for a fresh lattice, or null.
 template <int D, int VK>
 __global__ __launch_bounds__(kBlock) void traj_kernel(GridArgs g, VelArgs v,
                                                       double* __restrict__ disp, StageTimes st,
                                                       double dt, int accumulate,
-                                                      int integrator) {
+                                                      int integrator,
+                                                      const double* __restrict__ trig) {
   int idx[D];
   idx[0] = blockIdx.x * kTrajBX + threadIdx.x;
   idx[1] = blockIdx.y * kTrajBY + threadIdx.y;
   if constexpr (D == 3) idx[2] = blockIdx.z;
   if (idx[0] >= g.n[0] || idx[1] >= g.n[1]) return;
-  traj_node<D, VK>(g, v, disp, st, dt, accumulate, integrator, idx);
+  traj_node<D, VK>(g, v, disp, st, dt, accumulate, integrator, idx, trig);
 }
 
 
