@@ -89,6 +89,7 @@ VALU_SIMDS, VALU_CYCLES_PER_INST, CLOCK_HZ = 1024, 4, 2.4e9
 VALU_JSON = os.path.join(PROFILES, "valu_counters.json")
 # Workload of each counter directory -> the kernels whose counts are kept.
 VALU_KERNELS = {"swirl_f32": ["recon2d_tiled_kernel<float, 3>"],
+                "swirl4096_f32": ["recon2d_tiled_kernel<float, 3>"],
                 "fourier3d_f32": ["recon3d_kernel<float, 3>"],
                 "deform3d_f64": ["recon3d_kernel<double, 1>"],
                 "deform3d_f32": ["recon3d_kernel<float, 1>"],
@@ -262,6 +263,7 @@ def make_workload(W, workload, n, prec):
 
 
 VALU_KEYS = {("swirl", 1024, "f32"): "swirl_f32/recon2d_tiled_kernel<float, 3>",
+             ("swirl", 4096, "f32"): "swirl4096_f32/recon2d_tiled_kernel<float, 3>",
              ("fourier3d", 256, "f32"): "fourier3d_f32/recon3d_kernel<float, 3>",
              ("deform3d", 512, "f64"): "deform3d_f64/recon3d_kernel<double, 1>",
              ("deform3d", 512, "f32"): "deform3d_f32/recon3d_kernel<float, 1>",
@@ -561,7 +563,8 @@ def other_configs():
                             "order_words_avg_ms": prof["orders_ms"] / max(prof["orders_launches"], 1),
                             "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
                                          "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
-                                         "bytes_per_node": per_node}}
+                                         "bytes_per_node": per_node},
+                            "valu_roof": valu_roof(VALU_KEYS[("swirl", 4096, "f32")], rms)}
     del out
 
     # 3-D configurations.
