@@ -299,16 +299,30 @@ hipError_t launch_order_words(sl_grid* gr, const sl::FieldPtrs& fp, char* ws, hi
     auto* f4 = reinterpret_cast<uint32_t*>(flags);
     auto* qa = reinterpret_cast<unsigned long long*>(wa);
     auto* qb2 = reinterpret_cast<unsigned long long*>(wb);
-    e = launch(sl::flags_quad_kernel<D, T>, qb, wt, 0, s, e0, nullptr, gr->g, fp, f4);
-    if (e == hipSuccess)
-      e = launch(sl::window_x_quad_kernel, qb, wt, 0, s, nullptr, nullptr, gr->g,
-                 (const uint32_t*)f4, qa);
-    if (e == hipSuccess)
-      e = launch(sl::window_yz_quad_kernel<1>, qb, wt, 0, s, nullptr, D == 2 ? e1 : nullptr,
-                 gr->g, (const unsigned long long*)qa, qb2);
-    if (e == hipSuccess && D == 3)
-      e = launch(sl::window_yz_quad_kernel<2>, qb, wt, 0, s, nullptr, e1, gr->g,
-                 (const unsigned long long*)qb2, qa);
+    const int nq = gr->g.n[0] / 4;
+    if (nq <= sl::kBlock) {
+      // Whole rows per workgroup: flags and x window in one pass.
+      const int rows = sl::kBlock / nq;
+      const dim3 fb((unsigned)((gr->g.n[1] + rows - 1) / rows), (unsigned)gr->g.n[2]);
+      e = launch(sl::flags_window_x_kernel<D, T>, fb, dim3(sl::kBlock), 0, s, e0, nullptr,
+                 gr->g, fp, qa);
+    } else {
+      e = launch(sl::flags_quad_kernel<D, T>, qb, wt, 0, s, e0, nullptr, gr->g, fp, f4);
+      if (e == hipSuccess)
+        e = launch(sl::window_x_quad_kernel, qb, wt, 0, s, nullptr, nullptr, gr->g,
+                   (const uint32_t*)f4, qa);
+    }
+    if (e == hipSuccess && D == 2)
+      e = launch(sl::window_yz_quad_kernel<1>, qb, wt, 0, s, nullptr, e1, gr->g,
+                 (const unsigned long long*)qa, qb2);
+    if (e == hipSuccess && D == 3) {
+      // The y and z windows in one pass, marching through chunks of planes.
+      const dim3 zb(qb.x, qb.y, (unsigned)((gr->g.n[2] + sl::kZChunk - 1) / sl::kZChunk));
+      e = launch(sl::window_yz3_quad_kernel, zb, wt, 0, s, nullptr, e1, gr->g,
+                 (const unsigned long long*)qa, qb2);
+    }
+    *ord = wb;
+    return e;
   } else {
     const dim3 fb((unsigned)((gr->ntot + sl::kBlock - 1) / sl::kBlock)), ft(sl::kBlock);
     e = launch(sl::flags_kernel<D, T>, fb, ft, 0, s, e0, nullptr, gr->g, fp, flags);

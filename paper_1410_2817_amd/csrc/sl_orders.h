@@ -174,4 +174,128 @@ __global__ __launch_bounds__(256) void window_yz_quad_kernel(
   out4[lin] = lo | hi;
 }
 
+// Flags and x window in one pass, for rows of at most kBlock quads: a
+// workgroup holds R = kBlock / nq whole rows (nq = n0 / 4 quads per row), so
+// the x neighbours of every quad, the periodic ones included, are in its LDS
+// and the flag bytes never reach memory.  Work-item t takes quad t % nq of
+// row t / nq; the flags are the ones flags_quad_kernel computes, the window
+// the one window_x_quad_kernel forms.  Grid: (ceil(n1 / R), n2) of kBlock.
+template <int D, typename T>
+__global__ __launch_bounds__(kBlock) void flags_window_x_kernel(GridArgs g, FieldPtrs fp,
+                                                                unsigned long long* __restrict__ out4) {
+  using V4 = T __attribute__((ext_vector_type(4)));
+  __shared__ uint32_t s_f[kBlock];
+  const int nq = g.n[0] / 4, R = kBlock / nq;
+  const int t = (int)threadIdx.x, q = t % nq, row = t / nq;
+  const int y = blockIdx.x * R + row, z = blockIdx.y;
+  const bool ok = row < R && y < g.n[1];
+  if (ok) {
+    const int n0 = g.n[0], n1 = g.n[1], n2 = g.n[2];
+    const int x = 4 * q;
+    const int ym = y == 0 ? n1 - 1 : y - 1, yp = y + 1 == n1 ? 0 : y + 1;
+    const int zm = z == 0 ? n2 - 1 : z - 1, zp = z + 1 == n2 ? 0 : z + 1;
+    const int rw = n0 * (y + n1 * z);
+    const int rym = n0 * (ym + n1 * z), ryp = n0 * (yp + n1 * z);
+    const int rzm = n0 * (y + n1 * zm), rzp = n0 * (y + n1 * zp);
+    const int xm = x == 0 ? n0 - 1 : x - 1, xp = x + 4 == n0 ? 0 : x + 4;
+    unsigned bits = 0;
+    for (int f = 0; f < g.nfields; ++f) {
+      const T* __restrict__ h = static_cast<const T*>(fp.in[f]);
+      const V4 c = *reinterpret_cast<const V4*>(h + rw + x);
+      const V4 vym = *reinterpret_cast<const V4*>(h + rym + x);
+      const V4 vyp = *reinterpret_cast<const V4*>(h + ryp + x);
+      const V4 vzm = D == 3 ? *reinterpret_cast<const V4*>(h + rzm + x) : c;
+      const V4 vzp = D == 3 ? *reinterpret_cast<const V4*>(h + rzp + x) : c;
+      const double l = (double)h[rw + xm], r = (double)h[rw + xp];
+      const double cc[4] = {(double)c.x, (double)c.y, (double)c.z, (double)c.w};
+      const double am[4] = {(double)vym.x, (double)vym.y, (double)vym.z, (double)vym.w};
+      const double ap[4] = {(double)vyp.x, (double)vyp.y, (double)vyp.z, (double)vyp.w};
+      const double bm[4] = {(double)vzm.x, (double)vzm.y, (double)vzm.z, (double)vzm.w};
+      const double bp[4] = {(double)vzp.x, (double)vzp.y, (double)vzp.z, (double)vzp.w};
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const double hm = j == 0 ? l : cc[j - 1], hp = j == 3 ? r : cc[j + 1];
+        const bool fl = jump_flag(hm, cc[j], hp, g.theta) ||
+                        jump_flag(am[j], cc[j], ap[j], g.theta) ||
+                        (D == 3 && jump_flag(bm[j], cc[j], bp[j], g.theta));
+        bits |= (fl ? 1u : 0u) << (8 * j + f);
+      }
+    }
+    s_f[t] = bits;
+  }
+  __syncthreads();
+  if (!ok) return;
+  const int base = row * nq;
+  const unsigned w[3] = {s_f[base + (q == 0 ? nq - 1 : q - 1)], s_f[t],
+                         s_f[base + (q + 1 == nq ? 0 : q + 1)]};
+  unsigned b[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) b[k] = (w[k / 4] >> (8 * (k % 4))) & 0xffu;
+  unsigned long long o = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    unsigned lo = 0, hi = 0;
+#pragma unroll
+    for (int k = 2; k <= 7; ++k) lo |= b[j + k];
+#pragma unroll
+    for (int k = 3; k <= 6; ++k) hi |= b[j + k];
+    o |= (unsigned long long)(lo | (hi << 8)) << (16 * j);
+  }
+  out4[nq * (y + g.n[1] * z) + q] = o;
+}
+
+// The y and z window passes of a 3-D grid in one: the low bytes OR over the
+// 6 x 6 (y, z) block y-2..y+3, z-2..z+3 of the x-window words and the high
+// bytes over the 4 x 4 block y-1..y+2, z-1..z+2 (the two separable passes
+// composed).  A 64 x 4 workgroup owns 64 quads x 4 rows and marches through
+// kZChunk planes: each plane's rows y0-2..y0+6 go through LDS (two buffers,
+// one barrier per plane), each work-item forms its y window and keeps the
+// last six in registers for the z window.  Every input word is read from
+// memory once per chunk (plus the 5-plane halo), every output written once.
+// Grid: (ceil(nq / 64), ceil(n1 / 4), ceil(n2 / kZChunk)) of 64 x 4.
+constexpr int kZChunk = 32;
+__global__ __launch_bounds__(256) void window_yz3_quad_kernel(
+    GridArgs g, const unsigned long long* __restrict__ in4, unsigned long long* __restrict__ out4) {
+  constexpr unsigned long long LO = 0x00ff00ff00ff00ffull, HI = 0xff00ff00ff00ff00ull;
+  __shared__ unsigned long long s_rows[2][9][64];
+  const int nq = g.n[0] / 4, n1 = g.n[1], n2 = g.n[2];
+  const int tq = (int)threadIdx.x, ty = (int)threadIdx.y;
+  const int q = blockIdx.x * 64 + tq;
+  const int y0 = blockIdx.y * 4, y = y0 + ty;
+  const int z0 = blockIdx.z * kZChunk, z1 = min(z0 + kZChunk, n2);
+  const bool qok = q < nq;
+  unsigned long long lo[6] = {0, 0, 0, 0, 0, 0}, hi[6] = {0, 0, 0, 0, 0, 0};
+  // Rows and planes wrap periodically (n1, n2 >= 6).
+  int zw = z0 - 2 < 0 ? z0 - 2 + n2 : z0 - 2;
+  for (int k = 0; k < z1 - z0 + 5; ++k) {
+    const int buf = k & 1;
+    for (int rr = ty; rr < 9; rr += 4) {
+      int yy = y0 - 2 + rr;
+      yy = yy < 0 ? yy + n1 : (yy >= n1 ? yy - n1 : yy);
+      s_rows[buf][rr][tq] = qok ? in4[q + nq * (yy + n1 * zw)] : 0ull;
+    }
+    __syncthreads();
+    unsigned long long l = 0, h = 0;
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+      const unsigned long long v = s_rows[buf][ty + d][tq];
+      l |= v & LO;
+      if (d >= 1 && d <= 4) h |= v & HI;
+    }
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+      lo[j] = lo[j + 1];
+      hi[j] = hi[j + 1];
+    }
+    lo[5] = l;
+    hi[5] = h;
+    if (k >= 5 && qok && y < n1) {
+      const int zo = z0 + k - 5;
+      out4[q + nq * (y + n1 * zo)] =
+          (lo[0] | lo[1] | lo[2] | lo[3] | lo[4] | lo[5]) | (hi[1] | hi[2] | hi[3] | hi[4]);
+    }
+    zw = zw + 1 == n2 ? 0 : zw + 1;
+  }
+}
+
 }  // namespace sl
