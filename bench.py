@@ -43,6 +43,14 @@ TRAFFIC = {
 HEADLINE = ("deform3d", 512, "f64")
 
 
+_T0 = time.perf_counter()
+
+
+def note(msg):
+    """Progress of a long run, on stderr (the JSON line stays alone on stdout)."""
+    print("[bench %7.1f s] %s" % (time.perf_counter() - _T0, msg), file=sys.stderr, flush=True)
+
+
 def source_hash() -> str:
     """Hash of every HIP source and the C header, to tell whether recorded
     counters still apply to the kernels as built."""
@@ -218,7 +226,7 @@ def parse():
                     help="time without kernel events")
     ap.add_argument("--event-period", type=int, default=8,
                     help="attach timing events to every N-th launch of each kernel kind")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+    ap.add_argument("--cpu-seconds", type=float, default=20.0,
                     help="wall-clock budget of the oracle sample")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of known size (for PMC scaling)")
@@ -383,12 +391,14 @@ def main():
                     "event_period": args.event_period},
         "accuracy": acc,
     }
+    note("headline: %d steps, %.4g node-updates/s" % (args.steps, value))
     if not args.no_configs and headline:
         out["precision_forms"] = precision_forms()
         out["configs"] = other_configs()
     if not args.no_serving and headline:
         out["serving"] = run_serving(args.serving_requests, args.serving_budget_gib)
     if not args.no_cpu_baseline:
+        note("CPU baseline (the oracle on the host)")
         if dim == 3:
             cpu, vs = sampled_cpu_baseline(wl, stored, args.cpu_seconds)
             out["cpu_baseline"] = cpu
@@ -505,6 +515,7 @@ def precision_forms():
         entry["split_vs_plain_l1_rel"] = [_l1(a, b) for a, b in zip(forms["f32"][0],
                                                                       forms["f64"][0])]
         res[name] = entry
+        note("precision forms: %s" % name)
     return res
 
 
@@ -527,6 +538,7 @@ def other_configs():
     rms = prof["recon_ms"] / max(prof["recon_launches"], 1)
     per_node = recon_bytes_per_node(2, wl.nfields, 4) + traj_bytes_per_node(2)
     ach = per_node * wl.nodes / (rms * 1e-3) / 1e9
+    note("config swirl1024_f32")
     res["swirl1024_f32"] = {
         "node_updates_per_s": wl.nodes * wl.nsteps / el, "ms_per_step": el * 1e3 / wl.nsteps,
         "steps": wl.nsteps,
@@ -545,6 +557,7 @@ def other_configs():
     exact = np.asarray(wl.fields[0], np.float64)
     prob = _oracle_problem(oracle, wl)
     rc, ofs, _ = oracle.run(prob, 0.0, wl.dt, 100, [exact])
+    note("config sbr64_f64")
     res["sbr64_f64"] = {"node_updates_per_s": wl.nodes * 100 / el, "ms_per_step": el * 1e3 / 100,
                         "l1_rel_vs_exact": _l1(got, exact), "l1_rel_vs_oracle": _l1(got, ofs[0]),
                         "linf_vs_oracle": float(np.abs(got - ofs[0]).max())}
@@ -557,6 +570,7 @@ def other_configs():
     rms = prof["recon_ms"] / max(prof["recon_launches"], 1)
     per_node = recon_bytes_per_node(2, wl.nfields, 4) + traj_bytes_per_node(2)
     ach = per_node * wl.nodes / (rms * 1e-3) / 1e9
+    note("config swirl4096_f32")
     res["swirl4096_f32"] = {"node_updates_per_s": wl.nodes * n4 / el, "ms_per_step": el * 1e3 / n4,
                             "steps": n4, "reconstruction_avg_ms": rms,
                             "trajectories_avg_ms": prof["traj_ms"] / max(prof["traj_launches"], 1),
@@ -574,6 +588,7 @@ def other_configs():
     keep = {}
     for name, wl, nsteps, prec in cases:
         out, el, prof, st = run_gpu(wl, nsteps, prec=prec)
+        note("config %s" % name)
         rms = prof["recon_ms"] / max(prof["recon_launches"], 1)
         vb = 4 if prec == "f32" else 8
         per_node = recon_bytes_per_node(3, wl.nfields, vb) + traj_bytes_per_node(3)
@@ -596,6 +611,7 @@ def other_configs():
     res["deform3d_512_f32"]["l1_rel_vs_f64_plain"] = _l1(keep["f32"], keep["f64"])
     del keep
     res["deform3d_512_f64_shard"] = shard_config(W.deform3d_slotted_sphere(512), 60)
+    note("config deform3d_512_f64_shard")
 
     # Burgers' equation (velocity carried by the fields), the paper's radial
     # shock test at 512^2 up to t = 0.3, plus its first 20 steps against the
@@ -605,6 +621,7 @@ def other_configs():
     brms = prof["recon_ms"] / max(prof["recon_launches"], 1)
     # Each launch reconstructs 2 FP64 fields and writes the next displacement.
     bgbs = (recon_bytes_per_node(2, 2, 8) + traj_bytes_per_node(2)) * wl.nodes / (brms * 1e-3) / 1e9
+    note("config burgers2d_512_f64")
     res["burgers2d_512_f64"] = {"node_updates_per_s": wl.nodes * wl.nsteps / el,
                                 "ms_per_step": el * 1e3 / wl.nsteps, "steps": wl.nsteps,
                                 "reconstruction_avg_ms": brms,
@@ -632,6 +649,7 @@ def other_configs():
     # displacement.
     g_rec = recon_bytes_per_node(2, 3, 4) * wl.nodes / (grms * 1e-3) / 1e9
     g_trj = (16 + traj_bytes_per_node(2)) * wl.nodes / (gtms * 1e-3) / 1e9
+    note("config gridded_swirl1024_f32")
     res["gridded_swirl1024_f32"] = {
         "node_updates_per_s": wl.nodes * 160 / el, "ms_per_step": el * 1e3 / 160, "steps": 160,
         "trajectories_avg_ms": gtms, "reconstruction_avg_ms": grms,
@@ -646,6 +664,7 @@ def other_configs():
         sum(float(np.abs(g - o).sum()) for g, o in zip(got, ofs)) /
         sum(float(np.abs(o).sum()) for o in ofs))
     res.update(kelvin_configs())
+    note("config kelvin")
     return res
 
 
@@ -774,6 +793,7 @@ def run_serving(count: int, budget_gib: float):
     modes = {}
     for mode, window in SERVING_MODES:
         r = _serving_mode(count, budget_gib, mode, window)
+        note("serving %s window %d" % (mode, window))
         modes["%s_w%d" % (mode, window)] = r
         if res is None:
             res = dict(r)

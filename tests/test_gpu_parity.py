@@ -381,12 +381,14 @@ def test_full_size_3d_sampled(B, torch, orc, which):
     ("swirl96_f32", W.swirl_three_fields(96, value_prec="f32")),
     ("swirl96_f64", W.swirl_three_fields(96, value_prec="f64")),
     ("swirl70_f64", W.swirl_three_fields(70, value_prec="f64")),
+    ("swirl1280_f32", W.swirl_three_fields(1280, value_prec="f32")),
 ])
 def test_2d_limiter_paths_agree_bitwise(B, torch, name, wl):
     """2-D grids take the limiter flags either inside the reconstruction
     tiles or from the separate order-word pass (quad kernels when rows are a
-    multiple of 4, scalar ones otherwise); both give the same orders, so the
-    results are bitwise equal."""
+    multiple of 4: flags and x window in one launch for rows of up to 256
+    quads, as at 96, in two beyond, as at 1280; scalar kernels otherwise, as
+    at 70); both give the same orders, so the results are bitwise equal."""
     outs = []
     for where in (B.SL_LIMITER_IN_TILES, B.SL_LIMITER_ORDER_WORDS):
         out, st, rc, _ = gpu_run(B, torch, wl, nsteps=3, t0=1.1, limiter_pass=where)
