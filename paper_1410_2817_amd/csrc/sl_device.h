@@ -133,22 +133,34 @@ __device__ __forceinline__ int wrap_near(int v, int n) {
 }
 
 // Butterfly reductions over the 64 lanes of a wave (all lanes active).
+// Wave-wide reductions over the 64 lanes with DPP lane moves (all lanes must
+// be active): two quad exchanges, the half-row and row mirrors reduce each
+// row of 16, then the broadcasts of lanes 15 and 31 into the following rows
+// gather the whole wave in lane 63, which is read out as a wave-uniform
+// value.  Each step is one VALU instruction with no LDS round trip (a
+// butterfly of shuffles went through ds_bpermute and waited on LDS at every
+// step).
+template <class Op>
+__device__ __forceinline__ int wave_reduce(int v, int identity, Op op) {
+  v = op(v, __builtin_amdgcn_mov_dpp(v, 0xb1, 0xf, 0xf, false));   // quad_perm 1,0,3,2
+  v = op(v, __builtin_amdgcn_mov_dpp(v, 0x4e, 0xf, 0xf, false));   // quad_perm 2,3,0,1
+  v = op(v, __builtin_amdgcn_mov_dpp(v, 0x141, 0xf, 0xf, false));  // row_half_mirror
+  v = op(v, __builtin_amdgcn_mov_dpp(v, 0x140, 0xf, 0xf, false));  // row_mirror
+  v = op(v, __builtin_amdgcn_update_dpp(identity, v, 0x142, 0xa, 0xf, false));  // row_bcast:15
+  v = op(v, __builtin_amdgcn_update_dpp(identity, v, 0x143, 0xc, 0xf, false));  // row_bcast:31
+  return __builtin_amdgcn_readlane(v, 63);
+}
+
 __device__ __forceinline__ int wave_min(int v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
-  return v;
+  return wave_reduce(v, INT_MAX, [](int a, int b) { return min(a, b); });
 }
 
 __device__ __forceinline__ int wave_max(int v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
-  return v;
+  return wave_reduce(v, INT_MIN, [](int a, int b) { return max(a, b); });
 }
 
 __device__ __forceinline__ unsigned wave_sum(unsigned v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
+  return (unsigned)wave_reduce((int)v, 0, [](int a, int b) { return (int)((unsigned)a + (unsigned)b); });
 }
 
 // Adds the number of active lanes with `pred` to *ctr, one atomic per wave and
