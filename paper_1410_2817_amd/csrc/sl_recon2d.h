@@ -353,18 +353,27 @@ __device__ __forceinline__ void recon2d_tile(const GridArgs& g, const FieldPtrs&
       for (int by2 = 2 * wave; by2 < BY; by2 += 2 * (kTileThreads / 64)) {
         const int by = by2 + (lane >> 5);
         const bool in = bx < BX && by < BY;
-        const int c = (bx + 1) + VX * (by + 1);
+        // Idle lanes read box node (0, 0), so that every lane loads: all
+        // fields' stencils are then in flight together instead of one
+        // field's after another's (1024^2 step 47.0 -> 46.1 us).
+        const int c = in ? (bx + 1) + VX * (by + 1) : VX + 1;
+        T hs[nf][5];
 #pragma unroll
         for (int f = 0; f < nf; ++f) {
           const T* lv = lval + (size_t)f * nval;
+          hs[f][0] = lv[c];
+          hs[f][1] = lv[c - 1];
+          hs[f][2] = lv[c + 1];
+          hs[f][3] = lv[c - VX];
+          hs[f][4] = lv[c + VX];
+        }
+#pragma unroll
+        for (int f = 0; f < nf; ++f) {
           // FP64 issues at the FP32 (non-packed) rate on CDNA4, so the exact
           // criterion on the stored values costs no more than a screen.
-          bool fx = false, fy = false;
-          if (in) {
-            const double hc = (double)lv[c];
-            fx = jump_flag((double)lv[c - 1], hc, (double)lv[c + 1], g.theta);
-            fy = jump_flag((double)lv[c - VX], hc, (double)lv[c + VX], g.theta);
-          }
+          const double hc = (double)hs[f][0];
+          const bool fx = jump_flag((double)hs[f][1], hc, (double)hs[f][2], g.theta);
+          const bool fy = jump_flag((double)hs[f][3], hc, (double)hs[f][4], g.theta);
           const unsigned long long m = __ballot(in && (fx || fy));
           if (lane == 0) {
             lbits[f * BY + by2] = (unsigned)m;
