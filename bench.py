@@ -37,7 +37,7 @@ PROFILES = os.path.join(ROOT, "profiles")
 # The measured workloads whose reconstruction kernel has an HBM traffic record
 # (rocprofv3 FETCH_SIZE / WRITE_SIZE): (workload, n, prec) -> (kernel, file).
 TRAFFIC = {
-    ("deform3d", 512, "f64"): ("recon3d_kernel<double, 1>", "recon3d_deform512_f64_traffic.json"),
+    ("deform3d", 512, "f64"): ("recon3d_kernel<double, 1, 3>", "recon3d_deform512_f64_traffic.json"),
     ("swirl", 1024, "f32"): ("recon2d_tiled_kernel<float, 3>", "recon2d_swirl1024_traffic.json"),
 }
 HEADLINE = ("deform3d", 512, "f64")
@@ -99,8 +99,8 @@ VALU_JSON = os.path.join(PROFILES, "valu_counters.json")
 VALU_KERNELS = {"swirl_f32": ["recon2d_tiled_kernel<float, 3>"],
                 "swirl4096_f32": ["recon2d_tiled_kernel<float, 3>"],
                 "fourier3d_f32": ["recon3d_kernel<float, 3>"],
-                "deform3d_f64": ["recon3d_kernel<double, 1>"],
-                "deform3d_f32": ["recon3d_kernel<float, 1>"],
+                "deform3d_f64": ["recon3d_kernel<double, 1, 3>"],
+                "deform3d_f32": ["recon3d_kernel<float, 1, 3>"],
                 "kelvin_f64": ["recon2d_tiled_kernel<double, 3>", "sw_stage_kernel<double, 2>"]}
 
 
@@ -273,8 +273,8 @@ def make_workload(W, workload, n, prec):
 VALU_KEYS = {("swirl", 1024, "f32"): "swirl_f32/recon2d_tiled_kernel<float, 3>",
              ("swirl", 4096, "f32"): "swirl4096_f32/recon2d_tiled_kernel<float, 3>",
              ("fourier3d", 256, "f32"): "fourier3d_f32/recon3d_kernel<float, 3>",
-             ("deform3d", 512, "f64"): "deform3d_f64/recon3d_kernel<double, 1>",
-             ("deform3d", 512, "f32"): "deform3d_f32/recon3d_kernel<float, 1>",
+             ("deform3d", 512, "f64"): "deform3d_f64/recon3d_kernel<double, 1, 3>",
+             ("deform3d", 512, "f32"): "deform3d_f32/recon3d_kernel<float, 1, 3>",
              ("kelvin", 1024, "f64"): "kelvin_f64/recon2d_tiled_kernel<double, 3>"}
 
 
@@ -604,7 +604,7 @@ def other_configs():
                      "order_words_avg_ms": prof["orders_ms"] / max(prof["orders_launches"], 1),
                      "hbm_achieved_gbs": ach, "hbm_frac": ach / HBM_PEAK_GBS,
                      "valu_roof": valu_roof({"fourier3d_256_f32": "fourier3d_f32/recon3d_kernel<float, 3>",
-                                             "deform3d_512_f32": "deform3d_f32/recon3d_kernel<float, 1>"}
+                                             "deform3d_512_f32": "deform3d_f32/recon3d_kernel<float, 1, 3>"}
                                             .get(name, ""), rms),
                      "order_hist": st["order_hist"], "walked": st["walked"]}
     # Split form against plain FP64 after the same 60 steps.

@@ -187,7 +187,22 @@ __device__ __forceinline__ int cell_solve3d(const GridArgs& g, const double* __r
 // non-zero when one field's bytes fit the 31-bit buffer offsets, `dbuf_ok`
 // when one displacement component's do; `nt` / `v`: the next step's
 // trajectories of the tile's nodes (NextTraj).
-template <typename T, int NF>
+// The next step's trajectory of lattice node tgt (a fresh lattice): family VK,
+// or the grid's family at run time when VK < 0.
+template <int VK>
+__device__ __forceinline__ void next_traj3d(const GridArgs& g, const VelArgs& v,
+                                            const NextTraj& nt, const int* tgt) {
+  if constexpr (VK < 0)
+    traj_any<3>(g, v, nt.disp, nt.st, nt.dt, nt.integrator, tgt, nt.trig);
+  else
+    traj_node<3, VK>(g, v, nt.disp, nt.st, nt.dt, 0, nt.integrator, tgt, nt.trig);
+}
+
+// VK: the velocity family of the fused next-step trajectories when the kernel
+// is specialised for one (the deformational flow with one field, whose
+// registers then need not cover every family's), or -1 for the run-time
+// switch over all of them.
+template <typename T, int NF, int VK = -1>
 __global__ __launch_bounds__(kTileThreads, (Box3D<T, NF>::WAVES)) void recon3d_kernel(
     GridArgs g, FieldPtrs fp, const double* __restrict__ gdisp,
     const uint16_t* __restrict__ ord, unsigned long long* __restrict__ stats, int tiles_x,
@@ -222,7 +237,7 @@ __global__ __launch_bounds__(kTileThreads, (Box3D<T, NF>::WAVES)) void recon3d_k
   constexpr bool OVERLAP = X::STAGE && X::BZ * nf * (int)sizeof(T) <= 96;
   if constexpr (!OVERLAP) {
     if (nt.disp && !nt.carried && act)
-      traj_any<3>(g, v, nt.disp, nt.st, nt.dt, nt.integrator, tgt, nt.trig);
+      next_traj3d<VK>(g, v, nt, tgt);
   }
 
   // 1. Own displacement and start cell.
@@ -263,7 +278,7 @@ __global__ __launch_bounds__(kTileThreads, (Box3D<T, NF>::WAVES)) void recon3d_k
         gz = gz + 1 == g.n[2] ? 0 : gz + 1;
       }
       if (nt.disp && !nt.carried && act)
-        traj_any<3>(g, v, nt.disp, nt.st, nt.dt, nt.integrator, tgt, nt.trig);
+        next_traj3d<VK>(g, v, nt, tgt);
 #pragma unroll
       for (int bz = 0; bz < X::BZ; ++bz)
 #pragma unroll
