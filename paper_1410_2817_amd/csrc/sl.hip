@@ -296,7 +296,6 @@ hipError_t launch_order_words(sl_grid* gr, const sl::FieldPtrs& fp, char* ws, hi
   if (quad) {
     const dim3 qb((unsigned)((gr->g.n[0] / 4 + 63) / 64), (unsigned)((gr->g.n[1] + 3) / 4),
                   (unsigned)gr->g.n[2]);
-    auto* f4 = reinterpret_cast<uint32_t*>(flags);
     auto* qa = reinterpret_cast<unsigned long long*>(wa);
     auto* qb2 = reinterpret_cast<unsigned long long*>(wb);
     const int nq = gr->g.n[0] / 4;
@@ -307,6 +306,7 @@ hipError_t launch_order_words(sl_grid* gr, const sl::FieldPtrs& fp, char* ws, hi
       e = launch(sl::flags_window_x_kernel<D, T>, fb, dim3(sl::kBlock), 0, s, e0, nullptr,
                  gr->g, fp, qa);
     } else {
+      auto* f4 = reinterpret_cast<uint32_t*>(flags);
       e = launch(sl::flags_quad_kernel<D, T>, qb, wt, 0, s, e0, nullptr, gr->g, fp, f4);
       if (e == hipSuccess)
         e = launch(sl::window_x_quad_kernel, qb, wt, 0, s, nullptr, nullptr, gr->g,

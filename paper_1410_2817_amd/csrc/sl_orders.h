@@ -78,33 +78,31 @@ __global__ __launch_bounds__(256) void window_or_kernel(GridArgs g,
 
 // The same passes four x-nodes per work-item, for rows whose length is a
 // multiple of 4 (and 16-byte aligned fields): flag bytes and window words
-// move as 32- and 64-bit words.  Grids: (ceil(n0/4/64), ceil(n1/4), n2) of
-// 64 x 4 (n2 = 1 in 2-D).
+// move as 32- and 64-bit words.
+
+// Flag bytes of the quad x = 4q .. 4q+3 of row (y, z): byte j, bit f set when
+// the criterion fires for field f at node x + j.
 template <int D, typename T>
-__global__ __launch_bounds__(256) void flags_quad_kernel(GridArgs g, FieldPtrs fp,
-                                                         uint32_t* __restrict__ flags4) {
+__device__ __forceinline__ unsigned quad_flag_bits(const GridArgs& g, const FieldPtrs& fp, int q,
+                                                   int y, int z) {
   using V4 = T __attribute__((ext_vector_type(4)));
-  const int nq = g.n[0] / 4;
-  const int q = blockIdx.x * 64 + threadIdx.x, y = blockIdx.y * 4 + threadIdx.y;
-  const int z = blockIdx.z;
-  if (q >= nq || y >= g.n[1]) return;
   const int n0 = g.n[0], n1 = g.n[1], n2 = g.n[2];
   const int x = 4 * q;
   const int ym = y == 0 ? n1 - 1 : y - 1, yp = y + 1 == n1 ? 0 : y + 1;
   const int zm = z == 0 ? n2 - 1 : z - 1, zp = z + 1 == n2 ? 0 : z + 1;
-  const int row = n0 * (y + n1 * z);
+  const int rw = n0 * (y + n1 * z);
   const int rym = n0 * (ym + n1 * z), ryp = n0 * (yp + n1 * z);
   const int rzm = n0 * (y + n1 * zm), rzp = n0 * (y + n1 * zp);
   const int xm = x == 0 ? n0 - 1 : x - 1, xp = x + 4 == n0 ? 0 : x + 4;
   unsigned bits = 0;
   for (int f = 0; f < g.nfields; ++f) {
     const T* __restrict__ h = static_cast<const T*>(fp.in[f]);
-    const V4 c = *reinterpret_cast<const V4*>(h + row + x);
+    const V4 c = *reinterpret_cast<const V4*>(h + rw + x);
     const V4 vym = *reinterpret_cast<const V4*>(h + rym + x);
     const V4 vyp = *reinterpret_cast<const V4*>(h + ryp + x);
     const V4 vzm = D == 3 ? *reinterpret_cast<const V4*>(h + rzm + x) : c;
     const V4 vzp = D == 3 ? *reinterpret_cast<const V4*>(h + rzp + x) : c;
-    const double l = (double)h[row + xm], r = (double)h[row + xp];
+    const double l = (double)h[rw + xm], r = (double)h[rw + xp];
     const double cc[4] = {(double)c.x, (double)c.y, (double)c.z, (double)c.w};
     const double am[4] = {(double)vym.x, (double)vym.y, (double)vym.z, (double)vym.w};
     const double ap[4] = {(double)vyp.x, (double)vyp.y, (double)vyp.z, (double)vyp.w};
@@ -119,27 +117,21 @@ __global__ __launch_bounds__(256) void flags_quad_kernel(GridArgs g, FieldPtrs f
       bits |= (fl ? 1u : 0u) << (8 * j + f);
     }
   }
-  flags4[(row + x) / 4] = bits;
+  return bits;
 }
 
-__global__ __launch_bounds__(256) void window_x_quad_kernel(GridArgs g,
-                                                            const uint32_t* __restrict__ flags4,
-                                                            unsigned long long* __restrict__ out4) {
-  const int nq = g.n[0] / 4;
-  const int q = blockIdx.x * 64 + threadIdx.x, y = blockIdx.y * 4 + threadIdx.y;
-  const int z = blockIdx.z;
-  if (q >= nq || y >= g.n[1]) return;
-  const int rowq = nq * (y + g.n[1] * z);
-  // Bytes of the nodes x-4 .. x+7 (x = 4q); nq >= 2 since n0 >= 6.
-  const unsigned w[3] = {flags4[rowq + (q == 0 ? nq - 1 : q - 1)], flags4[rowq + q],
-                         flags4[rowq + (q + 1 == nq ? 0 : q + 1)]};
+// The x window words of a quad from the flag bytes of it and its two
+// neighbours (nodes x-4 .. x+7): for node x + j the quintic window ORs bytes
+// j+2 .. j+7 (nodes x+j-2 .. x+j+3), the cubic one bytes j+3 .. j+6.
+__device__ __forceinline__ unsigned long long quad_window_x(unsigned left, unsigned mid,
+                                                            unsigned right) {
+  const unsigned w[3] = {left, mid, right};
   unsigned b[12];
 #pragma unroll
   for (int k = 0; k < 12; ++k) b[k] = (w[k / 4] >> (8 * (k % 4))) & 0xffu;
   unsigned long long o = 0;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    // Node x + j: quintic window b[j+2 .. j+7], cubic window b[j+3 .. j+6].
     unsigned lo = 0, hi = 0;
 #pragma unroll
     for (int k = 2; k <= 7; ++k) lo |= b[j + k];
@@ -147,7 +139,7 @@ __global__ __launch_bounds__(256) void window_x_quad_kernel(GridArgs g,
     for (int k = 3; k <= 6; ++k) hi |= b[j + k];
     o |= (unsigned long long)(lo | (hi << 8)) << (16 * j);
   }
-  out4[rowq + q] = o;
+  return o;
 }
 
 template <int AXIS>
@@ -174,74 +166,53 @@ __global__ __launch_bounds__(256) void window_yz_quad_kernel(
   out4[lin] = lo | hi;
 }
 
-// Flags and x window in one pass, for rows of at most kBlock quads: a
-// workgroup holds R = kBlock / nq whole rows (nq = n0 / 4 quads per row), so
-// the x neighbours of every quad, the periodic ones included, are in its LDS
-// and the flag bytes never reach memory.  Work-item t takes quad t % nq of
-// row t / nq; the flags are the ones flags_quad_kernel computes, the window
-// the one window_x_quad_kernel forms.  Grid: (ceil(n1 / R), n2) of kBlock.
+// Flags and x window in one pass (the flag bytes never reach memory), for
+// rows of at most kBlock quads: a workgroup holds R = kBlock / nq whole rows
+// (nq = n0 / 4 quads per row), so the x neighbours of every quad, the
+// periodic ones included, are in its LDS.  Work-item t takes quad t % nq of
+// row t / nq.  Grid: (ceil(n1 / R), n2) of kBlock.
 template <int D, typename T>
 __global__ __launch_bounds__(kBlock) void flags_window_x_kernel(GridArgs g, FieldPtrs fp,
                                                                 unsigned long long* __restrict__ out4) {
-  using V4 = T __attribute__((ext_vector_type(4)));
   __shared__ uint32_t s_f[kBlock];
   const int nq = g.n[0] / 4, R = kBlock / nq;
   const int t = (int)threadIdx.x, q = t % nq, row = t / nq;
   const int y = blockIdx.x * R + row, z = blockIdx.y;
   const bool ok = row < R && y < g.n[1];
-  if (ok) {
-    const int n0 = g.n[0], n1 = g.n[1], n2 = g.n[2];
-    const int x = 4 * q;
-    const int ym = y == 0 ? n1 - 1 : y - 1, yp = y + 1 == n1 ? 0 : y + 1;
-    const int zm = z == 0 ? n2 - 1 : z - 1, zp = z + 1 == n2 ? 0 : z + 1;
-    const int rw = n0 * (y + n1 * z);
-    const int rym = n0 * (ym + n1 * z), ryp = n0 * (yp + n1 * z);
-    const int rzm = n0 * (y + n1 * zm), rzp = n0 * (y + n1 * zp);
-    const int xm = x == 0 ? n0 - 1 : x - 1, xp = x + 4 == n0 ? 0 : x + 4;
-    unsigned bits = 0;
-    for (int f = 0; f < g.nfields; ++f) {
-      const T* __restrict__ h = static_cast<const T*>(fp.in[f]);
-      const V4 c = *reinterpret_cast<const V4*>(h + rw + x);
-      const V4 vym = *reinterpret_cast<const V4*>(h + rym + x);
-      const V4 vyp = *reinterpret_cast<const V4*>(h + ryp + x);
-      const V4 vzm = D == 3 ? *reinterpret_cast<const V4*>(h + rzm + x) : c;
-      const V4 vzp = D == 3 ? *reinterpret_cast<const V4*>(h + rzp + x) : c;
-      const double l = (double)h[rw + xm], r = (double)h[rw + xp];
-      const double cc[4] = {(double)c.x, (double)c.y, (double)c.z, (double)c.w};
-      const double am[4] = {(double)vym.x, (double)vym.y, (double)vym.z, (double)vym.w};
-      const double ap[4] = {(double)vyp.x, (double)vyp.y, (double)vyp.z, (double)vyp.w};
-      const double bm[4] = {(double)vzm.x, (double)vzm.y, (double)vzm.z, (double)vzm.w};
-      const double bp[4] = {(double)vzp.x, (double)vzp.y, (double)vzp.z, (double)vzp.w};
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const double hm = j == 0 ? l : cc[j - 1], hp = j == 3 ? r : cc[j + 1];
-        const bool fl = jump_flag(hm, cc[j], hp, g.theta) ||
-                        jump_flag(am[j], cc[j], ap[j], g.theta) ||
-                        (D == 3 && jump_flag(bm[j], cc[j], bp[j], g.theta));
-        bits |= (fl ? 1u : 0u) << (8 * j + f);
-      }
-    }
-    s_f[t] = bits;
-  }
+  if (ok) s_f[t] = quad_flag_bits<D, T>(g, fp, q, y, z);
   __syncthreads();
   if (!ok) return;
   const int base = row * nq;
-  const unsigned w[3] = {s_f[base + (q == 0 ? nq - 1 : q - 1)], s_f[t],
-                         s_f[base + (q + 1 == nq ? 0 : q + 1)]};
-  unsigned b[12];
-#pragma unroll
-  for (int k = 0; k < 12; ++k) b[k] = (w[k / 4] >> (8 * (k % 4))) & 0xffu;
-  unsigned long long o = 0;
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    unsigned lo = 0, hi = 0;
-#pragma unroll
-    for (int k = 2; k <= 7; ++k) lo |= b[j + k];
-#pragma unroll
-    for (int k = 3; k <= 6; ++k) hi |= b[j + k];
-    o |= (unsigned long long)(lo | (hi << 8)) << (16 * j);
-  }
-  out4[nq * (y + g.n[1] * z) + q] = o;
+  out4[nq * (y + g.n[1] * z) + q] =
+      quad_window_x(s_f[base + (q == 0 ? nq - 1 : q - 1)], s_f[t],
+                    s_f[base + (q + 1 == nq ? 0 : q + 1)]);
+}
+
+// Longer rows: the flag bytes of each quad (grid (ceil(nq/64), ceil(n1/4),
+// n2) of 64 x 4), then the x window of each quad from its own and its two
+// neighbours' bytes.  (Overlapping segments of 256 quads with the flags in
+// LDS, as above, measured slower at 4096^2: 0.645 -> 0.683 ms per step.)
+template <int D, typename T>
+__global__ __launch_bounds__(256) void flags_quad_kernel(GridArgs g, FieldPtrs fp,
+                                                         uint32_t* __restrict__ flags4) {
+  const int nq = g.n[0] / 4;
+  const int q = blockIdx.x * 64 + threadIdx.x, y = blockIdx.y * 4 + threadIdx.y;
+  const int z = blockIdx.z;
+  if (q >= nq || y >= g.n[1]) return;
+  flags4[nq * (y + g.n[1] * z) + q] = quad_flag_bits<D, T>(g, fp, q, y, z);
+}
+
+__global__ __launch_bounds__(256) void window_x_quad_kernel(GridArgs g,
+                                                            const uint32_t* __restrict__ flags4,
+                                                            unsigned long long* __restrict__ out4) {
+  const int nq = g.n[0] / 4;
+  const int q = blockIdx.x * 64 + threadIdx.x, y = blockIdx.y * 4 + threadIdx.y;
+  const int z = blockIdx.z;
+  if (q >= nq || y >= g.n[1]) return;
+  const int rowq = nq * (y + g.n[1] * z);
+  // nq >= 2 since n0 >= 6.
+  out4[rowq + q] = quad_window_x(flags4[rowq + (q == 0 ? nq - 1 : q - 1)], flags4[rowq + q],
+                                 flags4[rowq + (q + 1 == nq ? 0 : q + 1)]);
 }
 
 // The y and z window passes of a 3-D grid in one: the low bytes OR over the
