@@ -104,16 +104,26 @@ VALU_KERNELS = {"swirl_f32": ["recon2d_tiled_kernel<float, 3>"],
                 "kelvin_f64": ["recon2d_tiled_kernel<double, 3>", "sw_stage_kernel<double, 2>"]}
 
 
+def _code_only(text: str) -> str:
+    """C/C++ source without its comments and trailing blanks: a record taken
+    for the kernels stays valid when only their comments change."""
+    import re
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    return "\n".join(line.rstrip() for line in text.splitlines() if line.strip())
+
+
 def all_sources_hash() -> str:
-    """Hash of every HIP source and the C header."""
+    """Hash of the code (comments left out) of every HIP source and the C
+    header."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1410_2817_amd", "csrc")
     names = sorted(n for n in os.listdir(csrc) if n.endswith((".h", ".hip")))
     for rel in ["include/sl.h"] + ["paper_1410_2817_amd/csrc/" + n for n in names]:
         h.update(rel.encode())
-        with open(os.path.join(ROOT, rel), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, rel), encoding="utf-8") as fh:
+            h.update(_code_only(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

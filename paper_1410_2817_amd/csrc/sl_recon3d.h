@@ -183,10 +183,6 @@ __device__ __forceinline__ int cell_solve3d(const GridArgs& g, const double* __r
   return el.solve(g, xi);
 }
 
-// `ord` holds the window words (null when the limiter is off); `buf_ok` is
-// non-zero when one field's bytes fit the 31-bit buffer offsets, `dbuf_ok`
-// when one displacement component's do; `nt` / `v`: the next step's
-// trajectories of the tile's nodes (NextTraj).
 // The next step's trajectory of lattice node tgt (a fresh lattice): family VK,
 // or the grid's family at run time when VK < 0.
 template <int VK>
@@ -198,6 +194,10 @@ __device__ __forceinline__ void next_traj3d(const GridArgs& g, const VelArgs& v,
     traj_node<3, VK>(g, v, nt.disp, nt.st, nt.dt, 0, nt.integrator, tgt, nt.trig);
 }
 
+// `ord` holds the window words (null when the limiter is off); `buf_ok` is
+// non-zero when one field's bytes fit the 31-bit buffer offsets, `dbuf_ok`
+// when one displacement component's do; `nt` / `v`: the next step's
+// trajectories of the tile's nodes (NextTraj).
 // VK: the velocity family of the fused next-step trajectories when the kernel
 // is specialised for one (the deformational flow with one field, whose
 // registers then need not cover every family's), or -1 for the run-time
