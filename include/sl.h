@@ -150,7 +150,10 @@ typedef struct sl_velocity {
 
 typedef struct sl_grid_desc {
   int dim;                /* 2 or 3 */
-  int64_t n[3];           /* nodes per axis, x first; n[a] >= 2*order_max+2 */
+  int64_t n[3];           /* nodes per axis, x first: 6 <= n[a] <= 2^24 (the quintic
+                           * stencil fits the periodic grid once), n[1] <= 262140 and
+                           * n[2] <= 65535 (launch-grid limits), fewer than 2^30
+                           * nodes in all (SL_EINVAL otherwise) */
   double length[3];       /* physical extent per axis, > 0 */
   int nfields;            /* 1..SL_MAX_FIELDS */
   int value_prec;         /* SL_FP64 or SL_FP32 */

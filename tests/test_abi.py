@@ -74,6 +74,10 @@ def test_create_and_workspace_size(lib):
     dict(vel_kind=4),  # Fourier without modes
     dict(newton_max_iter=0), dict(newton_tol=0.0), dict(scan_radius=99),
     dict(length=(1.0, 0.0)), dict(vel_params=[float("nan")]), dict(limiter_pass=3),
+    # size limits: 2^30 nodes in all, n_x above 2^24, n_y above 4 x 65535,
+    # n_z above 65535 (array order: x last)
+    dict(shape=(1024, 1024, 1024)), dict(shape=(8, (1 << 24) + 1)),
+    dict(shape=(4 * 65535 + 1, 8)), dict(shape=(65536, 8, 8)),
 ])
 def test_create_rejects_bad_descriptors(lib, bad):
     kw = dict(bad)
@@ -90,6 +94,21 @@ def test_create_rejects_bad_descriptors(lib, bad):
         d, keep = _desc(**kw)
     rc, h = _create(d)
     assert rc == B.SL_EINVAL and not h.value
+
+
+@pytest.mark.parametrize("shape", [(1023, 1024, 1024), (65535, 8, 8), (4 * 65535, 8),
+                                   (8, 1 << 24)])
+def test_create_accepts_the_largest_grids(lib, shape):
+    # The largest grid (2^30 - 2^20 nodes) and each axis at its limit: the
+    # workspace holds at least the two FP64 displacement sets.
+    d, _ = _desc(shape=shape, limiter=True)
+    rc, h = _create(d)
+    assert rc == B.SL_OK and h.value
+    n = 1
+    for s in shape:
+        n *= s
+    assert lib.sl_workspace_bytes(h) >= 2 * 8 * len(shape) * n
+    assert lib.sl_destroy_grid(h) == B.SL_OK
 
 
 def test_null_arguments(lib):

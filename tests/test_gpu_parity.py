@@ -289,6 +289,72 @@ def test_jump_flags_at_ties_fp32(B, torch, orc, theta):
         assert np.abs(a_ - b_).max() <= 1e-5 * np.abs(b_).max()
 
 
+def _edge_nodes(field, z_lo, z_hi, planes):
+    """Linear indices of nodes where a 0/1 field changes along x, taken from a
+    few planes (3-D, array axis 0 in [z_lo, z_hi)) or rows (2-D) through the
+    body, without a pass over the whole grid."""
+    nx = field.shape[-1]
+    out = []
+    for z in np.linspace(z_lo, z_hi - 1, planes).astype(np.int64):
+        sl = np.asarray(field[z])
+        idx = np.nonzero(np.diff(sl, axis=-1, append=sl[..., :1]) != 0)
+        lin = idx[-1] + (idx[0] * nx if sl.ndim == 2 else 0)
+        out.append(lin + z * sl.size)
+    return np.concatenate(out)
+
+
+def _large_workload(which):
+    """Grids above 2^28 nodes, where one field's or one displacement
+    component's bytes exceed the 31-bit buffer offsets and the kernels take
+    their plain-pointer paths: 650^3 FP64 (ragged tiles in every axis),
+    1024 x 1024 x 1023 with FP32 values (the largest grid a descriptor
+    accepts, 2^30 - 2^20 nodes) and a 16400^2 swirl in FP64."""
+    if which == "deform650_f64":
+        return W.deform3d_slotted_sphere(650), 0.7
+    if which == "deform_max_f32":
+        shape = (1023, 1024, 1024)
+        fs = [W.slotted_disk(shape, (0.35, 0.35, 0.35), 0.15, 0.05, 0.25).astype(np.float32)]
+        return W.Workload("deform3d_max_f32", shape, (1.0, 1.0, 1.0), fs,
+                          W.Velocity(W.VEL_DEFORM3D, [3.0, 1.0]), dt=1.5 / 1024, nsteps=1,
+                          order_max=2, limiter=True, value_prec="f32"), 0.7
+    shape = (16400, 16400)
+    fs = [W.slotted_disk(shape, (0.5, 0.75), 0.15, 0.05, 0.25)]
+    return W.Workload("swirl2d_16400_f64", shape, (1.0, 1.0), fs,
+                      W.Velocity(W.VEL_SWIRL2D, [5.0, 1.0]), dt=4.0 / 16400, nsteps=1,
+                      order_max=2, limiter=True, value_prec="f64"), 1.1
+
+
+@pytest.mark.parametrize("which", ["deform650_f64", "deform_max_f32", "swirl16400_f64"])
+def test_grids_beyond_buffer_offsets_sampled(B, torch, orc, which):
+    """One step on grids whose fields or displacement components exceed 2^31
+    bytes (the plain-pointer paths of the element solve and the gathers, and
+    32-bit node indices up to the largest grid), checked at sampled nodes
+    (random ones and nodes on the body's edge) that the oracle evaluates one
+    by one; the sample is gathered on the device."""
+    wl, t0 = _large_workload(which)
+    say("beyond buffer offsets", which, wl.shape)
+    vals = stored_values(wl)
+    g = B.Grid.from_workload(wl)
+    out = g.advance(g.new_fields(vals), t0, wl.dt, 1)
+    rc, st = g.sync()
+    assert rc == 0 and st["search_fail"] == 0 and st["newton_fail"] == 0
+    assert st["nodes"] == wl.nodes
+    gen = np.random.Generator(np.random.PCG64(13))
+    nz = wl.shape[0]
+    lo, hi = (int(0.22 * nz), int(0.48 * nz)) if wl.dim == 3 else (int(0.62 * nz), int(0.88 * nz))
+    edge = _edge_nodes(wl.fields[0], lo, hi, 12 if wl.dim == 3 else 64)
+    sample = np.unique(np.concatenate([gen.integers(0, wl.nodes, 2000),
+                                       gen.choice(edge, 1000)]))
+    idx = torch.as_tensor(sample, device=out[0].device)
+    got = out[0].reshape(-1)[idx].double().cpu().numpy()
+    del out
+    rc2, ref, _ = orc.step_sampled(oracle_problem(orc, wl), t0, wl.dt, vals, sample)
+    assert rc2 == 0
+    err = np.abs(got - ref[:, 0]).max()
+    say("  max abs err", err, "at", sample.size, "nodes")
+    assert err <= (1e-5 if wl.value_prec == "f32" else 1e-12) * max(1.0, np.abs(ref[:, 0]).max())
+
+
 @pytest.mark.parametrize("name,wl", [
     ("swirl96_f32", W.swirl_three_fields(96, value_prec="f32")),
     ("fourier3d_28_f32", W.fourier3d_three_fields(28, value_prec="f32")),
