@@ -221,10 +221,13 @@ __global__ __launch_bounds__(256) void window_x_quad_kernel(GridArgs g,
 // composed).  A 64 x 4 workgroup owns 64 quads x 4 rows and marches through
 // kZChunk planes: each plane's rows y0-2..y0+6 go through LDS (two buffers,
 // one barrier per plane), each work-item forms its y window and keeps the
-// last six in registers for the z window.  Every input word is read from
-// memory once per chunk (plus the 5-plane halo), every output written once.
+// last six in registers for the z window.  The rows are loaded kZAhead planes
+// ahead into registers, so that loads stay in flight across the planes.
+// Every input word is read from memory once per chunk (plus the 5-plane
+// halo), every output written once.
 // Grid: (ceil(nq / 64), ceil(n1 / 4), ceil(n2 / kZChunk)) of 64 x 4.
 constexpr int kZChunk = 32;
+constexpr int kZAhead = 4;
 __global__ __launch_bounds__(256) void window_yz3_quad_kernel(
     GridArgs g, const unsigned long long* __restrict__ in4, unsigned long long* __restrict__ out4) {
   constexpr unsigned long long LO = 0x00ff00ff00ff00ffull, HI = 0xff00ff00ff00ff00ull;
@@ -234,38 +237,61 @@ __global__ __launch_bounds__(256) void window_yz3_quad_kernel(
   const int q = blockIdx.x * 64 + tq;
   const int y0 = blockIdx.y * 4, y = y0 + ty;
   const int z0 = blockIdx.z * kZChunk, z1 = min(z0 + kZChunk, n2);
+  const int K = z1 - z0 + 5;  // planes z0-2 .. z1+2
   const bool qok = q < nq;
+  // Rows and planes wrap periodically (n1, n2 >= 6).  Work-item row ty
+  // stages the LDS rows ty, ty + 4 and (ty == 0) 8.
+  int roff[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    int yy = y0 - 2 + ty + 4 * i;
+    yy = yy < 0 ? yy + n1 : (yy >= n1 ? yy - n1 : yy);
+    roff[i] = q + nq * yy;
+  }
+  const int nrow = ty == 0 ? 3 : 2;
+  int zl = z0 - 2 < 0 ? z0 - 2 + n2 : z0 - 2;  // plane of the next load
+  unsigned long long pre[kZAhead][3];
+  const auto load_plane = [&](unsigned long long* r) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+      r[i] = qok && i < nrow ? in4[roff[i] + nq * n1 * zl] : 0ull;
+    zl = zl + 1 == n2 ? 0 : zl + 1;
+  };
+#pragma unroll
+  for (int j = 0; j < kZAhead; ++j)
+    if (j < K) load_plane(pre[j]);
   unsigned long long lo[6] = {0, 0, 0, 0, 0, 0}, hi[6] = {0, 0, 0, 0, 0, 0};
-  // Rows and planes wrap periodically (n1, n2 >= 6).
-  int zw = z0 - 2 < 0 ? z0 - 2 + n2 : z0 - 2;
-  for (int k = 0; k < z1 - z0 + 5; ++k) {
-    const int buf = k & 1;
-    for (int rr = ty; rr < 9; rr += 4) {
-      int yy = y0 - 2 + rr;
-      yy = yy < 0 ? yy + n1 : (yy >= n1 ? yy - n1 : yy);
-      s_rows[buf][rr][tq] = qok ? in4[q + nq * (yy + n1 * zw)] : 0ull;
-    }
-    __syncthreads();
-    unsigned long long l = 0, h = 0;
+  for (int k0 = 0; k0 < K; k0 += kZAhead) {
 #pragma unroll
-    for (int d = 0; d < 6; ++d) {
-      const unsigned long long v = s_rows[buf][ty + d][tq];
-      l |= v & LO;
-      if (d >= 1 && d <= 4) h |= v & HI;
-    }
+    for (int j = 0; j < kZAhead; ++j) {
+      const int k = k0 + j;
+      if (k >= K) break;  // uniform over the workgroup
+      const int buf = k & 1;
 #pragma unroll
-    for (int j = 0; j < 5; ++j) {
-      lo[j] = lo[j + 1];
-      hi[j] = hi[j + 1];
+      for (int i = 0; i < 3; ++i)
+        if (i < nrow) s_rows[buf][ty + 4 * i][tq] = pre[j][i];
+      __syncthreads();
+      if (k + kZAhead < K) load_plane(pre[j]);
+      unsigned long long l = 0, h = 0;
+#pragma unroll
+      for (int d = 0; d < 6; ++d) {
+        const unsigned long long v = s_rows[buf][ty + d][tq];
+        l |= v & LO;
+        if (d >= 1 && d <= 4) h |= v & HI;
+      }
+#pragma unroll
+      for (int m = 0; m < 5; ++m) {
+        lo[m] = lo[m + 1];
+        hi[m] = hi[m + 1];
+      }
+      lo[5] = l;
+      hi[5] = h;
+      if (k >= 5 && qok && y < n1) {
+        const int zo = z0 + k - 5;
+        out4[q + nq * (y + n1 * zo)] =
+            (lo[0] | lo[1] | lo[2] | lo[3] | lo[4] | lo[5]) | (hi[1] | hi[2] | hi[3] | hi[4]);
+      }
     }
-    lo[5] = l;
-    hi[5] = h;
-    if (k >= 5 && qok && y < n1) {
-      const int zo = z0 + k - 5;
-      out4[q + nq * (y + n1 * zo)] =
-          (lo[0] | lo[1] | lo[2] | lo[3] | lo[4] | lo[5]) | (hi[1] | hi[2] | hi[3] | hi[4]);
-    }
-    zw = zw + 1 == n2 ? 0 : zw + 1;
   }
 }
 

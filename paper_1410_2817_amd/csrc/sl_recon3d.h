@@ -69,26 +69,45 @@ __device__ __forceinline__ double buffer_value<double>(__amdgpu_buffer_rsrc_t rs
 // r - 2 + (kx, ky, kz).  x innermost, then y, then z, on every path.  The z
 // loop stays rolled: unrolled (on the LDS path) the hoisted loads spilled
 // registers, 7.97 -> 9.77 ms per deformational 512^3 FP64 launch and 6.87 ->
-// 7.49 ms in FP32.
-template <typename T, class Val>
+// 7.49 ms in FP32.  Each plane reads its rows in pairs, the twelve values
+// before their products, so that a wave keeps six LDS reads in flight: with
+// one row sum fed straight from the reads the schedule waited on every read
+// (deformational 512^3 FP64 step 7.60 -> 7.56 ms, Fourier 256^3 1.91 ->
+// 1.75 ms).  FENCE keeps the compiler from moving a pair's reads into the
+// products (one-field kernels: FP64 7.56 -> 7.47 ms, FP32 values 6.28 -> 6.23
+// ms; three Fourier fields lose 2 %, so they go without).  The z weights
+// shift down one slot per plane (a rolled loop cannot index a register array
+// without scratch memory or a chain of selects).  Same operation order as the
+// plain triple loop, so the value is bitwise that of the other paths.
+template <bool FENCE, typename T, class Val>
 __device__ __forceinline__ T zsum3d(const T* wx, const T* wy, const T* wz, const Val& val) {
   T acc = T(0);
+  T w0 = wz[0], w1 = wz[1], w2 = wz[2], w3 = wz[3], w4 = wz[4], w5 = wz[5];
 #pragma unroll 1
   for (int kz = 0; kz < 6; ++kz) {
     T pl = T(0);
 #pragma unroll
-    for (int ky = 0; ky < 6; ++ky) {
-      T s = T(0);
+    for (int ky = 0; ky < 6; ky += 2) {
+      T v[2][6];
 #pragma unroll
-      for (int kx = 0; kx < 6; ++kx) s = fma(val(kx, ky, kz), wx[kx], s);
-      pl = fma(s, wy[ky], pl);
+      for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int kx = 0; kx < 6; ++kx) v[r][kx] = val(kx, ky + r, kz);
+      if constexpr (FENCE) __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        T s = T(0);
+#pragma unroll
+        for (int kx = 0; kx < 6; ++kx) s = fma(v[r][kx], wx[kx], s);
+        pl = fma(s, wy[ky + r], pl);
+      }
     }
-    // Rolled loop: pick wz[kz] by selects (a dynamic index into a register
-    // array would go through scratch memory).
-    T wk = wz[5];
-#pragma unroll
-    for (int q = 4; q >= 0; --q) wk = kz == q ? wz[q] : wk;
-    acc = fma(pl, wk, acc);
+    acc = fma(pl, w0, acc);
+    w0 = w1;
+    w1 = w2;
+    w2 = w3;
+    w3 = w4;
+    w4 = w5;
   }
   return acc;
 }
@@ -369,7 +388,7 @@ __global__ __launch_bounds__(kTileThreads, (Box3D<T, NF>::WAVES)) void recon3d_k
       auto field_value = [&](int f, const T* wx, const T* wy, const T* wz, auto linear_c) {
         const auto sum = [&](const auto& at) {
           if constexpr (decltype(linear_c)::value) return zsum3d_linear<T>(wx, wy, wz, at);
-          else return zsum3d<T>(wx, wy, wz, at);
+          else return zsum3d<NF == 1, T>(wx, wy, wz, at);
         };
         T v;
         if (inbox) {
