@@ -287,7 +287,29 @@ __global__ __launch_bounds__(kTileThreads, (Box3D<T, NF>::WAVES)) void recon3d_k
     const int bx = (int)threadIdx.x % X::BX, by = (int)threadIdx.x / X::BX;
     const int gxy = wrap_near(ox[0] + bx, g.n[0]) + sy * wrap_near(ox[1] + by, g.n[1]);
     int gz = wrap_near(ox[2], g.n[2]);
-    if constexpr (OVERLAP) {
+    if constexpr (OVERLAP && VK >= 0) {
+      // The trajectory's own loads (its evaluator's sin/cos table) go out
+      // before the box loads: loads complete in issue order, so issued after
+      // them they made the trajectory wait for the whole box.
+      const bool traj = nt.disp && !nt.carried && act;
+      NodeVelocity<VK, 3> vel{};
+      double td[3], tx[3];
+      if (traj) traj_start<3>(g, v, vel, nt.disp, nt.dt, 0, tgt, nt.trig, td, tx);
+      T sv[X::BZ][nf];
+#pragma unroll
+      for (int bz = 0; bz < X::BZ; ++bz) {
+        const int gl = gxy + sz * gz;
+#pragma unroll
+        for (int f = 0; f < nf; ++f) sv[bz][f] = static_cast<const T*>(fp.in[f])[gl];
+        gz = gz + 1 == g.n[2] ? 0 : gz + 1;
+      }
+      if (traj) traj_finish<3>(g, v, vel, nt.disp, nt.st, nt.dt, nt.integrator, tgt, td, tx);
+#pragma unroll
+      for (int bz = 0; bz < X::BZ; ++bz)
+#pragma unroll
+        for (int f = 0; f < nf; ++f)
+          lval[f * X::NB + bx + X::PX * by + X::PX * X::BY * bz] = sv[bz][f];
+    } else if constexpr (OVERLAP) {
       T sv[X::BZ][nf];
 #pragma unroll
       for (int bz = 0; bz < X::BZ; ++bz) {

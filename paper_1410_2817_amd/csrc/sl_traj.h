@@ -48,15 +48,17 @@ constexpr int kTrajBX = 64, kTrajBY = 4;
 // eval(v, x0, delta, tf, u) at x0 + delta).
 // `trig` (fresh lattice only): the per-axis sin/cos table of trig_table_kernel
 // for the velocity families whose evaluator starts from sin/cos at x0.
+// traj_start reads the start position and initialises `vel`; traj_finish
+// integrates from there and writes the displacement.  Split so that a caller
+// can issue the evaluator's table loads first, then loads of its own, and
+// integrate while those are in flight.
 template <int D, class Vel>
-__device__ __forceinline__ void traj_node_with(const GridArgs& g, const VelArgs& v, Vel vel,
-                                               double* __restrict__ disp,
-                                               const StageTimes& st, double dt,
-                                               int accumulate, int integrator,
-                                               const int* idx,
-                                               const double* __restrict__ trig = nullptr) {
+__device__ __forceinline__ void traj_start(const GridArgs& g, const VelArgs& v, Vel& vel,
+                                           const double* __restrict__ disp, double dt,
+                                           int accumulate, const int* idx,
+                                           const double* __restrict__ trig, double* d,
+                                           double* x) {
   const int lin = flatten<D>(g, idx);
-  double d[D], x[D];
 #pragma unroll
   for (int a = 0; a < D; ++a) {
     d[a] = accumulate ? disp[(size_t)a * g.ntot + lin] : 0.0;
@@ -67,6 +69,14 @@ __device__ __forceinline__ void traj_node_with(const GridArgs& g, const VelArgs&
     vel.init_table(trig, g, idx, small);
   else
     vel.init(v, x, small);
+}
+
+template <int D, class Vel>
+__device__ __forceinline__ void traj_finish(const GridArgs& g, const VelArgs& v, const Vel& vel,
+                                            double* __restrict__ disp, const StageTimes& st,
+                                            double dt, int integrator, const int* idx, double* d,
+                                            const double* x) {
+  const int lin = flatten<D>(g, idx);
   if (integrator == SL_RK4) {
     double k1[D], k2[D], k3[D], k4[D], o[D];
     vel.eval(v, x, nullptr, st.tf[0], k1);
@@ -108,6 +118,18 @@ __device__ __forceinline__ void traj_node_with(const GridArgs& g, const VelArgs&
   }
 #pragma unroll
   for (int a = 0; a < D; ++a) disp[(size_t)a * g.ntot + lin] = d[a];
+}
+
+template <int D, class Vel>
+__device__ __forceinline__ void traj_node_with(const GridArgs& g, const VelArgs& v, Vel vel,
+                                               double* __restrict__ disp,
+                                               const StageTimes& st, double dt,
+                                               int accumulate, int integrator,
+                                               const int* idx,
+                                               const double* __restrict__ trig = nullptr) {
+  double d[D], x[D];
+  traj_start<D>(g, v, vel, disp, dt, accumulate, idx, trig, d, x);
+  traj_finish<D>(g, v, vel, disp, st, dt, integrator, idx, d, x);
 }
 
 template <int D, int VK>
