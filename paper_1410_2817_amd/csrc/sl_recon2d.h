@@ -201,6 +201,23 @@ __device__ __forceinline__ void recon2d_tile(const GridArgs& g, const FieldPtrs&
   const int lx = threadIdx.x % C::TX, ly0 = threadIdx.x / C::TX;
   constexpr int ROWS = kTileThreads / C::TX;  // rows covered per pass
 
+  // 1a. Own displacements (start guesses), loaded before the trajectories
+  // below so that their latency and that of the trajectories' table loads
+  // overlap (loads complete in issue order).
+  double d0[C::NPT][2];
+  bool act[C::NPT];
+#pragma unroll
+  for (int k = 0; k < C::NPT; ++k) {
+    const int x = tx0 + lx, y = ty0 + ly0 + ROWS * k;
+    act[k] = x < g.n[0] && y < g.n[1];
+    d0[k][0] = d0[k][1] = 0.0;
+    if (act[k]) {
+      const int lin = x + g.n[0] * y;
+      d0[k][0] = gdisp[lin];
+      d0[k][1] = gdisp[(size_t)g.ntot + lin];
+    }
+  }
+
   // The next step's trajectories of the tile's own nodes (NextTraj); they
   // touch nothing the reconstruction below reads.
   if constexpr (std::is_same<VelT, VelArgs>::value) {
@@ -220,21 +237,14 @@ __device__ __forceinline__ void recon2d_tile(const GridArgs& g, const FieldPtrs&
   if (threadIdx.x < ST_COUNT) s_cnt[threadIdx.x] = 0u;
   __syncthreads();
 
-  // 1. Own displacements (start guesses) and the bounding box of start cells.
-  double d0[C::NPT][2];
+  // 1b. Start cells and their bounding box.
   int rs[C::NPT][2];
-  bool act[C::NPT];
   int mn[2] = {INT_MAX, INT_MAX}, mx[2] = {INT_MIN, INT_MIN};
 #pragma unroll
   for (int k = 0; k < C::NPT; ++k) {
     const int x = tx0 + lx, y = ty0 + ly0 + ROWS * k;
-    act[k] = x < g.n[0] && y < g.n[1];
-    d0[k][0] = d0[k][1] = 0.0;
     rs[k][0] = rs[k][1] = 0;
     if (act[k]) {
-      const int lin = x + g.n[0] * y;
-      d0[k][0] = gdisp[lin];
-      d0[k][1] = gdisp[(size_t)g.ntot + lin];
       rs[k][0] = (int)floor((double)x - d0[k][0]);
       rs[k][1] = (int)floor((double)y - d0[k][1]);
       mn[0] = min(mn[0], rs[k][0]);
