@@ -96,6 +96,36 @@ __device__ __forceinline__ int element_solve_near(const GridArgs& g, const NearD
   return el.solve(g, xi);
 }
 
+// The eight displacement values of cell r's vertices (x then y per vertex),
+// and the solve from them: the same values and arithmetic as
+// element_solve_near, with the loads issued early by the caller.
+__device__ __forceinline__ void cell_disp_near(const GridArgs& g, const NearDisp2D& acc,
+                                               const int* r, double* vd) {
+  const int x0 = wrap_near(r[0], g.n[0]), y0 = wrap_near(r[1], g.n[1]);
+  const int x1 = x0 + 1 == g.n[0] ? 0 : x0 + 1, y1 = y0 + 1 == g.n[1] ? 0 : y0 + 1;
+  const int row0 = g.n[0] * y0, row1 = g.n[0] * y1;
+  const int lin[4] = {x0 + row0, x1 + row0, x0 + row1, x1 + row1};
+  const double* __restrict__ gy = acc.gdisp + (size_t)g.ntot;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    vd[2 * e] = acc.gdisp[lin[e]];
+    vd[2 * e + 1] = gy[lin[e]];
+  }
+}
+
+__device__ __forceinline__ int element_solve_pre(const GridArgs& g, const int* tgt, const int* r,
+                                                 const double* vd, double* xi) {
+  double V[4][2];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    V[e][0] = (double)(r[0] + (e & 1) - tgt[0]) + vd[2 * e];
+    V[e][1] = (double)(r[1] + (e >> 1) - tgt[1]) + vd[2 * e + 1];
+  }
+  Element<2> el;
+  el.set(V);
+  return el.solve(g, xi);
+}
+
 // Jump-flag bits (all fields) of the lattice node at wrapped (x, y), from
 // global memory.
 template <typename T, int NF>
@@ -253,6 +283,13 @@ __device__ __forceinline__ void recon2d_tile(const GridArgs& g, const FieldPtrs&
       mx[1] = max(mx[1], rs[k][1]);
     }
   }
+  // The start cells' vertex displacements: loaded here, their latency hides
+  // behind the staging and the flags.
+  const NearDisp2D acc{gdisp, g};
+  double vd[C::NPT][8];
+#pragma unroll
+  for (int k = 0; k < C::NPT; ++k)
+    if (act[k]) cell_disp_near(g, acc, rs[k], vd[k]);
   // Wave reductions first: LDS atomics from every lane would be serialised.
   mn[0] = wave_min(mn[0]);
   mn[1] = wave_min(mn[1]);
@@ -395,7 +432,6 @@ __device__ __forceinline__ void recon2d_tile(const GridArgs& g, const FieldPtrs&
     __syncthreads();
   }
 
-  const NearDisp2D acc{gdisp, g};
   int walked_any = 0, scanned_any = 0, sfail = 0, nfail = 0, c0 = 0, c1 = 0, c2 = 0, bad = 0;
 
 #pragma unroll 1
@@ -413,7 +449,7 @@ __device__ __forceinline__ void recon2d_tile(const GridArgs& g, const FieldPtrs&
     const auto solve = [&](const int* rr, double* x) {
       return element_solve_near(g, acc, tgt, rr, x);
     };
-    const int rc0 = solve(r, xi);
+    const int rc0 = element_solve_pre(g, tgt, r, vd[k], xi);
     if (rc0 != 1 || !in_cube<2>(g, xi)) {
       const double x0[2] = {xi[0], xi[1]};
       loc = locate_from<2>(g, solve, rc0, x0, r, xi, walked);
