@@ -283,13 +283,23 @@ __device__ __forceinline__ void recon2d_tile(const GridArgs& g, const FieldPtrs&
       mx[1] = max(mx[1], rs[k][1]);
     }
   }
-  // The start cells' vertex displacements: loaded here, their latency hides
-  // behind the staging and the flags.
+  // The start cells' vertex displacements and, where the order words are
+  // read, the start cell's word: loaded here, their latency hides behind the
+  // staging and the flags.  A node whose walk leaves the start cell re-reads
+  // its word below.
   const NearDisp2D acc{gdisp, g};
   double vd[C::NPT][8];
+  unsigned o_start[C::NPT];
+  const bool lim_words = ord != nullptr && g.limiter && g.order_max > 0;
 #pragma unroll
-  for (int k = 0; k < C::NPT; ++k)
-    if (act[k]) cell_disp_near(g, acc, rs[k], vd[k]);
+  for (int k = 0; k < C::NPT; ++k) {
+    o_start[k] = 0u;
+    if (act[k]) {
+      cell_disp_near(g, acc, rs[k], vd[k]);
+      if (lim_words)
+        o_start[k] = ord[wrap_near(rs[k][0], g.n[0]) + g.n[0] * wrap_near(rs[k][1], g.n[1])];
+    }
+  }
   // Wave reductions first: LDS atomics from every lane would be serialised.
   mn[0] = wave_min(mn[0]);
   mn[1] = wave_min(mn[1]);
@@ -475,7 +485,10 @@ __device__ __forceinline__ void recon2d_tile(const GridArgs& g, const FieldPtrs&
     if (ord != nullptr) {
       if (!inbox) stencil_global<T, NF>(g, fp, r, false, ix, iy, or6, or4);
       if (lim) {
-        const unsigned o = ord[wrap_near(r[0], g.n[0]) + g.n[0] * wrap_near(r[1], g.n[1])];
+        const unsigned o =
+            r[0] == rs[k][0] && r[1] == rs[k][1]
+                ? o_start[k]
+                : ord[wrap_near(r[0], g.n[0]) + g.n[0] * wrap_near(r[1], g.n[1])];
         or6 = o & 0xffu;
         or4 = o >> 8;
       }
