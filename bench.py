@@ -98,7 +98,7 @@ VALU_JSON = os.path.join(PROFILES, "valu_counters.json")
 # Workload of each counter directory -> the kernels whose counts are kept.
 VALU_KERNELS = {"swirl_f32": ["recon2d_tiled_kernel<float, 3>"],
                 "swirl4096_f32": ["recon2d_tiled_kernel<float, 3>"],
-                "fourier3d_f32": ["recon3d_kernel<float, 3, -1>"],
+                "fourier3d_f32": ["recon3d_kernel<float, 3, 4>"],
                 "deform3d_f64": ["recon3d_kernel<double, 1, 3>"],
                 "deform3d_f32": ["recon3d_kernel<float, 1, 3>"],
                 "kelvin_f64": ["recon2d_tiled_kernel<double, 3>", "sw_stage_kernel<double, 2>"]}
@@ -282,7 +282,7 @@ def make_workload(W, workload, n, prec):
 
 VALU_KEYS = {("swirl", 1024, "f32"): "swirl_f32/recon2d_tiled_kernel<float, 3>",
              ("swirl", 4096, "f32"): "swirl4096_f32/recon2d_tiled_kernel<float, 3>",
-             ("fourier3d", 256, "f32"): "fourier3d_f32/recon3d_kernel<float, 3, -1>",
+             ("fourier3d", 256, "f32"): "fourier3d_f32/recon3d_kernel<float, 3, 4>",
              ("deform3d", 512, "f64"): "deform3d_f64/recon3d_kernel<double, 1, 3>",
              ("deform3d", 512, "f32"): "deform3d_f32/recon3d_kernel<float, 1, 3>",
              ("kelvin", 1024, "f64"): "kelvin_f64/recon2d_tiled_kernel<double, 3>"}
@@ -613,7 +613,7 @@ def other_configs():
                      "trajectories_avg_ms": prof["traj_ms"] / max(prof["traj_launches"], 1),
                      "order_words_avg_ms": prof["orders_ms"] / max(prof["orders_launches"], 1),
                      "hbm_achieved_gbs": ach, "hbm_frac": ach / HBM_PEAK_GBS,
-                     "valu_roof": valu_roof({"fourier3d_256_f32": "fourier3d_f32/recon3d_kernel<float, 3, -1>",
+                     "valu_roof": valu_roof({"fourier3d_256_f32": "fourier3d_f32/recon3d_kernel<float, 3, 4>",
                                              "deform3d_512_f32": "deform3d_f32/recon3d_kernel<float, 1, 3>"}
                                             .get(name, ""), rms),
                      "order_hist": st["order_hist"], "walked": st["walked"]}

@@ -389,8 +389,13 @@ hipError_t launch_recon(sl_grid* gr, const sl::FieldPtrs& fp, char* ws, const do
                   stats, tiles_x, tiles_y, ntiles, buf_ok, dbuf_ok, nt, gr->v);
     // The deformational flow with one field (the paper's 3-D test) has a
     // kernel of its own: 0.6 % (FP64) to 1 % (FP32 values) faster per step.
+    // So do Fourier flows with three fields, whose registers then cover that
+    // family's trajectories alone (no spills): 256^3 step 1.82 -> 1.80 ms.
     if (gr->g.nfields == 1 && gr->v.kind == SL_VEL_DEFORM3D)
       return launch(sl::recon3d_kernel<T, 1, SL_VEL_DEFORM3D>, grid, block, 0, s, e0, e1, gr->g,
+                    fp, disp, ord, stats, tiles_x, tiles_y, ntiles, buf_ok, dbuf_ok, nt, gr->v);
+    if (gr->g.nfields == 3 && gr->v.kind == SL_VEL_FOURIER)
+      return launch(sl::recon3d_kernel<T, 3, SL_VEL_FOURIER>, grid, block, 0, s, e0, e1, gr->g,
                     fp, disp, ord, stats, tiles_x, tiles_y, ntiles, buf_ok, dbuf_ok, nt, gr->v);
     switch (gr->g.nfields) {
       SL_RECON3D(1)
