@@ -38,7 +38,7 @@ PROFILES = os.path.join(ROOT, "profiles")
 # (rocprofv3 FETCH_SIZE / WRITE_SIZE): (workload, n, prec) -> (kernel, file).
 TRAFFIC = {
     ("deform3d", 512, "f64"): ("recon3d_kernel<double, 1, 3>", "recon3d_deform512_f64_traffic.json"),
-    ("swirl", 1024, "f32"): ("recon2d_tiled_kernel<float, 3>", "recon2d_swirl1024_traffic.json"),
+    ("swirl", 1024, "f32"): ("recon2d_tiled_kernel<float, 3, 2>", "recon2d_swirl1024_traffic.json"),
 }
 HEADLINE = ("deform3d", 512, "f64")
 
@@ -96,12 +96,12 @@ def record_traffic(key, fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, co
 VALU_SIMDS, VALU_CYCLES_PER_INST, CLOCK_HZ = 1024, 4, 2.4e9
 VALU_JSON = os.path.join(PROFILES, "valu_counters.json")
 # Workload of each counter directory -> the kernels whose counts are kept.
-VALU_KERNELS = {"swirl_f32": ["recon2d_tiled_kernel<float, 3>"],
-                "swirl4096_f32": ["recon2d_tiled_kernel<float, 3>"],
+VALU_KERNELS = {"swirl_f32": ["recon2d_tiled_kernel<float, 3, 2>"],
+                "swirl4096_f32": ["recon2d_tiled_kernel<float, 3, 2>"],
                 "fourier3d_f32": ["recon3d_kernel<float, 3, 4>"],
                 "deform3d_f64": ["recon3d_kernel<double, 1, 3>"],
                 "deform3d_f32": ["recon3d_kernel<float, 1, 3>"],
-                "kelvin_f64": ["recon2d_tiled_kernel<double, 3>", "sw_stage_kernel<double, 2>"]}
+                "kelvin_f64": ["recon2d_tiled_kernel<double, 3, -1>", "sw_stage_kernel<double, 2>"]}
 
 
 def _code_only(text: str) -> str:
@@ -280,12 +280,12 @@ def make_workload(W, workload, n, prec):
     return W.deform3d_slotted_sphere(n, value_prec=prec)
 
 
-VALU_KEYS = {("swirl", 1024, "f32"): "swirl_f32/recon2d_tiled_kernel<float, 3>",
-             ("swirl", 4096, "f32"): "swirl4096_f32/recon2d_tiled_kernel<float, 3>",
+VALU_KEYS = {("swirl", 1024, "f32"): "swirl_f32/recon2d_tiled_kernel<float, 3, 2>",
+             ("swirl", 4096, "f32"): "swirl4096_f32/recon2d_tiled_kernel<float, 3, 2>",
              ("fourier3d", 256, "f32"): "fourier3d_f32/recon3d_kernel<float, 3, 4>",
              ("deform3d", 512, "f64"): "deform3d_f64/recon3d_kernel<double, 1, 3>",
              ("deform3d", 512, "f32"): "deform3d_f32/recon3d_kernel<float, 1, 3>",
-             ("kelvin", 1024, "f64"): "kelvin_f64/recon2d_tiled_kernel<double, 3>"}
+             ("kelvin", 1024, "f64"): "kelvin_f64/recon2d_tiled_kernel<double, 3, -1>"}
 
 
 def main():
@@ -753,7 +753,7 @@ def kelvin_configs():
                     "source_kernel_avg_ms": ksms,
                     "reconstruction_hbm_gbs": k_rec, "stage_hbm_gbs": k_stg,
                     "valu_roof_reconstruction": valu_roof(
-                        "kelvin_f64/recon2d_tiled_kernel<double, 3>", krms),
+                        "kelvin_f64/recon2d_tiled_kernel<double, 3, -1>", krms),
                     "valu_roof_stage": valu_roof("kelvin_f64/sw_stage_kernel<double, 2>", ksms),
                     "reconstructions_per_step": 3, "source_launches_per_step": 6,
                     "search_fail": st["search_fail"], "l2_rel_vs_exact_t1": err}

@@ -359,6 +359,13 @@ hipError_t launch_recon(sl_grid* gr, const sl::FieldPtrs& fp, char* ws, const do
     return launch(sl::recon2d_tiled_kernel<T, NF>, grid, block,                          \
                   (uint32_t)sl::Tile2D<T, NF>::LDS_BYTES, s, e0, e1, gr->g, fp, disp, \
                   ord, stats, tiles_x, ntiles, nt, gr->v);
+    // The swirl with three fields has a kernel of its own, whose fused
+    // trajectories are that family's alone (no scalar spills): 1024^2 step
+    // 45.2 -> 44.4 us, 4096^2 0.599 -> 0.589 ms.
+    if (gr->g.nfields == 3 && gr->v.kind == SL_VEL_SWIRL2D)
+      return launch(sl::recon2d_tiled_kernel<T, 3, SL_VEL_SWIRL2D>, grid, block,
+                    (uint32_t)sl::Tile2D<T, 3>::LDS_BYTES, s, e0, e1, gr->g, fp, disp, ord, stats,
+                    tiles_x, ntiles, nt, gr->v);
     switch (gr->g.nfields) {
       SL_RECON2D(1)
       SL_RECON2D(2)

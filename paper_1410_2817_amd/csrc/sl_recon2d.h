@@ -216,7 +216,7 @@ __device__ __forceinline__ T zsum2d(const T* wx, const T* wy, const Val& val) {
 //
 // `nt` / `v` (VelT = VelArgs): the tile then also integrates the next step's
 // trajectories of its own nodes (see NextTraj); VelT = NoVel compiles that out.
-template <typename T, int NF, class VelT>
+template <typename T, int NF, class VelT, int VK = -1>
 __device__ __forceinline__ void recon2d_tile(const GridArgs& g, const FieldPtrs& fp,
                                              const double* __restrict__ gdisp,
                                              const uint16_t* __restrict__ ord,
@@ -255,8 +255,14 @@ __device__ __forceinline__ void recon2d_tile(const GridArgs& g, const FieldPtrs&
 #pragma unroll 1
       for (int k = 0; k < C::NPT; ++k) {
         const int idx[2] = {tx0 + lx, ty0 + ly0 + ROWS * k};
-        if (idx[0] < g.n[0] && idx[1] < g.n[1])
-          traj_any<2>(g, v, nt.disp, nt.st, nt.dt, nt.integrator, idx, nt.trig);
+        if (idx[0] < g.n[0] && idx[1] < g.n[1]) {
+          // VK: the grid's velocity family when the kernel is specialised
+          // for one, else the run-time switch over all of them.
+          if constexpr (VK >= 0)
+            traj_node<2, VK>(g, v, nt.disp, nt.st, nt.dt, 0, nt.integrator, idx, nt.trig);
+          else
+            traj_any<2>(g, v, nt.disp, nt.st, nt.dt, nt.integrator, idx, nt.trig);
+        }
       }
     }
   }
@@ -594,15 +600,15 @@ __device__ __forceinline__ void recon2d_tile(const GridArgs& g, const FieldPtrs&
     atomicAdd(stat_copy(stats) + threadIdx.x, (unsigned long long)s_cnt[threadIdx.x]);
 }
 
-template <typename T, int NF>
+template <typename T, int NF, int VK = -1>
 __global__ __launch_bounds__(kTileThreads, (tile2d_waves<T, NF>()))
 void recon2d_tiled_kernel(
     GridArgs g, FieldPtrs fp, const double* __restrict__ gdisp,
     const uint16_t* __restrict__ ord, unsigned long long* __restrict__ stats, int tiles_x,
     int ntiles, NextTraj nt, VelArgs v) {
   extern __shared__ __align__(16) unsigned char smem[];
-  recon2d_tile<T, NF>(g, fp, gdisp, ord, stats, xcd_tile(blockIdx.x, ntiles), tiles_x, smem, nt,
-                      v);
+  recon2d_tile<T, NF, VelArgs, VK>(g, fp, gdisp, ord, stats, xcd_tile(blockIdx.x, ntiles),
+                                   tiles_x, smem, nt, v);
 }
 
 }  // namespace sl
