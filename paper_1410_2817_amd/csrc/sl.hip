@@ -360,8 +360,8 @@ hipError_t launch_recon(sl_grid* gr, const sl::FieldPtrs& fp, char* ws, const do
                   (uint32_t)sl::Tile2D<T, NF>::LDS_BYTES, s, e0, e1, gr->g, fp, disp, \
                   ord, stats, tiles_x, ntiles, nt, gr->v);
     // The swirl with three fields has a kernel of its own, whose fused
-    // trajectories are that family's alone (no scalar spills): 1024^2 step
-    // 45.2 -> 44.4 us, 4096^2 0.599 -> 0.589 ms.
+    // trajectories are that family's alone (10 scalar registers spilled
+    // against 16): 1024^2 step 45.2 -> 44.4 us, 4096^2 0.599 -> 0.589 ms.
     if (gr->g.nfields == 3 && gr->v.kind == SL_VEL_SWIRL2D)
       return launch(sl::recon2d_tiled_kernel<T, 3, SL_VEL_SWIRL2D>, grid, block,
                     (uint32_t)sl::Tile2D<T, 3>::LDS_BYTES, s, e0, e1, gr->g, fp, disp, ord, stats,
@@ -397,7 +397,8 @@ hipError_t launch_recon(sl_grid* gr, const sl::FieldPtrs& fp, char* ws, const do
     // The deformational flow with one field (the paper's 3-D test) has a
     // kernel of its own: 0.6 % (FP64) to 1 % (FP32 values) faster per step.
     // So do Fourier flows with three fields, whose registers then cover that
-    // family's trajectories alone (no spills): 256^3 step 1.82 -> 1.80 ms.
+    // family's trajectories alone (4 VGPRs and 11 scalar registers spilled
+    // against 5 and 12): 256^3 step 1.82 -> 1.80 ms.
     if (gr->g.nfields == 1 && gr->v.kind == SL_VEL_DEFORM3D)
       return launch(sl::recon3d_kernel<T, 1, SL_VEL_DEFORM3D>, grid, block, 0, s, e0, e1, gr->g,
                     fp, disp, ord, stats, tiles_x, tiles_y, ntiles, buf_ok, dbuf_ok, nt, gr->v);
