@@ -101,7 +101,7 @@ VALU_KERNELS = {"swirl_f32": ["recon2d_tiled_kernel<float, 3, 2>"],
                 "fourier3d_f32": ["recon3d_kernel<float, 3, 4>"],
                 "deform3d_f64": ["recon3d_kernel<double, 1, 3>"],
                 "deform3d_f32": ["recon3d_kernel<float, 1, 3>"],
-                "kelvin_f64": ["recon2d_tiled_kernel<double, 3, -1>", "sw_stage_kernel<double, 2>"]}
+                "kelvin_f64": ["recon2d_tiled_kernel<double, 3, 6>", "sw_stage_kernel<double, 2>"]}
 
 
 def _code_only(text: str) -> str:
@@ -285,7 +285,7 @@ VALU_KEYS = {("swirl", 1024, "f32"): "swirl_f32/recon2d_tiled_kernel<float, 3, 2
              ("fourier3d", 256, "f32"): "fourier3d_f32/recon3d_kernel<float, 3, 4>",
              ("deform3d", 512, "f64"): "deform3d_f64/recon3d_kernel<double, 1, 3>",
              ("deform3d", 512, "f32"): "deform3d_f32/recon3d_kernel<float, 1, 3>",
-             ("kelvin", 1024, "f64"): "kelvin_f64/recon2d_tiled_kernel<double, 3, -1>"}
+             ("kelvin", 1024, "f64"): "kelvin_f64/recon2d_tiled_kernel<double, 3, 6>"}
 
 
 def main():
@@ -753,7 +753,7 @@ def kelvin_configs():
                     "source_kernel_avg_ms": ksms,
                     "reconstruction_hbm_gbs": k_rec, "stage_hbm_gbs": k_stg,
                     "valu_roof_reconstruction": valu_roof(
-                        "kelvin_f64/recon2d_tiled_kernel<double, 3, -1>", krms),
+                        "kelvin_f64/recon2d_tiled_kernel<double, 3, 6>", krms),
                     "valu_roof_stage": valu_roof("kelvin_f64/sw_stage_kernel<double, 2>", ksms),
                     "reconstructions_per_step": 3, "source_launches_per_step": 6,
                     "search_fail": st["search_fail"], "l2_rel_vs_exact_t1": err}

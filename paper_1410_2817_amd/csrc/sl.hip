@@ -362,6 +362,14 @@ hipError_t launch_recon(sl_grid* gr, const sl::FieldPtrs& fp, char* ws, const do
     // The swirl with three fields has a kernel of its own, whose fused
     // trajectories are that family's alone (10 scalar registers spilled
     // against 16): 1024^2 step 45.2 -> 44.4 us, 4096^2 0.599 -> 0.589 ms.
+    // A carried velocity with three FP64 fields (the shallow-water system)
+    // runs a kernel without the fused trajectories, at five waves per SIMD.
+    if constexpr (sizeof(T) == 8) {
+      if (gr->g.nfields == 3 && gr->v.kind == SL_VEL_CARRIED)
+        return launch(sl::recon2d_tiled_kernel<T, 3, SL_VEL_CARRIED>, grid, block,
+                      (uint32_t)sl::Tile2D<T, 3>::LDS_BYTES, s, e0, e1, gr->g, fp, disp, ord,
+                      stats, tiles_x, ntiles, nt, gr->v);
+    }
     if (gr->g.nfields == 3 && gr->v.kind == SL_VEL_SWIRL2D)
       return launch(sl::recon2d_tiled_kernel<T, 3, SL_VEL_SWIRL2D>, grid, block,
                     (uint32_t)sl::Tile2D<T, 3>::LDS_BYTES, s, e0, e1, gr->g, fp, disp, ord, stats,

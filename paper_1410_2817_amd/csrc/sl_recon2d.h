@@ -51,13 +51,17 @@ struct Tile2D {
 };
 
 // Waves per SIMD the register budget of the 2-D reconstruction kernels
-// targets, per (precision, field count): the most that compile without
-// spills (the LDS boxes allow more), except FP64 with two fields, where four
-// waves spill 20 VGPRs yet measured faster than three without spills
-// (Burgers 512^2 step 18.0 -> 15.7 us).
-template <typename T, int NF>
+// targets, per (precision, field count, velocity family VK of a specialised
+// kernel): the most that compile without spills (the LDS boxes allow more),
+// except where more waves with spills measured faster: FP64 with two fields
+// at four waves spills 20 VGPRs (Burgers 512^2 step 18.0 -> 15.7 us), and a
+// carried velocity with three FP64 fields, whose kernel integrates no
+// trajectories, at five waves (Kelvin 1024^2 reconstruction 35.8 -> 33.9 us;
+// with the fused trajectories five waves lost 18 %).
+template <typename T, int NF, int VK = -1>
 constexpr int tile2d_waves() {
   if (sizeof(T) == 4) return (NF >= 2 && NF <= 4) ? 6 : (NF == 1 ? 5 : 4);
+  if (NF == 3 && VK == SL_VEL_CARRIED) return 5;
   return NF <= 3 ? 4 : 3;
 }
 
@@ -252,7 +256,7 @@ __device__ __forceinline__ void recon2d_tile(const GridArgs& g, const FieldPtrs&
 
   // The next step's trajectories of the tile's own nodes (NextTraj); they
   // touch nothing the reconstruction below reads.
-  if constexpr (std::is_same<VelT, VelArgs>::value) {
+  if constexpr (std::is_same<VelT, VelArgs>::value && VK != SL_VEL_CARRIED) {
     if (nt.disp && !nt.carried) {
 #pragma unroll 1
       for (int k = 0; k < C::NPT; ++k) {
@@ -603,7 +607,7 @@ __device__ __forceinline__ void recon2d_tile(const GridArgs& g, const FieldPtrs&
 }
 
 template <typename T, int NF, int VK = -1>
-__global__ __launch_bounds__(kTileThreads, (tile2d_waves<T, NF>()))
+__global__ __launch_bounds__(kTileThreads, (tile2d_waves<T, NF, VK>()))
 void recon2d_tiled_kernel(
     GridArgs g, FieldPtrs fp, const double* __restrict__ gdisp,
     const uint16_t* __restrict__ ord, unsigned long long* __restrict__ stats, int tiles_x,

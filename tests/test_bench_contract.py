@@ -54,7 +54,7 @@ def test_headline_is_the_largest_single_gpu_configuration():
     "fourier3d_f32/recon3d_kernel<float, 3, 4>",
     "deform3d_f64/recon3d_kernel<double, 1, 3>",
     "deform3d_f32/recon3d_kernel<float, 1, 3>",
-    "kelvin_f64/recon2d_tiled_kernel<double, 3, -1>",
+    "kelvin_f64/recon2d_tiled_kernel<double, 3, 6>",
     "kelvin_f64/sw_stage_kernel<double, 2>",
 ])
 def test_valu_record_matches_the_kernels(key):
